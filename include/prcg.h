@@ -1,0 +1,213 @@
+/*
+ * libprcg: conjugate-gradient solvers for sparse symmetric positive definite
+ * systems A x = b on one AMD MI355X (gfx950), following
+ *   T. Chen and E. Carson, "Predict-and-recompute conjugate gradient
+ *   variants", SIAM J. Sci. Comput. 42(5), 2020.
+ *
+ * The problem is the paper's: A is n-by-n, sparse, symmetric positive
+ * definite (Section 1); an optional SPD preconditioner M is used only through
+ * products with M^{-1} (Section 1, preconditioned variants); the inputs are
+ * exactly HS-CG's, (A, M, b, x0), and no variant has a tuning parameter.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments named as device arrays are device pointers on the device
+ *   that was current when the matrix handle was created (for instance the
+ *   data pointer of a torch CUDA tensor).  `info`, `history`, `iters`,
+ *   `status` and `sys_row_offset` are host pointers.
+ * - Ownership: the library never keeps a caller pointer after a call
+ *   returns.  prcg_create_csr copies the matrix; a handle owns all of its
+ *   device memory and prcg_destroy releases it.
+ * - Streams: all device work is enqueued on the stream given at creation
+ *   (NULL = the default stream).  Solves return after the work is finished;
+ *   the host waits once per batch of iterations, never once per iteration.
+ * - Concurrency: a handle is not thread-safe; distinct handles may be used
+ *   from different threads.
+ * - Errors: every function returns a prcg_status.  Negative codes are caller
+ *   or system errors: after PRCG_EINVAL nothing was written, after
+ *   PRCG_EDEVICE outputs are unspecified.  Non-negative codes are numerical
+ *   outcomes and come with a valid x.  prcg_last_error() describes the last
+ *   non-OK status of the calling thread.
+ * - Arithmetic is IEEE double precision throughout; indices are int32, so
+ *   n and nnz are below 2^31.
+ */
+#ifndef PRCG_H
+#define PRCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct prcg_matrix_s* prcg_matrix;
+typedef struct prcg_batch_s* prcg_batch;
+
+/* The variants.
+ *   PRCG_HS      Alg. 1, Hestenes-Stiefel CG: one product, inner products
+ *                nu_k and mu_k, two synchronisations per iteration.
+ *   PRCG_PR      Alg. 2, predict-and-recompute CG: nu'_k from
+ *                eq. nuk_simplified predicts beta_k; mu, sigma, gamma and the
+ *                recomputed nu share one reduction.
+ *   PRCG_PIPE_PR Alg. 3, pipelined predict-and-recompute CG: recurrences for
+ *                s, s~, w', w~'; the products u = A s~ and w = A r~ (the
+ *                recompute of w') read A once and overlap the reduction.
+ *   PRCG_M       M-CG (Appendix D): PR-CG with nu'_k = -nu_{k-1} + alpha^2 gamma.
+ *   PRCG_PIPE_M  pipe-PR-M-CG (Appendix D): pipe-PR-CG with the M-CG nu'.   */
+typedef enum {
+    PRCG_HS = 0,
+    PRCG_PR = 1,
+    PRCG_PIPE_PR = 2,
+    PRCG_M = 3,
+    PRCG_PIPE_M = 4
+} prcg_variant;
+
+/* Preconditioners: none (M = I) or Jacobi (M^{-1} = diag(A)^{-1}). */
+typedef enum { PRCG_PRECOND_NONE = 0, PRCG_PRECOND_JACOBI = 1 } prcg_precond;
+
+typedef enum {
+    PRCG_OK = 0,             /* converged: ||r_k|| <= tol * ||b||, x = x_k            */
+    PRCG_NOT_CONVERGED = 1,  /* k reached maxit; x = x_maxit                           */
+    PRCG_BREAKDOWN = 2,      /* nu_k <= 0, mu_k <= 0, nu' <= 0 or a non-finite scalar  */
+    PRCG_EINVAL = -1,        /* invalid argument or matrix                            */
+    PRCG_ENOMEM = -2,        /* device or host allocation failed                      */
+    PRCG_EDEVICE = -3        /* a HIP call failed                                     */
+} prcg_status;
+
+/* Outcome of one solve.  relres_updated = ||r_k|| / ||b|| with r_k the
+ * recursively updated residual; relres_true = ||b - A x_k|| / ||b||,
+ * computed once at exit.  Both are 0 when b = 0. */
+typedef struct {
+    int32_t iters;
+    int32_t status;
+    double relres_updated;
+    double relres_true;
+} prcg_info;
+
+/* Storage the library chose for a matrix (informational). */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    int64_t stored_entries;   /* entries held by the SpMV layout, padding included */
+    int32_t format;           /* 0 = SELL-64 (one row per lane), 1 = vector CSR     */
+    int32_t lanes_per_row;    /* 1 for SELL-64, L for vector CSR                    */
+    int32_t grid;             /* workgroups of the row-parallel kernels             */
+    int32_t block;            /* threads per workgroup                              */
+    int64_t matrix_bytes;     /* bytes of the SpMV layout read by one product       */
+} prcg_matrix_props;
+
+/*
+ * Create a matrix handle from CSR arrays (Section 1: A sparse SPD).
+ *   n, nnz    1 <= n < 2^31, 0 <= nnz < 2^31.
+ *   row_ptr   device int32[n+1]: row_ptr[0] = 0, non-decreasing,
+ *             row_ptr[n] = nnz.
+ *   col_idx   device int32[nnz]: 0 <= col < n.  Any order within a row;
+ *             duplicates are summed.  Each row is summed in stored order.
+ *   values    device float64[nnz].
+ *   precond   PRCG_PRECOND_JACOBI needs every diagonal entry (summed over
+ *             duplicates) to be > 0.
+ *   hip_stream  hipStream_t cast to void*, or NULL.
+ * The arrays are copied (and re-laid-out for the SpMV); the caller may free
+ * them afterwards.  Symmetry and definiteness are preconditions, not
+ * checked; violating them shows up as PRCG_BREAKDOWN or PRCG_NOT_CONVERGED.
+ * Returns PRCG_EINVAL for an invalid structure (nothing is allocated then).
+ */
+prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double* values, prcg_precond precond, void* hip_stream,
+                            prcg_matrix* out);
+
+/* Replace the values of A (same sparsity pattern, CSR order as at
+ * creation; device float64[nnz]) and refresh the Jacobi diagonal. */
+prcg_status prcg_set_values(prcg_matrix A, const double* values);
+
+/* Change the stream used by later calls on A. */
+prcg_status prcg_set_stream(prcg_matrix A, void* hip_stream);
+
+/* y = A x (device float64[n] each; x and y must not overlap).  The product
+ * of Section 3 eq. Ax: each row summed in stored order with fused
+ * multiply-adds. */
+prcg_status prcg_spmv(prcg_matrix A, const double* x, double* y);
+
+/*
+ * Solve A x = b with one variant (Algs. 1-3, Appendix D), starting from the
+ * initialisation of Appendix D.
+ *   b        device float64[n].
+ *   x        device float64[n]; x_0 on entry, the final iterate on exit.
+ *   tol      >= 0.  Stops at the first k with ||r_k|| <= tol * ||b|| (r_k
+ *            the updated residual).  tol = 0 runs exactly maxit iterations
+ *            unless the method breaks down.
+ *   maxit    >= 0.
+ *   info     host, nullable.
+ *   history  host, nullable, maxit+1 doubles: history[k] = ||r_k|| / ||b||
+ *            for k = 0..iters (entries past iters are left untouched).
+ * b = 0 gives x = 0, iters = 0, PRCG_OK.  Breakdown (the paper notes the
+ * methods break down when nu turns negative): nu_k <= 0, mu_k <= 0 or a
+ * non-finite scalar after the reduction of iteration k returns x_k; a
+ * predicted nu'_{k+1} <= 0 makes iteration k+1 the last one (its x and r
+ * updates do not involve nu'), which returns x_{k+1} with PRCG_OK if its
+ * residual meets tol, else PRCG_BREAKDOWN.
+ * Inner products are reduced deterministically: the same call on the same
+ * device gives bitwise identical results.
+ */
+prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x, double tol,
+                       int32_t maxit, prcg_info* info, double* history);
+
+/*
+ * Per-kernel device time of `iters` iterations of variant v, continuing
+ * from the state left by the last prcg_solve on A with the same variant
+ * (the iteration is run with tol = 0, so the iterations are genuine work).
+ * Each kernel launch is bracketed by HIP events on the handle's stream.
+ *   ms_per_launch  host float64[8]: average milliseconds per launch of each
+ *                  kernel of one iteration, in launch order.
+ *   names          host, nullable, char[8][48]: kernel names.
+ *   nkernels       host: number of kernels per iteration.
+ */
+prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, double* ms_per_launch,
+                              char (*names)[48], int32_t* nkernels);
+
+/* Describe the storage chosen for A. */
+prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props);
+
+/*
+ * Batched solve of nsys independent systems stored as one block-diagonal
+ * matrix (not in the paper; the block-diagonal structure is the only
+ * assumption).  One persistent kernel advances every system: each
+ * workgroup takes the next-largest unsolved system from a queue and runs
+ * the whole solve with workgroup-local reductions.
+ *   blockdiag       a handle created by prcg_create_csr (no column index
+ *                   may leave its block; checked here).
+ *   sys_row_offset  host int64[nsys+1]: system s owns rows
+ *                   [off[s], off[s+1]); off[0] = 0, strictly increasing,
+ *                   off[nsys] = n.
+ */
+prcg_status prcg_create_batch(prcg_matrix blockdiag, int32_t nsys, const int64_t* sys_row_offset,
+                              prcg_batch* out);
+
+/* Solve every system of the batch with variant v (PR or HS), same
+ * semantics per system as prcg_solve.  b, x: device float64[n].
+ * iters, status: host int32[nsys], nullable. */
+prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, double* x, double tol,
+                               int32_t maxit, int32_t* iters, int32_t* status);
+
+/*
+ * Adjoint of a solve (not in the paper): for L(x) with x = A^{-1} b and
+ * gx = dL/dx, solves A lambda = gx with variant v (A is symmetric, so
+ * A^T = A) and returns
+ *   gb     device float64[n], nullable:   dL/db = lambda;
+ *   gvals  device float64[nnz], nullable: dL/dA_e = -lambda[row(e)] * x[col(e)]
+ *          for every stored entry e, in the CSR order given at creation.
+ *   x      device float64[n]: the forward solution.
+ *   info   host, nullable: outcome of the adjoint solve.
+ */
+prcg_status prcg_adjoint(prcg_matrix A, prcg_variant v, const double* x, const double* gx, double* gb,
+                         double* gvals, double tol, int32_t maxit, prcg_info* info);
+
+void prcg_destroy(prcg_matrix A);
+void prcg_batch_destroy(prcg_batch B);
+const char* prcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRCG_H */

@@ -281,12 +281,11 @@ static int orc_hs(orc_ctx* C, int64_t* kout)
     int64_t k = 0;
     int status;
     if (dg && dg->mu) dg->mu[0] = mu;
+    /* same order as in the loop: converged, nu breakdown, maxit, mu breakdown */
     if (orc_observe(C, 0, rr, nu, r)) { status = ORC_OK; goto out; }
-    if (!orc_finite(nu) || !orc_finite(rr) || !(nu > 0.0) || !orc_finite(mu) || !(mu > 0.0)) {
-        status = ORC_BREAKDOWN;
-        goto out;
-    }
+    if (!orc_finite(nu) || !orc_finite(rr) || !(nu > 0.0)) { status = ORC_BREAKDOWN; goto out; }
     if (k == C->maxit) { status = ORC_NOT_CONVERGED; goto out; }
+    if (!orc_finite(mu) || !(mu > 0.0)) { status = ORC_BREAKDOWN; goto out; }
     double alpha = nu / mu;                                    /* alpha0 = nu0 / <p0, s0> */
     if (dg && dg->alpha) dg->alpha[0] = alpha;
 

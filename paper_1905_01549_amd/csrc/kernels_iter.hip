@@ -1,0 +1,664 @@
+// Iteration kernels of HS-CG (Alg. 1), PR-CG (Alg. 2), pipe-PR-CG (Alg. 3)
+// and their Meurant forms (Appendix D), plus the initialisation of
+// Appendix D and the exit kernels.
+//
+// Structure on the GPU.  A global synchronisation of the paper (C_gr, a
+// reduction over all rows) becomes a kernel boundary: stage 1 of every
+// reduction writes one partial per workgroup, and the kernel that needs the
+// totals sums the partials in a fixed order (stage 2), so results are
+// bitwise repeatable and no host synchronisation happens per iteration.
+// The sparse product needs its input vector complete at neighbouring rows,
+// which is a second kernel boundary (the paper's C_mv).
+//
+//   PR-CG:   [update + stage 2] [SpMV + 5 inner products]
+//            stage 2 and the scalar step (alpha_k, nu'_{k+1}, beta_{k+1})
+//            run redundantly in every workgroup of the update kernel.
+//   pipe-PR: [update + 5 inner products] [SpMV pair (u, w) || stage 2]
+//            every vector update and inner product of Alg. 3 depends only
+//            on data of the row, so they share one pass; workgroup 0 of the
+//            SpMV kernel runs stage 2 while the other workgroups compute
+//            u = A s~ and w = A r~ (one pass over A): the overlap of the
+//            reduction with the products of Section 2.2.1.
+//   HS-CG:   [stage 2 of mu + x, r updates + nu] [stage 2 of nu + p update]
+//            [SpMV + mu]: two reductions per iteration, as Alg. 1 needs.
+//
+// Jacobi (M^{-1} = diag(d)): the vectors the algorithms define explicitly
+// as M^{-1} v (HS r~, PR s~, pipe u~ and w~) are recomputed as d*v where
+// needed instead of being stored; this gives identical bits.  Vectors
+// defined by recurrence (PR/pipe r~, pipe s~) are stored.  Without a
+// preconditioner every tilde vector is its plain counterpart.
+#include "prcg_device.h"
+
+namespace prcg {
+
+namespace {
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// The scalar step after the reduction of iteration k of a one-reduction
+// variant (PR, M, pipe-PR, pipe-M): record ||r_k||, test convergence and
+// breakdown, then form alpha_k, nu'_{k+1} and beta_{k+1} (Alg. 2 / Alg. 3,
+// eq. nuk_simplified; Meurant: nu' = -nu + alpha^2 gamma).
+__device__ void step_one_reduction(State& st, const double (&t)[5], bool pre, bool meurant, double* hist,
+                                   bool writer)
+{
+    const double mu = t[0], sigma = t[1], gamma = t[2], nu = t[3];
+    const double rr = pre ? t[4] : nu;
+    const int k = st.k + 1;
+    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
+    if (writer) hist[k] = rnorm / st.bnorm;
+    st.k = k;
+    st.nu = nu;
+    st.mu = mu;
+    st.sigma = sigma;
+    st.gamma = gamma;
+    st.rr = rr;
+    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
+        st.done = 1;
+        st.status = kOK;
+        return;
+    }
+    if (st.last || !finite(nu) || !finite(mu) || !finite(rr) || !(nu > 0.0) || !(mu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        return;
+    }
+    if (k == st.maxit) {
+        st.done = 1;
+        st.status = kNotConverged;
+        return;
+    }
+    const double alpha = nu / mu;
+    const double nup = meurant ? -nu + alpha * alpha * gamma : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
+    st.alpha = alpha;
+    st.nup = nup;
+    if (!finite(nup) || !(nup > 0.0)) {
+        st.last = 1;  // the next iteration's x and r updates are still taken
+        st.beta = 0.0;
+    } else {
+        st.beta = nup / nu;
+    }
+}
+
+// HS-CG after the reduction of nu_k (Alg. 1): record ||r_k||, test, beta_k.
+__device__ void step_hs_nu(State& st, double nu, double rr, double* hist, bool writer)
+{
+    const int k = st.k + 1;
+    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
+    if (writer) hist[k] = rnorm / st.bnorm;
+    st.k = k;
+    st.rr = rr;
+    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
+        st.done = 1;
+        st.status = kOK;
+        st.nu = nu;
+        return;
+    }
+    if (!finite(nu) || !finite(rr) || !(nu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        st.nu = nu;
+        return;
+    }
+    if (k == st.maxit) {
+        st.done = 1;
+        st.status = kNotConverged;
+        st.nu = nu;
+        return;
+    }
+    if (k > 0) st.beta = nu / st.nu;  // beta_k = nu_k / nu_{k-1}
+    st.nu = nu;
+}
+
+// HS-CG after the reduction of mu_k: alpha_k = nu_k / mu_k.
+__device__ void step_hs_mu(State& st, double mu)
+{
+    st.mu = mu;
+    if (!finite(mu) || !(mu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        return;
+    }
+    st.alpha = st.nu / mu;
+}
+
+__device__ __forceinline__ bool writer_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// ------------------------------------------------------------------ init
+
+// x = x0, r0 = b - A x0, p0 = r~0 = M^{-1} r0 (r~0 stored when it evolves by
+// recurrence); partial of <b, b>.
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_init_r(SellView S, CsrView C, Split sp, const double* __restrict__ b,
+                                                   const double* __restrict__ x0, Vecs v, int store_rt,
+                                                   double* __restrict__ PB)
+{
+    __shared__ double lds[kWaves * 1];
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[1] = {0.0};
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, x0, nullptr, [&](int64_t i, double ax, double) {
+            const double bi = b[i];
+            const double ri = bi - ax;
+            v.x[i] = x0[i];
+            v.r[i] = ri;
+            const double rti = PRE ? v.d[i] * ri : ri;
+            if (PRE && store_rt) v.rt[i] = rti;
+            v.p[i] = rti;
+            acc[0] = fma(bi, bi, acc[0]);
+        });
+    }
+    write_partials<1>(acc, PB, sp.Gs, blockIdx.x, lds);
+}
+
+// s0 = A p0 (s~0 = M^{-1} s0 stored when it evolves by recurrence);
+// partials of mu0, sigma0, gamma0, nu0, <r0, r0>.
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split sp, Vecs v, int store_st,
+                                                   double* __restrict__ PS)
+{
+    __shared__ double lds[kWaves * 5];
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, v.p, nullptr, [&](int64_t i, double si, double) {
+            v.s[i] = si;
+            const double ri = v.r[i];
+            const double di = PRE ? v.d[i] : 1.0;
+            const double sti = PRE ? di * si : si;
+            const double rti = PRE ? di * ri : ri;
+            if (PRE && store_st) v.st[i] = sti;
+            acc[0] = fma(v.p[i], si, acc[0]);  // mu0    = <p0, s0>
+            acc[1] = fma(rti, si, acc[1]);     // sigma0 = <r~0, s0>
+            acc[2] = fma(sti, si, acc[2]);     // gamma0 = <s~0, s0>
+            acc[3] = fma(rti, ri, acc[3]);     // nu0    = <r~0, r0>
+            acc[4] = fma(ri, ri, acc[4]);      // <r0, r0>
+        });
+    }
+    write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+// pipe-PR-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0.
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split sp, Vecs v)
+{
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    const double* st = PRE ? v.st : v.s;
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, st, nullptr, [&](int64_t i, double ui, double) {
+            v.u[i] = ui;
+            v.w[i] = v.s[i];
+        });
+    }
+}
+
+// One workgroup: ||b||, the b = 0 case, and the first scalar step where the
+// variant's first iteration kernel does not perform it.
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_init_finish(int variant, Split sp, const double* __restrict__ PB,
+                                                        const double* __restrict__ PS, State* __restrict__ out,
+                                                        double* __restrict__ hist, double tol, int maxit)
+{
+    __shared__ double lds[kWaves * 5];
+    double bb[1];
+    reduce_partials<1>(PB, sp.G, sp.Gs, bb, lds);
+    double t[5];
+    reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+    State st = {};
+    st.bnorm = sqrt(bb[0]);
+    st.tol = tol;
+    st.maxit = maxit;
+    st.k = -1;
+    st.status = kNotConverged;
+    const bool w = threadIdx.x == 0;
+    if (bb[0] == 0.0) {
+        st.k = 0;
+        st.done = 1;
+        st.status = kOK;
+        st.zero_x = 1;
+        st.rr = 0.0;
+        if (w) hist[0] = 0.0;
+    } else if (variant == kPipePR || variant == kPipeM) {
+        step_one_reduction(st, t, PRE, variant == kPipeM, hist, w);
+    } else if (variant == kHS) {
+        step_hs_nu(st, t[3], PRE ? t[4] : t[3], hist, w);
+    }
+    // PR / M: the first update kernel performs the step for k = 0.
+    if (w) *out = st;
+}
+
+// ------------------------------------------------------------------ PR-CG
+
+__device__ __forceinline__ void row_range(const Split& sp, int64_t g0, int64_t g1, int64_t& i0, int64_t& i1)
+{
+    i0 = g0 * kGroupRows + threadIdx.x;
+    i1 = g1 * kGroupRows < sp.n ? g1 * kGroupRows : sp.n;
+}
+
+// Stage 2 of iteration k + scalar step, then the vector updates of
+// iteration k+1 (Alg. 2): x += alpha p; r -= alpha s; r~ -= alpha s~;
+// p = r~ + beta p.
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
+                                                      State* __restrict__ out, double* __restrict__ hist,
+                                                      const double* __restrict__ PS, int meurant, Vecs v)
+{
+    __shared__ double lds[kWaves * 5];
+    State st = *in;
+    if (st.done) {
+        if (writer_thread()) *out = st;
+        return;
+    }
+    double t[5];
+    reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+    step_one_reduction(st, t, PRE, meurant != 0, hist, writer_thread());
+    if (writer_thread()) *out = st;
+    if (st.done) return;
+    const double alpha = st.alpha, beta = st.beta;
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    for (int64_t i = i0; i < i1; i += kBlock) {
+        const double si = v.s[i];
+        const double pi = v.p[i];
+        v.x[i] = fma(alpha, pi, v.x[i]);
+        const double ri = fma(-alpha, si, v.r[i]);
+        v.r[i] = ri;
+        double rti = ri;
+        if (PRE) {
+            rti = fma(-alpha, v.d[i] * si, v.rt[i]);
+            v.rt[i] = rti;
+        }
+        v.p[i] = fma(beta, pi, rti);
+    }
+}
+
+// s_k = A p_k, s~_k = M^{-1} s_k, and the inner products of Alg. 2
+// mu = <p, s>, sigma = <r~, s>, gamma = <s~, s>, nu = <r~, r> (+ <r, r>).
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
+                                                    double* __restrict__ PS, Vecs v)
+{
+    __shared__ double lds[kWaves * 5];
+    if (cur->done) return;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, v.p, nullptr, [&](int64_t i, double si, double) {
+            v.s[i] = si;
+            const double ri = v.r[i];
+            const double rti = PRE ? v.rt[i] : ri;
+            const double sti = PRE ? v.d[i] * si : si;
+            acc[0] = fma(v.p[i], si, acc[0]);
+            acc[1] = fma(rti, si, acc[1]);
+            acc[2] = fma(sti, si, acc[2]);
+            acc[3] = fma(rti, ri, acc[3]);
+            if (PRE) acc[4] = fma(ri, ri, acc[4]);
+        });
+    }
+    write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+// ------------------------------------------------------------------ pipe-PR-CG
+
+// All vector updates of iteration k (Alg. 3) in one pass, then the four
+// (five) inner products of the same iteration from the updated rows:
+//   x += alpha p; r -= alpha s; r~ -= alpha s~; w' = w - alpha u;
+//   w~' = w~ - alpha u~; p = r~ + beta p; s = w' + beta s; s~ = w~' + beta s~.
+// w' and w~' live only in registers (Section 2.2.1: w and w' need not be
+// stored separately; w is recomputed by the next kernel).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* __restrict__ cur,
+                                                        double* __restrict__ PS, Vecs v)
+{
+    __shared__ double lds[kWaves * 5];
+    const State st = *cur;
+    if (st.done) return;
+    const double alpha = st.alpha, beta = st.beta;
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < i1; i += kBlock) {
+        const double pi = v.p[i];
+        const double si = v.s[i];
+        const double wi = v.w[i];
+        const double ui = v.u[i];
+        v.x[i] = fma(alpha, pi, v.x[i]);
+        const double ri = fma(-alpha, si, v.r[i]);
+        v.r[i] = ri;
+        const double wpi = fma(-alpha, ui, wi);            // w'_k
+        double rti = ri, sti;
+        const double snew = fma(beta, si, wpi);            // s_k = w'_k + beta s_{k-1}
+        if (PRE) {
+            const double di = v.d[i];
+            const double sti_old = v.st[i];
+            rti = fma(-alpha, sti_old, v.rt[i]);           // r~_k
+            v.rt[i] = rti;
+            const double wtpi = fma(-alpha, di * ui, di * wi);  // w~'_k = w~ - alpha u~
+            sti = fma(beta, sti_old, wtpi);                // s~_k
+            v.st[i] = sti;
+        } else {
+            sti = snew;
+        }
+        const double pnew = fma(beta, pi, rti);            // p_k
+        v.p[i] = pnew;
+        v.s[i] = snew;
+        acc[0] = fma(pnew, snew, acc[0]);                  // mu_k    = <p_k, s_k>
+        acc[1] = fma(rti, snew, acc[1]);                   // sigma_k = <r~_k, s_k>
+        acc[2] = fma(sti, snew, acc[2]);                   // gamma_k = <s~_k, s_k>
+        acc[3] = fma(rti, ri, acc[3]);                     // nu_k    = <r~_k, r_k>
+        if (PRE) acc[4] = fma(ri, ri, acc[4]);
+    }
+    write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+// u_k = A s~_k and w_k = A r~_k (the recompute) in one pass over A, run by
+// workgroups 1..G, while workgroup 0 reduces the inner products of
+// iteration k and performs the scalar step (Section 2.2.1: the products and
+// the reduction proceed simultaneously).
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+                                                      State* __restrict__ out, double* __restrict__ hist,
+                                                      const double* __restrict__ PS, int meurant, Vecs v)
+{
+    __shared__ double lds[kWaves * 5];
+    State st = *in;
+    if (blockIdx.x == 0) {
+        if (!st.done) {
+            double t[5];
+            reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+            step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+        }
+        if (threadIdx.x == 0) *out = st;
+        return;
+    }
+    if (st.done) return;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x - 1, sp.G, sp.ngroups, g0, g1);
+    const double* st_vec = PRE ? v.st : v.s;
+    const double* rt_vec = PRE ? v.rt : v.r;
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 2>(S, C, g, st_vec, rt_vec, [&](int64_t i, double ui, double wi) {
+            v.u[i] = ui;
+            v.w[i] = wi;
+        });
+    }
+}
+
+// ------------------------------------------------------------------ HS-CG
+
+// Stage 2 of mu_{k-1} (alpha_{k-1}), then x += alpha p, r -= alpha s and the
+// partials of nu_k = <r~_k, r_k> (+ <r_k, r_k>), r~_k = M^{-1} r_k.
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restrict__ in, State* __restrict__ out,
+                                                  const double* __restrict__ PS, double* __restrict__ PU, Vecs v)
+{
+    __shared__ double lds[kWaves * 2];
+    State st = *in;
+    if (st.done) {
+        if (writer_thread()) *out = st;
+        return;
+    }
+    double t[1];
+    reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
+    step_hs_mu(st, t[0]);
+    if (writer_thread()) *out = st;
+    if (st.done) return;
+    const double alpha = st.alpha;
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = i0; i < i1; i += kBlock) {
+        v.x[i] = fma(alpha, v.p[i], v.x[i]);
+        const double ri = fma(-alpha, v.s[i], v.r[i]);
+        v.r[i] = ri;
+        const double rti = PRE ? v.d[i] * ri : ri;
+        acc[0] = fma(rti, ri, acc[0]);
+        if (PRE) acc[1] = fma(ri, ri, acc[1]);
+    }
+    write_partials<2>(acc, PU, sp.Gs, blockIdx.x, lds);
+}
+
+// Stage 2 of nu_k (convergence test, beta_k), then p_k = r~_k + beta_k p_{k-1}.
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restrict__ in, State* __restrict__ out,
+                                                 double* __restrict__ hist, const double* __restrict__ PU, Vecs v)
+{
+    __shared__ double lds[kWaves * 2];
+    State st = *in;
+    if (st.done) {
+        if (writer_thread()) *out = st;
+        return;
+    }
+    double t[2];
+    reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+    step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, writer_thread());
+    if (writer_thread()) *out = st;
+    if (st.done) return;
+    const double beta = st.beta;
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    for (int64_t i = i0; i < i1; i += kBlock) {
+        const double ri = v.r[i];
+        const double rti = PRE ? v.d[i] * ri : ri;
+        v.p[i] = fma(beta, v.p[i], rti);
+    }
+}
+
+// s_k = A p_k and the partials of mu_k = <p_k, s_k>.
+template <int LANES>
+__global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
+                                                    double* __restrict__ PS, Vecs v)
+{
+    __shared__ double lds[kWaves * 1];
+    if (cur->done) return;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[1] = {0.0};
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, v.p, nullptr, [&](int64_t i, double si, double) {
+            v.s[i] = si;
+            acc[0] = fma(v.p[i], si, acc[0]);
+        });
+    }
+    write_partials<1>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+// ------------------------------------------------------------------ exit
+
+// x_out = x (or 0 when b = 0) and the partials of ||b - A x_out||^2.
+template <int LANES>
+__global__ __launch_bounds__(kBlock) void k_final_res(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
+                                                      const double* __restrict__ b, const double* __restrict__ x,
+                                                      double* __restrict__ xout, double* __restrict__ PB)
+{
+    __shared__ double lds[kWaves * 1];
+    const int zero = cur->zero_x;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[1] = {0.0};
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, x, nullptr, [&](int64_t i, double ax, double) {
+            const double bi = b[i];
+            const double ti = zero ? bi : bi - ax;
+            xout[i] = zero ? 0.0 : x[i];
+            acc[0] = fma(ti, ti, acc[0]);
+        });
+    }
+    write_partials<1>(acc, PB, sp.Gs, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_reduce(Split sp, const double* __restrict__ PB, State* __restrict__ st)
+{
+    __shared__ double lds[kWaves * 1];
+    double t[1];
+    reduce_partials<1>(PB, sp.G, sp.Gs, t, lds);
+    if (threadIdx.x == 0) {
+        const double bn = st->bnorm;
+        st->relres_true = bn > 0.0 ? sqrt(t[0]) / bn : 0.0;
+    }
+}
+
+// y = A x
+template <int LANES>
+__global__ __launch_bounds__(kBlock) void k_spmv(SellView S, CsrView C, Split sp, const double* __restrict__ x,
+                                                 double* __restrict__ y)
+{
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    for (int64_t g = g0; g < g1; ++g)
+        rows_of_group<LANES, 1>(S, C, g, x, nullptr, [&](int64_t i, double yi, double) { y[i] = yi; });
+}
+
+// ------------------------------------------------------------------ host dispatch
+
+template <class F>
+hipError_t with_lanes(int lanes, F&& f)
+{
+    switch (lanes) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class F>
+hipError_t with_pre(int pre, F&& f)
+{
+    return pre ? f(std::true_type{}) : f(std::false_type{});
+}
+
+SellView sell_or_empty(const SellView* s) { return s ? *s : SellView{nullptr, nullptr, nullptr, 0, 0}; }
+CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullptr, nullptr, 0}; }
+
+}  // namespace
+
+hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView* csr, const Split& sp,
+                       const Vecs& v, const Bufs& B, const double* b, const double* x0, double tol, int32_t maxit,
+                       hipStream_t st)
+{
+    const SellView S = sell_or_empty(sell);
+    const CsrView C = csr_or_empty(csr);
+    const bool pipe = variant == kPipePR || variant == kPipeM;
+    const int store_rt = variant != kHS;  // r~ evolves by recurrence in PR and pipe-PR
+    const int store_st = pipe;            // s~ evolves by recurrence in pipe-PR
+    hipError_t e = with_lanes(sp.lanes, [&](auto L) {
+        return with_pre(pre, [&](auto P) {
+            hipLaunchKernelGGL((k_init_r<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
+                               S, C, sp, b, x0, v, store_rt, B.PB);
+            hipLaunchKernelGGL((k_init_s<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
+                               S, C, sp, v, store_st, B.PS);
+            if (pipe)
+                hipLaunchKernelGGL((k_init_u<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0,
+                                   st, S, C, sp, v);
+            return hipGetLastError();
+        });
+    });
+    if (e != hipSuccess) return e;
+    return with_pre(pre, [&](auto P) {
+        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, sp, B.PB,
+                           B.PS, B.S[0], B.hist, tol, (int)maxit);
+        return hipGetLastError();
+    });
+}
+
+int iter_kernel_count(int variant) { return variant == kHS ? 3 : 2; }
+
+const char* iter_kernel_name(int variant, int j)
+{
+    switch (variant) {
+    case kHS: return j == 0 ? "k_hs_xr" : (j == 1 ? "k_hs_p" : "k_hs_spmv");
+    case kPR:
+    case kM: return j == 0 ? "k_pr_update" : "k_pr_spmv";
+    default: return j == 0 ? "k_pipe_update" : "k_pipe_spmv";
+    }
+}
+
+hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellView* sell, const CsrView* csr,
+                              const Split& sp, const Vecs& v, const Bufs& B, hipStream_t st)
+{
+    const SellView S = sell_or_empty(sell);
+    const CsrView C = csr_or_empty(csr);
+    const dim3 grid(sp.G), block(kBlock);
+    const int nxt = 1 - cur;
+    const int meurant = variant == kM || variant == kPipeM;
+    hipError_t e = with_lanes(sp.lanes, [&](auto L) {
+        return with_pre(pre, [&](auto P) {
+            constexpr int LL = decltype(L)::value;
+            constexpr bool PP = decltype(P)::value;
+            switch (variant) {
+            case kPR:
+            case kM:
+                if (j == 0) {
+                    hipLaunchKernelGGL((k_pr_update<PP>), grid, block, 0, st, sp, B.S[cur], B.S[nxt], B.hist, B.PS,
+                                       meurant, v);
+                    cur = nxt;
+                } else {
+                    hipLaunchKernelGGL((k_pr_spmv<LL, PP>), grid, block, 0, st, S, C, sp, B.S[cur], B.PS, v);
+                }
+                break;
+            case kPipePR:
+            case kPipeM:
+                if (j == 0) {
+                    hipLaunchKernelGGL((k_pipe_update<PP>), grid, block, 0, st, sp, B.S[cur], B.PS, v);
+                } else {
+                    hipLaunchKernelGGL((k_pipe_spmv<LL, PP>), dim3(sp.G + 1), block, 0, st, S, C, sp, B.S[cur],
+                                       B.S[nxt], B.hist, B.PS, meurant, v);
+                    cur = nxt;
+                }
+                break;
+            default:  // HS
+                if (j == 0) {
+                    hipLaunchKernelGGL((k_hs_xr<PP>), grid, block, 0, st, sp, B.S[cur], B.S[nxt], B.PS, B.PU, v);
+                    cur = nxt;
+                } else if (j == 1) {
+                    hipLaunchKernelGGL((k_hs_p<PP>), grid, block, 0, st, sp, B.S[cur], B.S[nxt], B.hist, B.PU, v);
+                    cur = nxt;
+                } else {
+                    hipLaunchKernelGGL((k_hs_spmv<LL>), grid, block, 0, st, S, C, sp, B.S[cur], B.PS, v);
+                }
+                break;
+            }
+            return hipGetLastError();
+        });
+    });
+    return e;
+}
+
+hipError_t launch_final(const SellView* sell, const CsrView* csr, const Split& sp, const Vecs& v, const Bufs& B,
+                        int cur, const double* b, double* xout, hipStream_t st)
+{
+    const SellView S = sell_or_empty(sell);
+    const CsrView C = csr_or_empty(csr);
+    hipError_t e = with_lanes(sp.lanes, [&](auto L) {
+        hipLaunchKernelGGL((k_final_res<decltype(L)::value>), dim3(sp.G), dim3(kBlock), 0, st, S, C, sp, B.S[cur], b,
+                           v.x, xout, B.PB);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(kBlock), 0, st, sp, B.PB, B.S[cur]);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(const SellView* sell, const CsrView* csr, const Split& sp, const double* x, double* y,
+                       hipStream_t st)
+{
+    const SellView S = sell_or_empty(sell);
+    const CsrView C = csr_or_empty(csr);
+    return with_lanes(sp.lanes, [&](auto L) {
+        hipLaunchKernelGGL((k_spmv<decltype(L)::value>), dim3(sp.G), dim3(kBlock), 0, st, S, C, sp, x, y);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace prcg

@@ -1,0 +1,564 @@
+// libprcg host runtime: the C ABI of include/prcg.h.
+//
+// A matrix handle owns device copies of the CSR arrays, the SpMV layout
+// (SELL-64 for short rows, vector CSR for long ones), the Jacobi diagonal,
+// the solver vectors, the partial-sum buffers, two copies of the scalar
+// state and one instantiated HIP graph per variant.  A graph holds K
+// iterations of the variant's kernels; a solve runs the initialisation,
+// replays the graph until the device-side state says the solve ended (every
+// kernel returns at once after that), then computes the true residual.  The
+// host reads the state once per replay, overlapped with the next replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/prcg.h"
+#include "prcg_common.h"
+
+using namespace prcg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+prcg_status fail(prcg_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? PRCG_ENOMEM : PRCG_EDEVICE,                    \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+constexpr int kGraphIters = 16;  // iterations per graph replay (even: the state copy returns to 0)
+
+int env_int(const char* name, int dflt)
+{
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+bool is_device_pointer(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct prcg_matrix_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    int64_t n = 0, nnz = 0;
+    int precond = 0;
+    // CSR copies (the adjoint's outer product and value updates use them)
+    int32_t* row_ptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    // SELL-64 layout (when lanes == 1)
+    int64_t* slice_ptr = nullptr;
+    int32_t* scol = nullptr;
+    double* sval = nullptr;
+    int64_t nslices = 0;
+    int64_t stored = 0;
+    double* d = nullptr;
+    Split sp{};
+    // solver workspace
+    double* vecs = nullptr;  // x r rt p s st w u spare
+    State* S = nullptr;      // two copies
+    double* hist = nullptr;
+    int64_t hist_cap = 0;
+    double* partials = nullptr;  // PS | PU | PB
+    int32_t* dflags = nullptr;
+    State* hstate = nullptr;     // pinned, two slots
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+
+    SellView sell() const { return SellView{slice_ptr, scol, sval, n, nslices}; }
+    CsrView csr() const { return CsrView{row_ptr, col, val, n}; }
+    const SellView* sellp() const { return sp.lanes == 1 ? &sell_storage : nullptr; }
+    const CsrView* csrp() const { return sp.lanes == 1 ? nullptr : &csr_storage; }
+    SellView sell_storage{};
+    CsrView csr_storage{};
+
+    Vecs vecs_view() const
+    {
+        const size_t n8 = (size_t)n;
+        Vecs v;
+        v.x = vecs + 0 * n8;
+        v.r = vecs + 1 * n8;
+        v.rt = vecs + 2 * n8;
+        v.p = vecs + 3 * n8;
+        v.s = vecs + 4 * n8;
+        v.st = vecs + 5 * n8;
+        v.w = vecs + 6 * n8;
+        v.u = vecs + 7 * n8;
+        v.d = d;
+        return v;
+    }
+    double* spare() const { return vecs + 8 * (size_t)n; }
+
+    Bufs bufs() const
+    {
+        Bufs B;
+        B.S[0] = S;
+        B.S[1] = S + 1;
+        B.hist = hist;
+        B.PS = partials;
+        B.PU = partials + (size_t)kMaxDots * sp.Gs;
+        B.PB = partials + (size_t)(kMaxDots + 2) * sp.Gs;
+        return B;
+    }
+};
+
+namespace {
+
+void free_matrix(prcg_matrix A)
+{
+    if (!A) return;
+    (void)hipSetDevice(A->device);
+    for (auto& g : A->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& e : A->ev)
+        if (e) (void)hipEventDestroy(e);
+    void* dev[] = {A->row_ptr, A->col, A->val, A->slice_ptr, A->scol, A->sval, A->d, A->vecs,
+                   A->S, A->hist, A->partials, A->dflags};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (A->hstate) (void)hipHostFree(A->hstate);
+    if (A->capture) (void)hipStreamDestroy(A->capture);
+    delete A;
+}
+
+void invalidate_graphs(prcg_matrix A)
+{
+    for (auto& g : A->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Choose the work split: G workgroups (multiple of 8 when G >= 8, so every
+// XCD gets the same number), at most PRCG_GRID (default 1024).
+Split make_split(int64_t n, int lanes)
+{
+    Split sp{};
+    sp.n = n;
+    sp.lanes = lanes;
+    sp.ngroups = (n + kGroupRows - 1) / kGroupRows;
+    int gmax = std::max(8, env_int("PRCG_GRID", 1024));
+    int64_t G = std::min<int64_t>(sp.ngroups, gmax);
+    if (G >= 8) G -= G % 8;
+    sp.G = (int)std::max<int64_t>(G, 1);
+    sp.Gs = (sp.G + 63) / 64 * 64;
+    return sp;
+}
+
+prcg_status read_flags(prcg_matrix A, int32_t* host_flags, int nflags)
+{
+    HIP_TRY(hipMemcpyAsync(host_flags, A->dflags, sizeof(int32_t) * nflags, hipMemcpyDeviceToHost, A->stream));
+    HIP_TRY(hipStreamSynchronize(A->stream));
+    return PRCG_OK;
+}
+
+prcg_status ensure_hist(prcg_matrix A, int64_t need)
+{
+    if (A->hist_cap >= need) return PRCG_OK;
+    int64_t cap = std::max<int64_t>(need, 1024);
+    if (A->hist) HIP_TRY(hipFree(A->hist));
+    A->hist = nullptr;
+    A->hist_cap = 0;
+    HIP_TRY(hipMalloc(&A->hist, sizeof(double) * cap));
+    A->hist_cap = cap;
+    invalidate_graphs(A);  // the graphs hold the history pointer
+    return PRCG_OK;
+}
+
+prcg_status build_graph(prcg_matrix A, int variant)
+{
+    if (A->graph[variant]) return PRCG_OK;
+    const Vecs v = A->vecs_view();
+    const Bufs B = A->bufs();
+    HIP_TRY(hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal));
+    int cur = 0;
+    hipError_t err = hipSuccess;
+    for (int it = 0; it < kGraphIters && err == hipSuccess; ++it)
+        for (int j = 0; j < iter_kernel_count(variant) && err == hipSuccess; ++j)
+            err = launch_iter_kernel(variant, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, v, B, A->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(A->capture, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(PRCG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(err));
+    }
+    HIP_TRY(e2);
+    if (cur != 0) {
+        (void)hipGraphDestroy(g);
+        return fail(PRCG_EDEVICE, "internal: state copy does not return to 0 after a replay");
+    }
+    hipError_t e3 = hipGraphInstantiate(&A->graph[variant], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(e3);
+    return PRCG_OK;
+}
+
+// Runs a complete solve on the handle's stream.  x0 (device) may be the
+// spare zero vector; xout receives the result.
+prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double* x0, double* xout, double tol,
+                      int32_t maxit, State* final_state)
+{
+    prcg_status s = ensure_hist(A, (int64_t)maxit + 1);
+    if (s != PRCG_OK) return s;
+    s = build_graph(A, variant);
+    if (s != PRCG_OK) return s;
+    const Vecs v = A->vecs_view();
+    const Bufs B = A->bufs();
+    HIP_TRY(launch_init(variant, A->precond, A->sellp(), A->csrp(), A->sp, v, B, b, x0, tol, maxit, A->stream));
+    // transitions needed <= maxit + 2; each replay performs kGraphIters (HS: 2 per iteration)
+    const int64_t max_replays = ((int64_t)maxit + 2) / kGraphIters + 3;
+    int64_t launched = 0;
+    int pending = -1;  // slot whose copy is in flight
+    bool done = false;
+    while (!done) {
+        if (launched > max_replays)
+            return fail(PRCG_EDEVICE, "internal: solve did not finish within the expected number of replays");
+        HIP_TRY(hipGraphLaunch(A->graph[variant], A->stream));
+        const int slot = (int)(launched & 1);
+        HIP_TRY(hipMemcpyAsync(&A->hstate[slot], A->S, sizeof(State), hipMemcpyDeviceToHost, A->stream));
+        HIP_TRY(hipEventRecord(A->ev[slot], A->stream));
+        ++launched;
+        if (pending >= 0) {
+            HIP_TRY(hipEventSynchronize(A->ev[pending]));
+            done = A->hstate[pending].done != 0;
+        }
+        pending = slot;
+    }
+    HIP_TRY(launch_final(A->sellp(), A->csrp(), A->sp, v, B, 0, b, xout, A->stream));
+    HIP_TRY(hipMemcpyAsync(final_state, A->S, sizeof(State), hipMemcpyDeviceToHost, A->stream));
+    HIP_TRY(hipStreamSynchronize(A->stream));
+    return PRCG_OK;
+}
+
+prcg_status check_variant(int v)
+{
+    if (v < PRCG_HS || v > PRCG_PIPE_M) return fail(PRCG_EINVAL, "unknown variant");
+    return PRCG_OK;
+}
+
+void fill_info(const State& st, prcg_info* info)
+{
+    if (!info) return;
+    info->iters = st.k < 0 ? 0 : st.k;
+    info->status = st.status;
+    info->relres_updated = st.bnorm > 0.0 ? std::sqrt(st.rr > 0.0 ? st.rr : 0.0) / st.bnorm : 0.0;
+    info->relres_true = st.relres_true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* prcg_last_error(void) { return g_last_error.c_str(); }
+
+prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double* values, prcg_precond precond, void* hip_stream, prcg_matrix* out)
+{
+    if (!out) return fail(PRCG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t)1 << 31) return fail(PRCG_EINVAL, "n must satisfy 1 <= n < 2^31");
+    if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(PRCG_EINVAL, "nnz must satisfy 0 <= nnz < 2^31");
+    if (precond != PRCG_PRECOND_NONE && precond != PRCG_PRECOND_JACOBI) return fail(PRCG_EINVAL, "unknown precond");
+    if (!is_device_pointer(row_ptr) || (nnz > 0 && (!is_device_pointer(col_idx) || !is_device_pointer(values))))
+        return fail(PRCG_EINVAL, "row_ptr, col_idx and values must be device pointers");
+
+    prcg_matrix A = new prcg_matrix_s();
+    auto bail = [&](prcg_status s) {
+        free_matrix(A);
+        return s;
+    };
+#define TRY(expr)                                       \
+    do {                                                \
+        prcg_status s_ = (expr);                        \
+        if (s_ != PRCG_OK) return bail(s_);             \
+    } while (0)
+#define HTRY(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return bail(fail(e_ == hipErrorOutOfMemory ? PRCG_ENOMEM : PRCG_EDEVICE,                \
+                             std::string(#expr) + ": " + hipGetErrorString(e_)));                   \
+    } while (0)
+
+    HTRY(hipGetDevice(&A->device));
+    A->stream = (hipStream_t)hip_stream;
+    A->n = n;
+    A->nnz = nnz;
+    A->precond = precond;
+    HTRY(hipStreamCreateWithFlags(&A->capture, hipStreamNonBlocking));
+    HTRY(hipMalloc(&A->row_ptr, sizeof(int32_t) * (n + 1)));
+    HTRY(hipMalloc(&A->col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+    HTRY(hipMalloc(&A->val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+    HTRY(hipMalloc(&A->dflags, sizeof(int32_t) * 4));
+    HTRY(hipHostMalloc(&A->hstate, sizeof(State) * 2, hipHostMallocDefault));
+    HTRY(hipEventCreateWithFlags(&A->ev[0], hipEventDisableTiming));
+    HTRY(hipEventCreateWithFlags(&A->ev[1], hipEventDisableTiming));
+    HTRY(hipMemcpyAsync(A->row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, A->stream));
+    if (nnz > 0) {
+        HTRY(hipMemcpyAsync(A->col, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, A->stream));
+        HTRY(hipMemcpyAsync(A->val, values, sizeof(double) * nnz, hipMemcpyDeviceToDevice, A->stream));
+    }
+
+    // validate the structure (flags[0]) and find the longest row (flags[1])
+    HTRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t) * 4, A->stream));
+    HTRY(launch_validate(n, nnz, A->row_ptr, A->col, A->dflags, A->dflags + 1, A->stream));
+    int32_t hf[4];
+    TRY(read_flags(A, hf, 4));
+    if (hf[0] & 1) return bail(fail(PRCG_EINVAL, "row_ptr[0] must be 0"));
+    if (hf[0] & 2) return bail(fail(PRCG_EINVAL, "row_ptr must be non-decreasing within [0, nnz]"));
+    if (hf[0] & 4) return bail(fail(PRCG_EINVAL, "row_ptr[n] must equal nnz"));
+    if (hf[0] & 8) return bail(fail(PRCG_EINVAL, "column index out of range"));
+    const int32_t maxlen = hf[1];
+
+    if (precond == PRCG_PRECOND_JACOBI) {
+        HTRY(hipMalloc(&A->d, sizeof(double) * n));
+        HTRY(launch_jacobi(n, A->row_ptr, A->col, A->val, A->d, A->dflags, A->stream));
+        TRY(read_flags(A, hf, 1));
+        if (hf[0] & 16) return bail(fail(PRCG_EINVAL, "Jacobi needs every diagonal entry present and > 0"));
+    }
+
+    // SELL-64 sizes; keep SELL unless padding would inflate storage a lot
+    A->nslices = (n + kSlice - 1) / kSlice;
+    HTRY(hipMalloc(&A->slice_ptr, sizeof(int64_t) * (A->nslices + 1)));
+    {
+        int64_t* sizes = nullptr;
+        HTRY(hipMalloc(&sizes, sizeof(int64_t) * A->nslices));
+        hipError_t e1 = launch_slice_sizes(n, A->row_ptr, sizes, A->stream);
+        hipError_t e2 = e1 == hipSuccess ? launch_exclusive_scan(sizes, A->slice_ptr, A->nslices, A->stream) : e1;
+        hipError_t e3 = e2 == hipSuccess ? hipMemcpyAsync(&A->stored, A->slice_ptr + A->nslices, sizeof(int64_t),
+                                                          hipMemcpyDeviceToHost, A->stream)
+                                         : e2;
+        hipError_t e4 = e3 == hipSuccess ? hipStreamSynchronize(A->stream) : e3;
+        (void)hipFree(sizes);
+        HTRY(e4);
+    }
+    int lanes = 1;
+    const char* fmt = std::getenv("PRCG_FORMAT");
+    const double mean = (double)nnz / (double)n;
+    if (fmt && std::strncmp(fmt, "csr", 3) == 0) {
+        lanes = std::atoi(fmt + 3);
+        if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) lanes = 8;
+    } else if (!(fmt && std::strcmp(fmt, "sell") == 0)) {
+        const bool sell_ok = (double)A->stored <= 1.5 * (double)nnz + 64.0 * (double)A->nslices && maxlen <= 256;
+        if (!sell_ok) lanes = mean >= 96 ? 64 : mean >= 48 ? 32 : mean >= 24 ? 16 : 8;
+    }
+    if (lanes == 1) {
+        HTRY(hipMalloc(&A->scol, sizeof(int32_t) * std::max<int64_t>(A->stored, 1)));
+        HTRY(hipMalloc(&A->sval, sizeof(double) * std::max<int64_t>(A->stored, 1)));
+        HTRY(launch_fill_sell(n, A->row_ptr, A->col, A->val, A->slice_ptr, A->scol, A->sval, 1, A->stream));
+    }
+    A->sp = make_split(n, lanes);
+    A->sell_storage = A->sell();
+    A->csr_storage = A->csr();
+
+    HTRY(hipMalloc(&A->vecs, sizeof(double) * 9 * (size_t)n));
+    HTRY(hipMemsetAsync(A->vecs, 0, sizeof(double) * 9 * (size_t)n, A->stream));
+    HTRY(hipMalloc(&A->S, sizeof(State) * 2));
+    HTRY(hipMemsetAsync(A->S, 0, sizeof(State) * 2, A->stream));
+    HTRY(hipMalloc(&A->partials, sizeof(double) * (kMaxDots + 3) * (size_t)A->sp.Gs));
+    HTRY(hipStreamSynchronize(A->stream));
+    TRY(ensure_hist(A, 1024));
+    *out = A;
+    return PRCG_OK;
+#undef TRY
+#undef HTRY
+}
+
+prcg_status prcg_set_stream(prcg_matrix A, void* hip_stream)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    A->stream = (hipStream_t)hip_stream;
+    return PRCG_OK;
+}
+
+prcg_status prcg_set_values(prcg_matrix A, const double* values)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    if (A->nnz > 0 && !is_device_pointer(values)) return fail(PRCG_EINVAL, "values must be a device pointer");
+    HIP_TRY(hipSetDevice(A->device));
+    if (A->nnz > 0)
+        HIP_TRY(hipMemcpyAsync(A->val, values, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, A->stream));
+    if (A->sp.lanes == 1)
+        HIP_TRY(launch_fill_sell(A->n, A->row_ptr, A->col, A->val, A->slice_ptr, A->scol, A->sval, 0, A->stream));
+    if (A->precond == PRCG_PRECOND_JACOBI) {
+        HIP_TRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), A->stream));
+        HIP_TRY(launch_jacobi(A->n, A->row_ptr, A->col, A->val, A->d, A->dflags, A->stream));
+        int32_t hf[1];
+        prcg_status s = read_flags(A, hf, 1);
+        if (s != PRCG_OK) return s;
+        if (hf[0] & 16) return fail(PRCG_EINVAL, "Jacobi needs every diagonal entry present and > 0");
+    }
+    HIP_TRY(hipStreamSynchronize(A->stream));
+    return PRCG_OK;
+}
+
+prcg_status prcg_spmv(prcg_matrix A, const double* x, double* y)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    if (!is_device_pointer(x) || !is_device_pointer(y)) return fail(PRCG_EINVAL, "x and y must be device pointers");
+    if (x == y) return fail(PRCG_EINVAL, "x and y must not overlap");
+    HIP_TRY(hipSetDevice(A->device));
+    HIP_TRY(launch_spmv(A->sellp(), A->csrp(), A->sp, x, y, A->stream));
+    HIP_TRY(hipStreamSynchronize(A->stream));
+    return PRCG_OK;
+}
+
+prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x, double tol, int32_t maxit,
+                       prcg_info* info, double* history)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (!(tol >= 0.0)) return fail(PRCG_EINVAL, "tol must be >= 0");
+    if (maxit < 0) return fail(PRCG_EINVAL, "maxit must be >= 0");
+    if (!is_device_pointer(b) || !is_device_pointer(x)) return fail(PRCG_EINVAL, "b and x must be device pointers");
+    HIP_TRY(hipSetDevice(A->device));
+    State st;
+    prcg_status s = run_solve(A, v, b, x, x, tol, maxit, &st);
+    if (s != PRCG_OK) return s;
+    if (history) {
+        const int32_t k = st.k < 0 ? 0 : st.k;
+        HIP_TRY(hipMemcpy(history, A->hist, sizeof(double) * (k + 1), hipMemcpyDeviceToHost));
+    }
+    fill_info(st, info);
+    return (prcg_status)st.status;
+}
+
+prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
+{
+    if (!A || !props) return fail(PRCG_EINVAL, "null argument");
+    props->n = A->n;
+    props->nnz = A->nnz;
+    props->format = A->sp.lanes == 1 ? 0 : 1;
+    props->lanes_per_row = A->sp.lanes;
+    props->stored_entries = A->sp.lanes == 1 ? A->stored : A->nnz;
+    props->grid = A->sp.G;
+    props->block = kBlock;
+    props->matrix_bytes = A->sp.lanes == 1 ? 12 * A->stored + 8 * (A->nslices + 1)
+                                           : 12 * A->nnz + 4 * (A->n + 1);
+    return PRCG_OK;
+}
+
+prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, double* ms_per_launch,
+                              char (*names)[48], int32_t* nkernels)
+{
+    if (!A || !ms_per_launch || !nkernels) return fail(PRCG_EINVAL, "null argument");
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (iters < 1) return fail(PRCG_EINVAL, "iters must be >= 1");
+    HIP_TRY(hipSetDevice(A->device));
+    prcg_status s = ensure_hist(A, (int64_t)iters + 2);
+    if (s != PRCG_OK) return s;
+    const Vecs vv = A->vecs_view();
+    const Bufs B = A->bufs();
+    // right-hand side: the spare vector filled with ones; x0 = 0 (vector x)
+    const int nk = iter_kernel_count(v);
+    std::vector<double> ones((size_t)A->n, 1.0);
+    double* bvec = A->spare();
+    HIP_TRY(hipMemcpyAsync(bvec, ones.data(), sizeof(double) * A->n, hipMemcpyHostToDevice, A->stream));
+    HIP_TRY(hipMemsetAsync(vv.x, 0, sizeof(double) * A->n, A->stream));
+    HIP_TRY(launch_init(v, A->precond, A->sellp(), A->csrp(), A->sp, vv, B, bvec, vv.x, 0.0, iters + 1, A->stream));
+    std::vector<hipEvent_t> ev((size_t)2 * nk * iters, nullptr);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    int cur = 0;
+    hipError_t err = hipSuccess;
+    for (int it = 0; it < iters && err == hipSuccess; ++it)
+        for (int j = 0; j < nk && err == hipSuccess; ++j) {
+            const size_t q = (size_t)2 * (it * nk + j);
+            err = hipEventRecord(ev[q], A->stream);
+            if (err == hipSuccess)
+                err = launch_iter_kernel(v, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, vv, B, A->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[q + 1], A->stream);
+        }
+    if (err == hipSuccess) err = hipStreamSynchronize(A->stream);
+    std::vector<double> tot((size_t)nk, 0.0);
+    for (int it = 0; it < iters && err == hipSuccess; ++it)
+        for (int j = 0; j < nk && err == hipSuccess; ++j) {
+            const size_t q = (size_t)2 * (it * nk + j);
+            float ms = 0.f;
+            err = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            tot[j] += ms;
+        }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    HIP_TRY(err);
+    State st;
+    HIP_TRY(hipMemcpy(&st, A->S + cur, sizeof(State), hipMemcpyDeviceToHost));
+    if (st.done && st.k < iters)
+        return fail(PRCG_EDEVICE, "timing run ended early (breakdown); times would be diluted");
+    *nkernels = nk;
+    for (int j = 0; j < nk; ++j) {
+        ms_per_launch[j] = tot[j] / iters;
+        if (names) {
+            std::snprintf(names[j], 48, "%s", iter_kernel_name(v, j));
+        }
+    }
+    return PRCG_OK;
+}
+
+prcg_status prcg_adjoint(prcg_matrix A, prcg_variant v, const double* x, const double* gx, double* gb, double* gvals,
+                         double tol, int32_t maxit, prcg_info* info)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (!(tol >= 0.0) || maxit < 0) return fail(PRCG_EINVAL, "tol must be >= 0 and maxit >= 0");
+    if (!is_device_pointer(x) || !is_device_pointer(gx)) return fail(PRCG_EINVAL, "x and gx must be device pointers");
+    if ((gb && !is_device_pointer(gb)) || (gvals && !is_device_pointer(gvals)))
+        return fail(PRCG_EINVAL, "gb and gvals must be device pointers");
+    HIP_TRY(hipSetDevice(A->device));
+    // lambda = A^{-1} gx from x0 = 0 (the spare vector, zeroed); the result
+    // goes to gb, or to the spare vector itself when gb is NULL (the
+    // initialisation has copied x0 before the result is written).
+    double* x0 = A->spare();
+    double* lam = gb ? gb : x0;
+    HIP_TRY(hipMemsetAsync(x0, 0, sizeof(double) * A->n, A->stream));
+    State st;
+    prcg_status s = run_solve(A, v, gx, x0, lam, tol, maxit, &st);
+    if (s != PRCG_OK) return s;
+    if (gvals && A->nnz > 0) {
+        HIP_TRY(launch_outer_csr(A->n, A->row_ptr, A->col, lam, x, gvals, A->stream));
+        HIP_TRY(hipStreamSynchronize(A->stream));
+    }
+    fill_info(st, info);
+    return (prcg_status)st.status;
+}
+
+void prcg_destroy(prcg_matrix A) { free_matrix(A); }
+
+prcg_status prcg_create_batch(prcg_matrix, int32_t, const int64_t*, prcg_batch* out)
+{
+    if (out) *out = nullptr;
+    return fail(PRCG_EINVAL, "batched solver not available in this build");
+}
+
+prcg_status prcg_solve_batched(prcg_batch, prcg_variant, const double*, double*, double, int32_t, int32_t*, int32_t*)
+{
+    return fail(PRCG_EINVAL, "batched solver not available in this build");
+}
+
+void prcg_batch_destroy(prcg_batch) {}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal declarations shared by the libprcg translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace prcg {
+
+constexpr int kBlock = 256;     // threads per workgroup of every row-parallel kernel
+constexpr int kWaves = kBlock / 64;
+constexpr int kSlice = 64;      // SELL slice height: one wavefront, one row per lane
+constexpr int kGroupRows = kBlock;  // rows handled by one workgroup step (4 slices)
+constexpr int kMaxDots = 5;
+
+enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4 };
+enum Status { kOK = 0, kNotConverged = 1, kBreakdown = 2 };
+
+// Scalar state of a solve, resident in device memory.  Two copies are kept
+// and each kernel that advances the state reads one and writes the other, so
+// no workgroup ever reads a copy that another workgroup of the same kernel
+// is writing.
+struct alignas(128) State {
+    double alpha;        // alpha_k (used by the vector updates of iteration k+1)
+    double beta;         // beta_{k+1}
+    double nu;           // nu_k (the recomputed value)
+    double mu, sigma, gamma, rr;
+    double nup;          // nu'_{k+1}
+    double bnorm;        // ||b||
+    double tol;
+    double relres_true;  // ||b - A x|| / ||b||, filled at exit
+    int32_t k;           // index of the last reduction processed
+    int32_t done;        // 1 once the solve has ended
+    int32_t status;      // Status
+    int32_t last;        // 1 when nu' <= 0 made the next iteration the final one
+    int32_t maxit;
+    int32_t zero_x;      // b = 0: the returned x is 0
+    int32_t pad[2];
+};
+
+// SELL-64 matrix: rows are cut into slices of 64; slice s stores its
+// entries column-major, entry j of row 64 s + l at slice_ptr[s] + 64 j + l.
+// Rows shorter than the slice width are padded with value 0 and their own
+// row index as column.
+struct SellView {
+    const int64_t* slice_ptr;  // [nslices + 1]
+    const int32_t* col;
+    const double* val;
+    int64_t n;
+    int64_t nslices;
+};
+
+// Vector-CSR matrix for long rows: L lanes per row, CSR arrays as given.
+struct CsrView {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+    int64_t n;
+};
+
+// Work split of the row-parallel kernels: G workgroups; workgroup b owns a
+// contiguous run of 256-row groups.  Runs are assigned so that the
+// workgroups an XCD receives (b mod 8) own neighbouring runs.
+struct Split {
+    int64_t n;      // rows
+    int G;          // workgroups (partial sums per reduction)
+    int Gs;         // stride between reduction values in a partials buffer
+    int64_t ngroups;
+    int lanes;      // 1 = SELL-64, else lanes per row of vector CSR
+};
+
+// ---- setup kernels (kernels_setup.hip) ----
+hipError_t launch_validate(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                           int32_t* flags, int32_t* maxlen, hipStream_t st);
+hipError_t launch_jacobi(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                         double* d, int32_t* flags, hipStream_t st);
+hipError_t launch_slice_sizes(int64_t n, const int32_t* row_ptr, int64_t* sizes, hipStream_t st);
+hipError_t launch_exclusive_scan(const int64_t* in, int64_t* out, int64_t m, hipStream_t st);
+hipError_t launch_fill_sell(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                            const int64_t* slice_ptr, int32_t* scol, double* sval, int write_cols,
+                            hipStream_t st);
+hipError_t launch_block_check(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                              const int32_t* row_sys, const int64_t* sys_off, int32_t* flags, hipStream_t st);
+hipError_t launch_outer_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* lam,
+                            const double* x, double* g, hipStream_t st);
+hipError_t launch_spmv(const SellView* sell, const CsrView* csr, const Split& sp, const double* x,
+                       double* y, hipStream_t st);
+
+// ---- iteration kernels (kernels_iter.hip) ----
+struct Vecs {
+    double *x, *r, *rt, *p, *s, *st, *w, *u;
+    const double* d;  // Jacobi reciprocal diagonal or nullptr
+};
+
+struct Bufs {
+    State* S[2];
+    double* hist;
+    double* PS;  // [mu, sigma, gamma, nu, rr] partials
+    double* PU;  // [nu, rr] partials (HS)
+    double* PB;  // [bb] or [tt] partials
+};
+
+hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView* csr, const Split& sp,
+                       const Vecs& v, const Bufs& B, const double* b, const double* x0, double tol,
+                       int32_t maxit, hipStream_t st);
+// Number of kernels per iteration and their launch; `cur` is the state copy
+// that holds the current state and is updated.
+int iter_kernel_count(int variant);
+const char* iter_kernel_name(int variant, int j);
+hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellView* sell,
+                              const CsrView* csr, const Split& sp, const Vecs& v, const Bufs& B,
+                              hipStream_t st);
+hipError_t launch_final(const SellView* sell, const CsrView* csr, const Split& sp, const Vecs& v,
+                        const Bufs& B, int cur, const double* b, double* xout, hipStream_t st);
+
+}  // namespace prcg

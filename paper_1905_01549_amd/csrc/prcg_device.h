@@ -1,0 +1,158 @@
+// Device helpers shared by the libprcg kernels: deterministic reductions,
+// the XCD-aware split of rows over workgroups and the sparse row products.
+#pragma once
+
+#include "prcg_common.h"
+
+namespace prcg {
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Sum over the 64 lanes of a wavefront by a fixed butterfly; every lane ends
+// with the same bits (each level adds the same two operands).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of NV values over the workgroup (256 threads); every thread receives
+// the totals.  The order of additions is fixed, so results are repeatable.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* kWaves * NV */)
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lds[w * NV + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = lds[i];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) t += lds[q * NV + i];
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
+// Stage 2 of a reduction: the G per-workgroup partials of each of NV values
+// (value i at P[i * Gs + g]) are summed in a fixed order.  Every thread of
+// the calling workgroup receives the totals.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
+                                                double* lds)
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tot[i] = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) tot[i] += P[i * Gs + g];
+    }
+    block_sum<NV>(tot, lds);
+}
+
+// Stage 1: per-thread sums -> one partial per workgroup and value.
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&acc)[NV], double* __restrict__ P, int Gs, int slot,
+                                               double* lds)
+{
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) P[i * Gs + slot] = acc[i];
+    }
+}
+
+// Workgroup b of G owns the 256-row groups [g0, g1).  The hardware hands
+// workgroups to the 8 XCDs round-robin (b mod 8), so consecutive runs are
+// given to workgroups of the same XCD: neighbouring rows then share an L2.
+__device__ __forceinline__ void chunk_of(int b, int G, int64_t ngroups, int64_t& g0, int64_t& g1)
+{
+    int c = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    g0 = (int64_t)c * ngroups / G;
+    g1 = (int64_t)(c + 1) * ngroups / G;
+}
+
+// Products of one SELL-64 row with NX vectors (entries summed in stored order).
+template <int NX>
+__device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, const double* __restrict__ x0,
+                                         const double* __restrict__ x1, double& y0, double& y1)
+{
+    const int64_t base = A.slice_ptr[slice];
+    const int width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
+    const int32_t* __restrict__ c = A.col + base + lane;
+    const double* __restrict__ v = A.val + base + lane;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < width; ++j) {
+        const int cj = c[(int64_t)j * 64];
+        const double vj = v[(int64_t)j * 64];
+        a0 = fma(vj, x0[cj], a0);
+        if (NX == 2) a1 = fma(vj, x1[cj], a1);
+    }
+    y0 = a0;
+    y1 = a1;
+}
+
+// Calls f(row, y0, y1) for every row of 256-row group g, where y = A x for
+// one or two vectors.  SELL-64: one row per thread.
+template <int NX, class F>
+__device__ __forceinline__ void sell_group(const SellView& A, int64_t g, const double* __restrict__ x0,
+                                           const double* __restrict__ x1, F&& f)
+{
+    const int w = uniform(threadIdx.x >> 6);
+    const int64_t slice = g * kWaves + w;
+    if (slice >= A.nslices) return;
+    const int lane = threadIdx.x & 63;
+    double y0, y1;
+    sell_row<NX>(A, slice, lane, x0, x1, y0, y1);
+    const int64_t row = slice * kSlice + lane;
+    if (row < A.n) f(row, y0, y1);
+}
+
+// Vector CSR with L lanes per row: the 256 rows of group g are done in L
+// passes of 256/L rows; lane 0 of each L-lane team receives the row sums.
+template <int L, int NX, class F>
+__device__ __forceinline__ void csr_group(const CsrView& A, int64_t g, const double* __restrict__ x0,
+                                          const double* __restrict__ x1, F&& f)
+{
+    const int sub = threadIdx.x % L;
+    const int team = threadIdx.x / L;
+    for (int q = 0; q < L; ++q) {
+        const int64_t row = g * kGroupRows + (int64_t)q * (kBlock / L) + team;
+        double a0 = 0.0, a1 = 0.0;
+        if (row < A.n) {
+            const int32_t e1 = A.row_ptr[row + 1];
+            for (int32_t e = A.row_ptr[row] + sub; e < e1; e += L) {
+                const double ve = A.val[e];
+                const int ce = A.col[e];
+                a0 = fma(ve, x0[ce], a0);
+                if (NX == 2) a1 = fma(ve, x1[ce], a1);
+            }
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) {
+            a0 += __shfl_xor(a0, off, 64);
+            if (NX == 2) a1 += __shfl_xor(a1, off, 64);
+        }
+        if (sub == 0 && row < A.n) f(row, a0, a1);
+    }
+}
+
+// Dispatch on the storage format (LANES == 1: SELL-64, else vector CSR).
+template <int LANES, int NX, class F>
+__device__ __forceinline__ void rows_of_group(const SellView& S, const CsrView& C, int64_t g,
+                                              const double* __restrict__ x0, const double* __restrict__ x1, F&& f)
+{
+    if constexpr (LANES == 1)
+        sell_group<NX>(S, g, x0, x1, f);
+    else
+        csr_group<LANES, NX>(C, g, x0, x1, f);
+}
+
+}  // namespace prcg

@@ -1,0 +1,42 @@
+"""Algorithmic HBM bytes of the solver's kernels.
+
+Counting rule: the SpMV layout is read once per product; every row-indexed
+float64 vector a kernel needs is read once and every vector it updates is
+written once (8 bytes per row each); vectors gathered at neighbouring rows
+are counted once (the extra gathers hit the caches).  Vectors that the
+algorithms define as M^{-1} v are recomputed from the Jacobi diagonal d and
+count as a read of d.
+"""
+from __future__ import annotations
+
+# (reads, writes) in float64 words per row, per kernel, per variant and
+# preconditioning (True = Jacobi).  "matrix" marks the kernel reading A.
+KERNEL_WORDS = {
+    ("hs", False): [("k_hs_xr", 4, 2, False), ("k_hs_p", 2, 1, False), ("k_hs_spmv", 1, 1, True)],
+    ("hs", True): [("k_hs_xr", 5, 2, False), ("k_hs_p", 3, 1, False), ("k_hs_spmv", 1, 1, True)],
+    ("pr", False): [("k_pr_update", 4, 3, False), ("k_pr_spmv", 2, 1, True)],
+    ("pr", True): [("k_pr_update", 6, 4, False), ("k_pr_spmv", 4, 1, True)],
+    ("pipe_pr", False): [("k_pipe_update", 6, 4, False), ("k_pipe_spmv", 2, 2, True)],
+    ("pipe_pr", True): [("k_pipe_update", 9, 6, False), ("k_pipe_spmv", 2, 2, True)],
+}
+KERNEL_WORDS[("m", False)] = KERNEL_WORDS[("pr", False)]
+KERNEL_WORDS[("m", True)] = KERNEL_WORDS[("pr", True)]
+KERNEL_WORDS[("pipe_m", False)] = KERNEL_WORDS[("pipe_pr", False)]
+KERNEL_WORDS[("pipe_m", True)] = KERNEL_WORDS[("pipe_pr", True)]
+
+
+def kernel_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int) -> dict:
+    """Algorithmic bytes per launch of each kernel of one iteration."""
+    out = {}
+    for name, r, w, mat in KERNEL_WORDS[(variant, jacobi)]:
+        out[name] = 8 * n * (r + w) + (matrix_bytes if mat else 0)
+    return out
+
+
+def iteration_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int) -> int:
+    return sum(kernel_bytes(variant, jacobi, n, matrix_bytes).values())
+
+
+def csr_matrix_bytes(n: int, nnz: int) -> int:
+    """Bytes of plain CSR (int32 indices, float64 values) read once."""
+    return 12 * nnz + 4 * (n + 1)
