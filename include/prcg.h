@@ -88,12 +88,15 @@ typedef struct {
 typedef struct {
     int64_t n;
     int64_t nnz;
-    int64_t stored_entries;   /* entries held by the SpMV layout, padding included */
-    int32_t format;           /* 0 = SELL-64 (one row per lane), 1 = vector CSR     */
-    int32_t lanes_per_row;    /* 1 for SELL-64, L for vector CSR                    */
-    int32_t grid;             /* workgroups of the row-parallel kernels             */
-    int32_t block;            /* threads per workgroup                              */
-    int64_t matrix_bytes;     /* bytes of the SpMV layout read by one product       */
+    int64_t stored_entries;   /* value slots of the SpMV layout, padding included    */
+    int32_t format;           /* 0 = SELL-64 (one row per lane), 1 = vector CSR      */
+    int32_t lanes_per_row;    /* 1 for SELL-64, L for vector CSR                     */
+    int32_t grid;             /* workgroups of the row-parallel kernels              */
+    int32_t block;            /* threads per workgroup                               */
+    int64_t matrix_bytes;     /* bytes of the SpMV layout read by one product        */
+    double aligned_slices_frac; /* SELL-64: share of slots in offset-aligned slices,
+                                   which store one column offset per slot and slice
+                                   instead of a column index per entry              */
 } prcg_matrix_props;
 
 /*
@@ -153,10 +156,11 @@ prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x
                        int32_t maxit, prcg_info* info, double* history);
 
 /*
- * Per-kernel device time of `iters` iterations of variant v, continuing
- * from the state left by the last prcg_solve on A with the same variant
- * (the iteration is run with tol = 0, so the iterations are genuine work).
- * Each kernel launch is bracketed by HIP events on the handle's stream.
+ * Per-kernel device time of `iters` iterations of variant v on A, from
+ * x0 = 0 with b = (1, ..., 1) and tol = 0 (so every iteration does its full
+ * work; PRCG_EDEVICE if the run ends early).  Each launch carries dispatch
+ * start/stop timestamps (hipExtLaunchKernelGGL events), so the times are
+ * kernel execution times.  Overwrites the solver state of A.
  *   ms_per_launch  host float64[8]: average milliseconds per launch of each
  *                  kernel of one iteration, in launch order.
  *   names          host, nullable, char[8][48]: kernel names.

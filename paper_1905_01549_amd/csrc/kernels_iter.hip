@@ -27,11 +27,24 @@
 // needed instead of being stored; this gives identical bits.  Vectors
 // defined by recurrence (PR/pipe r~, pipe s~) are stored.  Without a
 // preconditioner every tilde vector is its plain counterpart.
+#include <hip/hip_ext.h>
+
 #include "prcg_device.h"
 
 namespace prcg {
 
 namespace {
+
+// Launch with optional dispatch timestamps (start/stop events recorded by
+// the dispatch itself, so they measure the kernel and nothing else).
+template <class K, class... Args>
+void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, const LaunchEvents* ev, Args... args)
+{
+    if (ev && ev->start)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev->start, ev->stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
@@ -241,39 +254,83 @@ __device__ __forceinline__ void row_range(const Split& sp, int64_t g0, int64_t g
 // Stage 2 of iteration k + scalar step, then the vector updates of
 // iteration k+1 (Alg. 2): x += alpha p; r -= alpha s; r~ -= alpha s~;
 // p = r~ + beta p.
-template <bool PRE>
+// REDUCE = false: the state was already advanced by k_pr_finish and `in`
+// is the current state (`out` unused).
+template <bool PRE, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, int meurant, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
     State st = *in;
-    if (st.done) {
+    if (REDUCE) {
+        if (st.done) {
+            if (writer_thread()) *out = st;
+            return;
+        }
+        double t[5];
+        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        step_one_reduction(st, t, PRE, meurant != 0, hist, writer_thread());
         if (writer_thread()) *out = st;
-        return;
     }
-    double t[5];
-    reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
-    step_one_reduction(st, t, PRE, meurant != 0, hist, writer_thread());
-    if (writer_thread()) *out = st;
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
-    for (int64_t i = i0; i < i1; i += kBlock) {
-        const double si = v.s[i];
-        const double pi = v.p[i];
-        v.x[i] = fma(alpha, pi, v.x[i]);
-        const double ri = fma(-alpha, si, v.r[i]);
-        v.r[i] = ri;
-        double rti = ri;
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    double* __restrict__ rt = v.rt;
+    double* __restrict__ p = v.p;
+    const double* __restrict__ s = v.s;
+    const double* __restrict__ d = v.d;
+    // two rows per step, every load issued before the first store
+    for (int64_t i = i0; i < i1; i += 2 * kBlock) {
+        const int64_t j = i + kBlock;
+        const bool two = j < i1;
+        const int64_t jj = two ? j : i;
+        const double s0 = s[i], s1 = s[jj];
+        const double p0 = p[i], p1 = p[jj];
+        const double x0 = x[i], x1 = x[jj];
+        const double r0 = r[i], r1 = r[jj];
+        double rt0 = 0.0, rt1 = 0.0, d0 = 0.0, d1 = 0.0;
         if (PRE) {
-            rti = fma(-alpha, v.d[i] * si, v.rt[i]);
-            v.rt[i] = rti;
+            rt0 = rt[i];
+            rt1 = rt[jj];
+            d0 = d[i];
+            d1 = d[jj];
         }
-        v.p[i] = fma(beta, pi, rti);
+        const double rn0 = fma(-alpha, s0, r0), rn1 = fma(-alpha, s1, r1);
+        const double rtn0 = PRE ? fma(-alpha, d0 * s0, rt0) : rn0;
+        const double rtn1 = PRE ? fma(-alpha, d1 * s1, rt1) : rn1;
+        x[i] = fma(alpha, p0, x0);
+        r[i] = rn0;
+        if (PRE) rt[i] = rtn0;
+        p[i] = fma(beta, p0, rtn0);
+        if (two) {
+            x[j] = fma(alpha, p1, x1);
+            r[j] = rn1;
+            if (PRE) rt[j] = rtn1;
+            p[j] = fma(beta, p1, rtn1);
+        }
     }
+}
+
+// One workgroup: stage 2 of iteration k and the scalar step (used when
+// the update kernel should not reduce the partials itself).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pr_finish(Split sp, const State* __restrict__ in,
+                                                      State* __restrict__ out, double* __restrict__ hist,
+                                                      const double* __restrict__ PS, int meurant)
+{
+    __shared__ double lds[kWaves * 5];
+    State st = *in;
+    if (!st.done) {
+        double t[5];
+        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+    }
+    if (threadIdx.x == 0) *out = st;
 }
 
 // s_k = A p_k, s~_k = M^{-1} s_k, and the inner products of Alg. 2
@@ -323,36 +380,46 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    double* __restrict__ rt = v.rt;
+    double* __restrict__ p = v.p;
+    double* __restrict__ s = v.s;
+    double* __restrict__ stv = v.st;
+    const double* __restrict__ w = v.w;
+    const double* __restrict__ u = v.u;
+    const double* __restrict__ d = v.d;
     for (int64_t i = i0; i < i1; i += kBlock) {
-        const double pi = v.p[i];
-        const double si = v.s[i];
-        const double wi = v.w[i];
-        const double ui = v.u[i];
-        v.x[i] = fma(alpha, pi, v.x[i]);
-        const double ri = fma(-alpha, si, v.r[i]);
-        v.r[i] = ri;
-        const double wpi = fma(-alpha, ui, wi);            // w'_k
-        double rti = ri, sti;
-        const double snew = fma(beta, si, wpi);            // s_k = w'_k + beta s_{k-1}
+        const double pi = p[i], si = s[i], wi = w[i], ui = u[i], xi = x[i], ri = r[i];
+        double di = 0.0, sti_old = 0.0, rti_old = 0.0;
         if (PRE) {
-            const double di = v.d[i];
-            const double sti_old = v.st[i];
-            rti = fma(-alpha, sti_old, v.rt[i]);           // r~_k
-            v.rt[i] = rti;
-            const double wtpi = fma(-alpha, di * ui, di * wi);  // w~'_k = w~ - alpha u~
-            sti = fma(beta, sti_old, wtpi);                // s~_k
-            v.st[i] = sti;
-        } else {
-            sti = snew;
+            di = d[i];
+            sti_old = stv[i];
+            rti_old = rt[i];
         }
-        const double pnew = fma(beta, pi, rti);            // p_k
-        v.p[i] = pnew;
-        v.s[i] = snew;
-        acc[0] = fma(pnew, snew, acc[0]);                  // mu_k    = <p_k, s_k>
-        acc[1] = fma(rti, snew, acc[1]);                   // sigma_k = <r~_k, s_k>
-        acc[2] = fma(sti, snew, acc[2]);                   // gamma_k = <s~_k, s_k>
-        acc[3] = fma(rti, ri, acc[3]);                     // nu_k    = <r~_k, r_k>
-        if (PRE) acc[4] = fma(ri, ri, acc[4]);
+        const double rn = fma(-alpha, si, ri);
+        const double wpi = fma(-alpha, ui, wi);              // w'_k = w_{k-1} - alpha u_{k-1}
+        const double snew = fma(beta, si, wpi);              // s_k = w'_k + beta s_{k-1}
+        double rti = rn, sti = snew;
+        if (PRE) {
+            rti = fma(-alpha, sti_old, rti_old);             // r~_k = r~_{k-1} - alpha s~_{k-1}
+            const double wtpi = fma(-alpha, di * ui, di * wi);  // w~'_k = w~_{k-1} - alpha u~_{k-1}
+            sti = fma(beta, sti_old, wtpi);                  // s~_k = w~'_k + beta s~_{k-1}
+        }
+        const double pnew = fma(beta, pi, rti);              // p_k = r~_k + beta p_{k-1}
+        x[i] = fma(alpha, pi, xi);
+        r[i] = rn;
+        if (PRE) {
+            rt[i] = rti;
+            stv[i] = sti;
+        }
+        p[i] = pnew;
+        s[i] = snew;
+        acc[0] = fma(pnew, snew, acc[0]);                    // mu_k    = <p_k, s_k>
+        acc[1] = fma(rti, snew, acc[1]);                     // sigma_k = <r~_k, s_k>
+        acc[2] = fma(sti, snew, acc[2]);                     // gamma_k = <s~_k, s_k>
+        acc[3] = fma(rti, rn, acc[3]);                       // nu_k    = <r~_k, r_k>
+        if (PRE) acc[4] = fma(rn, rn, acc[4]);
     }
     write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
 }
@@ -414,13 +481,20 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double acc[2] = {0.0, 0.0};
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    const double* __restrict__ p = v.p;
+    const double* __restrict__ s = v.s;
+    const double* __restrict__ d = v.d;
     for (int64_t i = i0; i < i1; i += kBlock) {
-        v.x[i] = fma(alpha, v.p[i], v.x[i]);
-        const double ri = fma(-alpha, v.s[i], v.r[i]);
-        v.r[i] = ri;
-        const double rti = PRE ? v.d[i] * ri : ri;
-        acc[0] = fma(rti, ri, acc[0]);
-        if (PRE) acc[1] = fma(ri, ri, acc[1]);
+        const double pi = p[i], si = s[i], xi = x[i], ri = r[i];
+        const double di = PRE ? d[i] : 1.0;
+        const double rn = fma(-alpha, si, ri);
+        x[i] = fma(alpha, pi, xi);
+        r[i] = rn;
+        const double rti = PRE ? di * rn : rn;
+        acc[0] = fma(rti, rn, acc[0]);
+        if (PRE) acc[1] = fma(rn, rn, acc[1]);
     }
     write_partials<2>(acc, PU, sp.Gs, blockIdx.x, lds);
 }
@@ -445,10 +519,18 @@ __global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restri
     int64_t g0, g1, i0, i1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
-    for (int64_t i = i0; i < i1; i += kBlock) {
-        const double ri = v.r[i];
-        const double rti = PRE ? v.d[i] * ri : ri;
-        v.p[i] = fma(beta, v.p[i], rti);
+    const double* __restrict__ r = v.r;
+    const double* __restrict__ d = v.d;
+    double* __restrict__ p = v.p;
+    for (int64_t i = i0; i < i1; i += 2 * kBlock) {
+        const int64_t j = i + kBlock;
+        const bool two = j < i1;
+        const int64_t jj = two ? j : i;
+        const double r0 = r[i], r1 = r[jj], p0 = p[i], p1 = p[jj];
+        const double rt0 = PRE ? d[i] * r0 : r0;
+        const double rt1 = PRE ? d[jj] * r1 : r1;
+        p[i] = fma(beta, p0, rt0);
+        if (two) p[j] = fma(beta, p1, rt1);
     }
 }
 
@@ -538,7 +620,10 @@ hipError_t with_pre(int pre, F&& f)
     return pre ? f(std::true_type{}) : f(std::false_type{});
 }
 
-SellView sell_or_empty(const SellView* s) { return s ? *s : SellView{nullptr, nullptr, nullptr, 0, 0}; }
+SellView sell_or_empty(const SellView* s)
+{
+    return s ? *s : SellView{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+}
 CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullptr, nullptr, 0}; }
 
 }  // namespace
@@ -572,20 +657,27 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     });
 }
 
-int iter_kernel_count(int variant) { return variant == kHS ? 3 : 2; }
+int iter_kernel_count(int variant, const Split& sp)
+{
+    if (variant == kHS) return 3;
+    if ((variant == kPR || variant == kM) && sp.stage2) return 3;
+    return 2;
+}
 
-const char* iter_kernel_name(int variant, int j)
+const char* iter_kernel_name(int variant, const Split& sp, int j)
 {
     switch (variant) {
     case kHS: return j == 0 ? "k_hs_xr" : (j == 1 ? "k_hs_p" : "k_hs_spmv");
     case kPR:
-    case kM: return j == 0 ? "k_pr_update" : "k_pr_spmv";
+    case kM:
+        if (sp.stage2) return j == 0 ? "k_pr_finish" : (j == 1 ? "k_pr_update" : "k_pr_spmv");
+        return j == 0 ? "k_pr_update" : "k_pr_spmv";
     default: return j == 0 ? "k_pipe_update" : "k_pipe_spmv";
     }
 }
 
 hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellView* sell, const CsrView* csr,
-                              const Split& sp, const Vecs& v, const Bufs& B, hipStream_t st)
+                              const Split& sp, const Vecs& v, const Bufs& B, hipStream_t st, const LaunchEvents* ev)
 {
     const SellView S = sell_or_empty(sell);
     const CsrView C = csr_or_empty(csr);
@@ -599,33 +691,42 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
             switch (variant) {
             case kPR:
             case kM:
-                if (j == 0) {
-                    hipLaunchKernelGGL((k_pr_update<PP>), grid, block, 0, st, sp, B.S[cur], B.S[nxt], B.hist, B.PS,
-                                       meurant, v);
+                if (sp.stage2 && j == 0) {
+                    launch(k_pr_finish<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                           (const double*)B.PS, meurant);
+                    cur = nxt;
+                } else if (sp.stage2 && j == 1) {
+                    launch(k_pr_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, meurant, v);
+                } else if (j == 0) {
+                    launch(k_pr_update<PP, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, meurant, v);
                     cur = nxt;
                 } else {
-                    hipLaunchKernelGGL((k_pr_spmv<LL, PP>), grid, block, 0, st, S, C, sp, B.S[cur], B.PS, v);
+                    launch(k_pr_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
                 }
                 break;
             case kPipePR:
             case kPipeM:
                 if (j == 0) {
-                    hipLaunchKernelGGL((k_pipe_update<PP>), grid, block, 0, st, sp, B.S[cur], B.PS, v);
+                    launch(k_pipe_update<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.PS, v);
                 } else {
-                    hipLaunchKernelGGL((k_pipe_spmv<LL, PP>), dim3(sp.G + 1), block, 0, st, S, C, sp, B.S[cur],
-                                       B.S[nxt], B.hist, B.PS, meurant, v);
+                    launch(k_pipe_spmv<LL, PP>, dim3(sp.G + 1), block, st, ev, S, C, sp, (const State*)B.S[cur],
+                           B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
                     cur = nxt;
                 }
                 break;
             default:  // HS
                 if (j == 0) {
-                    hipLaunchKernelGGL((k_hs_xr<PP>), grid, block, 0, st, sp, B.S[cur], B.S[nxt], B.PS, B.PU, v);
+                    launch(k_hs_xr<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           (const double*)B.PS, B.PU, v);
                     cur = nxt;
                 } else if (j == 1) {
-                    hipLaunchKernelGGL((k_hs_p<PP>), grid, block, 0, st, sp, B.S[cur], B.S[nxt], B.hist, B.PU, v);
+                    launch(k_hs_p<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                           (const double*)B.PU, v);
                     cur = nxt;
                 } else {
-                    hipLaunchKernelGGL((k_hs_spmv<LL>), grid, block, 0, st, S, C, sp, B.S[cur], B.PS, v);
+                    launch(k_hs_spmv<LL>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
                 }
                 break;
             }

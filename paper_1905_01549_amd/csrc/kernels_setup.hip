@@ -1,5 +1,7 @@
 // Matrix ingest kernels: CSR validation, the Jacobi diagonal, conversion to
 // the SELL-64 layout, and the sparse outer product of the adjoint.
+#include <climits>
+
 #include "prcg_device.h"
 
 namespace prcg {
@@ -59,54 +61,74 @@ __global__ void k_jacobi(int64_t n, const int32_t* __restrict__ row_ptr, const i
     }
 }
 
-// sizes[s] = 64 * (longest row of slice s).
-__global__ void k_slice_sizes(int64_t n, int64_t nslices, const int32_t* __restrict__ row_ptr,
-                              int64_t* __restrict__ sizes)
+// Slice planning, one wavefront per 64-row slice.  Each lane holds one row;
+// the union of the column offsets (col - row) of the slice is found by
+// repeatedly taking the wavefront minimum of the lanes' next offsets (rows
+// must be sorted by column).  A slice is stored offset-aligned when that
+// union has at most 1.5x the longest row and at most 64 members: slot j then
+// holds, for every row, its entry at offset union[j] or a zero.  Otherwise
+// the slice is packed: slot j holds each row's j-th entry and its column.
+// width[s] = slots of the slice; aligned[s] = 1 for offset-aligned.
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int offset_limit(int maxlen) { return min(kSlice, maxlen + maxlen / 2); }
+
+__global__ void k_slice_plan(int64_t n, int64_t nslices, const int32_t* __restrict__ row_ptr,
+                             const int32_t* __restrict__ col, int32_t* __restrict__ width,
+                             int32_t* __restrict__ aligned)
 {
     const int64_t i = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
     const int64_t s = i / kSlice;
-    int len = 0;
-    if (i < n) len = row_ptr[i + 1] - row_ptr[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-    if ((threadIdx.x & 63) == 0 && s < nslices) sizes[s] = (int64_t)kSlice * len;
-}
-
-// out[j] = sum_{i<j} in[i] for j = 0..m (out has m+1 entries); one workgroup.
-__global__ __launch_bounds__(1024) void k_exclusive_scan(const int64_t* __restrict__ in, int64_t* __restrict__ out,
-                                                         int64_t m)
-{
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (m + 1023) / 1024;
-    const int64_t lo = t * chunk, hi = lo + chunk < m ? lo + chunk : m;
-    int64_t s = 0;
-    for (int64_t j = lo; j < hi; ++j) s += in[j];
-    part[t] = s;
-    __syncthreads();
-    if (t == 0) {
-        int64_t run = 0;
-        for (int q = 0; q < 1024; ++q) {
-            const int64_t v = part[q];
-            part[q] = run;
-            run += v;
+    if (s >= nslices) return;  // whole wavefronts leave together (nslices * 64 threads are useful)
+    const int32_t a = i < n ? row_ptr[i] : 0;
+    const int32_t e = i < n ? row_ptr[i + 1] : 0;
+    const int len = e - a;
+    int sorted = 1;
+    for (int32_t q = a + 1; q < e; ++q)
+        if (col[q] <= col[q - 1]) sorted = 0;
+    const int maxlen = wave_max_i32(len);
+    const int all_sorted = wave_min_i32(sorted);
+    int slots = -1;
+    if (all_sorted && maxlen > 0) {
+        const int limit = offset_limit(maxlen);
+        int32_t q = a;
+        int count = 0;
+        for (;;) {
+            const int head = q < e ? (int)(col[q] - i) : INT_MAX;
+            const int m = wave_min_i32(head);
+            if (m == INT_MAX) break;
+            if (++count > limit) break;
+            if (head == m) ++q;
         }
-        out[m] = run;
+        if (count <= limit) slots = count;
     }
-    __syncthreads();
-    int64_t run = part[t];
-    for (int64_t j = lo; j < hi; ++j) {
-        out[j] = run;
-        run += in[j];
+    if ((threadIdx.x & 63) == 0) {
+        width[s] = slots >= 0 ? slots : maxlen;
+        aligned[s] = slots >= 0 ? 1 : 0;
     }
 }
 
-// Scatter CSR rows into SELL-64 slices; padding has value 0 and the row's
-// own index (or n-1 past the last row) as column.
+// Fill the SELL-64 storage planned above.  slice_ptr: value offsets;
+// slice_meta[s] = start of the slice's offsets in soff (aligned) or -1.
+// Packed padding has value 0 and the row's own index (n-1 past the last
+// row) as column.
 __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restrict__ row_ptr,
                             const int32_t* __restrict__ col, const double* __restrict__ val,
-                            const int64_t* __restrict__ slice_ptr, int32_t* __restrict__ scol,
-                            double* __restrict__ sval, int write_cols)
+                            const int64_t* __restrict__ slice_ptr, const int32_t* __restrict__ slice_meta,
+                            int32_t* __restrict__ soff, int32_t* __restrict__ scol, double* __restrict__ sval,
+                            int write_cols)
 {
     const int64_t i = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
     const int64_t s = i / kSlice;
@@ -115,16 +137,34 @@ __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restric
     const int64_t base = slice_ptr[s];
     const int width = (int)((slice_ptr[s + 1] - base) / kSlice);
     const int32_t a = i < n ? row_ptr[i] : 0;
-    const int len = i < n ? row_ptr[i + 1] - a : 0;
-    const int32_t pad_col = (int32_t)(i < n ? i : n - 1);
-    for (int j = 0; j < width; ++j) {
-        const int64_t pos = base + (int64_t)j * kSlice + lane;
-        if (j < len) {
-            if (write_cols) scol[pos] = col[a + j];
-            sval[pos] = val[a + j];
-        } else {
-            if (write_cols) scol[pos] = pad_col;
-            sval[pos] = 0.0;
+    const int32_t e = i < n ? row_ptr[i + 1] : 0;
+    const int meta = slice_meta[s];
+    if (meta >= 0) {
+        int32_t q = a;
+        for (int j = 0; j < width; ++j) {
+            const int head = q < e ? (int)(col[q] - i) : INT_MAX;
+            const int m = wave_min_i32(head);
+            const int64_t pos = base + (int64_t)j * kSlice + lane;
+            if (head == m) {
+                sval[pos] = val[q];
+                ++q;
+            } else {
+                sval[pos] = 0.0;
+            }
+            if (write_cols && lane == 0) soff[meta + j] = m;
+        }
+    } else {
+        const int len = e - a;
+        const int32_t pad_col = (int32_t)(i < n ? i : n - 1);
+        for (int j = 0; j < width; ++j) {
+            const int64_t pos = base + (int64_t)j * kSlice + lane;
+            if (j < len) {
+                if (write_cols) scol[pos] = col[a + j];
+                sval[pos] = val[a + j];
+            } else {
+                if (write_cols) scol[pos] = pad_col;
+                sval[pos] = 0.0;
+            }
         }
     }
 }
@@ -174,26 +214,22 @@ hipError_t launch_jacobi(int64_t n, const int32_t* row_ptr, const int32_t* col, 
     return hipGetLastError();
 }
 
-hipError_t launch_slice_sizes(int64_t n, const int32_t* row_ptr, int64_t* sizes, hipStream_t st)
+hipError_t launch_slice_plan(int64_t n, const int32_t* row_ptr, const int32_t* col, int32_t* width, int32_t* aligned,
+                             hipStream_t st)
 {
     const int64_t nslices = (n + kSlice - 1) / kSlice;
-    hipLaunchKernelGGL(k_slice_sizes, rows_grid(nslices * kSlice), dim3(kSetupBlock), 0, st, n, nslices, row_ptr,
-                       sizes);
-    return hipGetLastError();
-}
-
-hipError_t launch_exclusive_scan(const int64_t* in, int64_t* out, int64_t m, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, st, in, out, m);
+    hipLaunchKernelGGL(k_slice_plan, rows_grid(nslices * kSlice), dim3(kSetupBlock), 0, st, n, nslices, row_ptr, col,
+                       width, aligned);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_sell(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                            const int64_t* slice_ptr, int32_t* scol, double* sval, int write_cols, hipStream_t st)
+                            const int64_t* slice_ptr, const int32_t* slice_meta, int32_t* soff, int32_t* scol,
+                            double* sval, int write_cols, hipStream_t st)
 {
     const int64_t nslices = (n + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_fill_sell, rows_grid(nslices * kSlice), dim3(kSetupBlock), 0, st, n, nslices, row_ptr, col,
-                       val, slice_ptr, scol, sval, write_cols);
+                       val, slice_ptr, slice_meta, soff, scol, sval, write_cols);
     return hipGetLastError();
 }
 

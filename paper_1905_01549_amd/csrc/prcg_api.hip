@@ -74,10 +74,14 @@ struct prcg_matrix_s {
     double* val = nullptr;
     // SELL-64 layout (when lanes == 1)
     int64_t* slice_ptr = nullptr;
+    int32_t* slice_meta = nullptr;
+    int32_t* soff = nullptr;
     int32_t* scol = nullptr;
     double* sval = nullptr;
     int64_t nslices = 0;
-    int64_t stored = 0;
+    int64_t stored = 0;          // value slots, padding included
+    int64_t stored_packed = 0;   // slots of packed slices (they also read a column index)
+    int64_t noffsets = 0;        // offsets of aligned slices
     double* d = nullptr;
     Split sp{};
     // solver workspace
@@ -91,7 +95,7 @@ struct prcg_matrix_s {
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
-    SellView sell() const { return SellView{slice_ptr, scol, sval, n, nslices}; }
+    SellView sell() const { return SellView{slice_ptr, slice_meta, soff, scol, sval, n, nslices}; }
     CsrView csr() const { return CsrView{row_ptr, col, val, n}; }
     const SellView* sellp() const { return sp.lanes == 1 ? &sell_storage : nullptr; }
     const CsrView* csrp() const { return sp.lanes == 1 ? nullptr : &csr_storage; }
@@ -138,8 +142,8 @@ void free_matrix(prcg_matrix A)
         if (g) (void)hipGraphExecDestroy(g);
     for (auto& e : A->ev)
         if (e) (void)hipEventDestroy(e);
-    void* dev[] = {A->row_ptr, A->col, A->val, A->slice_ptr, A->scol, A->sval, A->d, A->vecs,
-                   A->S, A->hist, A->partials, A->dflags};
+    void* dev[] = {A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol, A->sval, A->d,
+                   A->vecs, A->S, A->hist, A->partials, A->dflags};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (A->hstate) (void)hipHostFree(A->hstate);
@@ -156,18 +160,19 @@ void invalidate_graphs(prcg_matrix A)
 }
 
 // Choose the work split: G workgroups (multiple of 8 when G >= 8, so every
-// XCD gets the same number), at most PRCG_GRID (default 1024).
+// XCD gets the same number), at most PRCG_GRID (default 1024, cap kMaxGrid).
 Split make_split(int64_t n, int lanes)
 {
     Split sp{};
     sp.n = n;
     sp.lanes = lanes;
     sp.ngroups = (n + kGroupRows - 1) / kGroupRows;
-    int gmax = std::max(8, env_int("PRCG_GRID", 1024));
+    int gmax = std::min(kMaxGrid, std::max(8, env_int("PRCG_GRID", 1024)));
     int64_t G = std::min<int64_t>(sp.ngroups, gmax);
     if (G >= 8) G -= G % 8;
     sp.G = (int)std::max<int64_t>(G, 1);
     sp.Gs = (sp.G + 63) / 64 * 64;
+    sp.stage2 = env_int("PRCG_STAGE2", 0) != 0 ? 1 : 0;
     return sp;
 }
 
@@ -200,7 +205,7 @@ prcg_status build_graph(prcg_matrix A, int variant)
     int cur = 0;
     hipError_t err = hipSuccess;
     for (int it = 0; it < kGraphIters && err == hipSuccess; ++it)
-        for (int j = 0; j < iter_kernel_count(variant) && err == hipSuccess; ++j)
+        for (int j = 0; j < iter_kernel_count(variant, A->sp) && err == hipSuccess; ++j)
             err = launch_iter_kernel(variant, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, v, B, A->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(A->capture, &g);
@@ -343,21 +348,36 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         if (hf[0] & 16) return bail(fail(PRCG_EINVAL, "Jacobi needs every diagonal entry present and > 0"));
     }
 
-    // SELL-64 sizes; keep SELL unless padding would inflate storage a lot
+    // SELL-64 plan: per-slice slot counts and layout (offset-aligned or packed)
     A->nslices = (n + kSlice - 1) / kSlice;
-    HTRY(hipMalloc(&A->slice_ptr, sizeof(int64_t) * (A->nslices + 1)));
+    std::vector<int32_t> width((size_t)A->nslices), aligned((size_t)A->nslices);
     {
-        int64_t* sizes = nullptr;
-        HTRY(hipMalloc(&sizes, sizeof(int64_t) * A->nslices));
-        hipError_t e1 = launch_slice_sizes(n, A->row_ptr, sizes, A->stream);
-        hipError_t e2 = e1 == hipSuccess ? launch_exclusive_scan(sizes, A->slice_ptr, A->nslices, A->stream) : e1;
-        hipError_t e3 = e2 == hipSuccess ? hipMemcpyAsync(&A->stored, A->slice_ptr + A->nslices, sizeof(int64_t),
-                                                          hipMemcpyDeviceToHost, A->stream)
-                                         : e2;
-        hipError_t e4 = e3 == hipSuccess ? hipStreamSynchronize(A->stream) : e3;
-        (void)hipFree(sizes);
-        HTRY(e4);
+        int32_t* dplan = nullptr;
+        HTRY(hipMalloc(&dplan, sizeof(int32_t) * 2 * A->nslices));
+        hipError_t e1 = launch_slice_plan(n, A->row_ptr, A->col, dplan, dplan + A->nslices, A->stream);
+        if (e1 == hipSuccess)
+            e1 = hipMemcpyAsync(width.data(), dplan, sizeof(int32_t) * A->nslices, hipMemcpyDeviceToHost, A->stream);
+        if (e1 == hipSuccess)
+            e1 = hipMemcpyAsync(aligned.data(), dplan + A->nslices, sizeof(int32_t) * A->nslices,
+                                hipMemcpyDeviceToHost, A->stream);
+        if (e1 == hipSuccess) e1 = hipStreamSynchronize(A->stream);
+        (void)hipFree(dplan);
+        HTRY(e1);
     }
+    std::vector<int64_t> hptr((size_t)A->nslices + 1);
+    std::vector<int32_t> hmeta((size_t)A->nslices);
+    hptr[0] = 0;
+    for (int64_t q = 0; q < A->nslices; ++q) {
+        hptr[q + 1] = hptr[q] + (int64_t)kSlice * width[q];
+        if (aligned[q]) {
+            hmeta[q] = (int32_t)A->noffsets;
+            A->noffsets += width[q];
+        } else {
+            hmeta[q] = -1;
+            A->stored_packed += (int64_t)kSlice * width[q];
+        }
+    }
+    A->stored = hptr[A->nslices];
     int lanes = 1;
     const char* fmt = std::getenv("PRCG_FORMAT");
     const double mean = (double)nnz / (double)n;
@@ -365,13 +385,23 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         lanes = std::atoi(fmt + 3);
         if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) lanes = 8;
     } else if (!(fmt && std::strcmp(fmt, "sell") == 0)) {
+        // vector CSR when padding would inflate the SELL storage or rows are long
         const bool sell_ok = (double)A->stored <= 1.5 * (double)nnz + 64.0 * (double)A->nslices && maxlen <= 256;
         if (!sell_ok) lanes = mean >= 96 ? 64 : mean >= 48 ? 32 : mean >= 24 ? 16 : 8;
     }
     if (lanes == 1) {
+        HTRY(hipMalloc(&A->slice_ptr, sizeof(int64_t) * (A->nslices + 1)));
+        HTRY(hipMalloc(&A->slice_meta, sizeof(int32_t) * A->nslices));
+        HTRY(hipMalloc(&A->soff, sizeof(int32_t) * std::max<int64_t>(A->noffsets, 1)));
         HTRY(hipMalloc(&A->scol, sizeof(int32_t) * std::max<int64_t>(A->stored, 1)));
         HTRY(hipMalloc(&A->sval, sizeof(double) * std::max<int64_t>(A->stored, 1)));
-        HTRY(launch_fill_sell(n, A->row_ptr, A->col, A->val, A->slice_ptr, A->scol, A->sval, 1, A->stream));
+        HTRY(hipMemcpyAsync(A->slice_ptr, hptr.data(), sizeof(int64_t) * (A->nslices + 1), hipMemcpyHostToDevice,
+                            A->stream));
+        HTRY(hipMemcpyAsync(A->slice_meta, hmeta.data(), sizeof(int32_t) * A->nslices, hipMemcpyHostToDevice,
+                            A->stream));
+        HTRY(launch_fill_sell(n, A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol, A->sval,
+                              1, A->stream));
+        HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
     }
     A->sp = make_split(n, lanes);
     A->sell_storage = A->sell();
@@ -405,7 +435,8 @@ prcg_status prcg_set_values(prcg_matrix A, const double* values)
     if (A->nnz > 0)
         HIP_TRY(hipMemcpyAsync(A->val, values, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, A->stream));
     if (A->sp.lanes == 1)
-        HIP_TRY(launch_fill_sell(A->n, A->row_ptr, A->col, A->val, A->slice_ptr, A->scol, A->sval, 0, A->stream));
+        HIP_TRY(launch_fill_sell(A->n, A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol,
+                                 A->sval, 0, A->stream));
     if (A->precond == PRCG_PRECOND_JACOBI) {
         HIP_TRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), A->stream));
         HIP_TRY(launch_jacobi(A->n, A->row_ptr, A->col, A->val, A->d, A->dflags, A->stream));
@@ -459,8 +490,14 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
     props->stored_entries = A->sp.lanes == 1 ? A->stored : A->nnz;
     props->grid = A->sp.G;
     props->block = kBlock;
-    props->matrix_bytes = A->sp.lanes == 1 ? 12 * A->stored + 8 * (A->nslices + 1)
-                                           : 12 * A->nnz + 4 * (A->n + 1);
+    // bytes one product reads: values, the column indices of packed slices,
+    // the offsets of aligned slices and the per-slice metadata
+    props->matrix_bytes = A->sp.lanes == 1
+                              ? 8 * A->stored + 4 * A->stored_packed + 4 * A->noffsets + 12 * A->nslices + 8
+                              : 12 * A->nnz + 4 * (A->n + 1);
+    props->aligned_slices_frac = 0.0;
+    if (A->sp.lanes == 1 && A->nslices > 0)
+        props->aligned_slices_frac = 1.0 - (double)A->stored_packed / (double)std::max<int64_t>(A->stored, 1);
     return PRCG_OK;
 }
 
@@ -476,7 +513,7 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
     const Vecs vv = A->vecs_view();
     const Bufs B = A->bufs();
     // right-hand side: the spare vector filled with ones; x0 = 0 (vector x)
-    const int nk = iter_kernel_count(v);
+    const int nk = iter_kernel_count(v, A->sp);
     std::vector<double> ones((size_t)A->n, 1.0);
     double* bvec = A->spare();
     HIP_TRY(hipMemcpyAsync(bvec, ones.data(), sizeof(double) * A->n, hipMemcpyHostToDevice, A->stream));
@@ -489,10 +526,8 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
     for (int it = 0; it < iters && err == hipSuccess; ++it)
         for (int j = 0; j < nk && err == hipSuccess; ++j) {
             const size_t q = (size_t)2 * (it * nk + j);
-            err = hipEventRecord(ev[q], A->stream);
-            if (err == hipSuccess)
-                err = launch_iter_kernel(v, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, vv, B, A->stream);
-            if (err == hipSuccess) err = hipEventRecord(ev[q + 1], A->stream);
+            const LaunchEvents le{ev[q], ev[q + 1]};
+            err = launch_iter_kernel(v, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, vv, B, A->stream, &le);
         }
     if (err == hipSuccess) err = hipStreamSynchronize(A->stream);
     std::vector<double> tot((size_t)nk, 0.0);
@@ -513,7 +548,7 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
     for (int j = 0; j < nk; ++j) {
         ms_per_launch[j] = tot[j] / iters;
         if (names) {
-            std::snprintf(names[j], 48, "%s", iter_kernel_name(v, j));
+            std::snprintf(names[j], 48, "%s", iter_kernel_name(v, A->sp, j));
         }
     }
     return PRCG_OK;

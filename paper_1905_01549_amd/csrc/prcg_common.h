@@ -12,6 +12,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kSlice = 64;      // SELL slice height: one wavefront, one row per lane
 constexpr int kGroupRows = kBlock;  // rows handled by one workgroup step (4 slices)
 constexpr int kMaxDots = 5;
+constexpr int kMaxGrid = 1024;  // largest workgroup count of the row-parallel kernels
 
 enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4 };
 enum Status { kOK = 0, kNotConverged = 1, kBreakdown = 2 };
@@ -38,12 +39,17 @@ struct alignas(128) State {
     int32_t pad[2];
 };
 
-// SELL-64 matrix: rows are cut into slices of 64; slice s stores its
-// entries column-major, entry j of row 64 s + l at slice_ptr[s] + 64 j + l.
-// Rows shorter than the slice width are padded with value 0 and their own
-// row index as column.
+// SELL-64 matrix: rows are cut into slices of 64 (one wavefront, one row
+// per lane); slice s stores its slots column-major, slot j of row 64 s + l
+// at slice_ptr[s] + 64 j + l.  An offset-aligned slice (slice_meta[s] >= 0)
+// stores no column indices: slot j of row r holds the entry at column
+// r + soff[slice_meta[s] + j] or a zero.  A packed slice (slice_meta[s] < 0)
+// holds each row's j-th entry in slot j with its column in col; short rows
+// are padded with zeros whose column is the row itself.
 struct SellView {
-    const int64_t* slice_ptr;  // [nslices + 1]
+    const int64_t* slice_ptr;   // [nslices + 1]
+    const int32_t* slice_meta;  // [nslices]
+    const int32_t* soff;
     const int32_t* col;
     const double* val;
     int64_t n;
@@ -67,6 +73,8 @@ struct Split {
     int Gs;         // stride between reduction values in a partials buffer
     int64_t ngroups;
     int lanes;      // 1 = SELL-64, else lanes per row of vector CSR
+    int stage2;     // PR/M: 0 = every update workgroup reduces the partials,
+                    // 1 = a one-workgroup kernel reduces them before the update
 };
 
 // ---- setup kernels (kernels_setup.hip) ----
@@ -74,11 +82,11 @@ hipError_t launch_validate(int64_t n, int64_t nnz, const int32_t* row_ptr, const
                            int32_t* flags, int32_t* maxlen, hipStream_t st);
 hipError_t launch_jacobi(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                          double* d, int32_t* flags, hipStream_t st);
-hipError_t launch_slice_sizes(int64_t n, const int32_t* row_ptr, int64_t* sizes, hipStream_t st);
-hipError_t launch_exclusive_scan(const int64_t* in, int64_t* out, int64_t m, hipStream_t st);
+hipError_t launch_slice_plan(int64_t n, const int32_t* row_ptr, const int32_t* col, int32_t* width,
+                             int32_t* aligned, hipStream_t st);
 hipError_t launch_fill_sell(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                            const int64_t* slice_ptr, int32_t* scol, double* sval, int write_cols,
-                            hipStream_t st);
+                            const int64_t* slice_ptr, const int32_t* slice_meta, int32_t* soff, int32_t* scol,
+                            double* sval, int write_cols, hipStream_t st);
 hipError_t launch_block_check(int64_t n, const int32_t* row_ptr, const int32_t* col,
                               const int32_t* row_sys, const int64_t* sys_off, int32_t* flags, hipStream_t st);
 hipError_t launch_outer_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* lam,
@@ -105,11 +113,16 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
                        int32_t maxit, hipStream_t st);
 // Number of kernels per iteration and their launch; `cur` is the state copy
 // that holds the current state and is updated.
-int iter_kernel_count(int variant);
-const char* iter_kernel_name(int variant, int j);
+int iter_kernel_count(int variant, const Split& sp);
+const char* iter_kernel_name(int variant, const Split& sp, int j);
+// Optional dispatch timestamps for one launch.
+struct LaunchEvents {
+    hipEvent_t start;
+    hipEvent_t stop;
+};
 hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellView* sell,
                               const CsrView* csr, const Split& sp, const Vecs& v, const Bufs& B,
-                              hipStream_t st);
+                              hipStream_t st, const LaunchEvents* ev = nullptr);
 hipError_t launch_final(const SellView* sell, const CsrView* csr, const Split& sp, const Vecs& v,
                         const Bufs& B, int cur, const double* b, double* xout, hipStream_t st);
 

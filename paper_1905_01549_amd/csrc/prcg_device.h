@@ -41,17 +41,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* kWaves
 }
 
 // Stage 2 of a reduction: the G per-workgroup partials of each of NV values
-// (value i at P[i * Gs + g]) are summed in a fixed order.  Every thread of
-// the calling workgroup receives the totals.
+// (value i at P[i * Gs + g], G <= kMaxGrid) are summed in a fixed order.
+// Every thread of the calling workgroup receives the totals.  All loads are
+// issued before the first addition so the cost is one memory latency.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
                                                 double* lds)
 {
+    constexpr int kPer = kMaxGrid / kBlock;
+    double buf[NV][kPer];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) tot[i] = 0.0;
-    for (int g = threadIdx.x; g < G; g += kBlock) {
+    for (int j = 0; j < kPer; ++j) {
+        const int g = threadIdx.x + j * kBlock;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) tot[i] += P[i * Gs + g];
+        for (int i = 0; i < NV; ++i) buf[i][j] = g < G ? P[i * Gs + g] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = buf[i][0];
+#pragma unroll
+        for (int j = 1; j < kPer; ++j) t += buf[i][j];
+        tot[i] = t;
     }
     block_sum<NV>(tot, lds);
 }
@@ -78,22 +88,39 @@ __device__ __forceinline__ void chunk_of(int b, int G, int64_t ngroups, int64_t&
     g1 = (int64_t)(c + 1) * ngroups / G;
 }
 
-// Products of one SELL-64 row with NX vectors (entries summed in stored order).
+// Products of one SELL-64 row with NX vectors (entries summed in stored
+// column order; zero slots add nothing).
 template <int NX>
 __device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, const double* __restrict__ x0,
                                          const double* __restrict__ x1, double& y0, double& y1)
 {
     const int64_t base = A.slice_ptr[slice];
     const int width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
-    const int32_t* __restrict__ c = A.col + base + lane;
+    const int meta = A.slice_meta[slice];
     const double* __restrict__ v = A.val + base + lane;
     double a0 = 0.0, a1 = 0.0;
+    if (meta >= 0) {
+        // offset-aligned: the column is row + offset, clamped into [0, n) so
+        // that zero slots of boundary rows read a valid entry
+        const int row = (int)(slice * kSlice + lane);
+        const int last = (int)A.n - 1;
+        const int32_t* __restrict__ off = A.soff + meta;
 #pragma unroll 4
-    for (int j = 0; j < width; ++j) {
-        const int cj = c[(int64_t)j * 64];
-        const double vj = v[(int64_t)j * 64];
-        a0 = fma(vj, x0[cj], a0);
-        if (NX == 2) a1 = fma(vj, x1[cj], a1);
+        for (int j = 0; j < width; ++j) {
+            const int cj = min(max(row + off[j], 0), last);
+            const double vj = v[(int64_t)j * 64];
+            a0 = fma(vj, x0[cj], a0);
+            if (NX == 2) a1 = fma(vj, x1[cj], a1);
+        }
+    } else {
+        const int32_t* __restrict__ c = A.col + base + lane;
+#pragma unroll 4
+        for (int j = 0; j < width; ++j) {
+            const int cj = c[(int64_t)j * 64];
+            const double vj = v[(int64_t)j * 64];
+            a0 = fma(vj, x0[cj], a0);
+            if (NX == 2) a1 = fma(vj, x1[cj], a1);
+        }
     }
     y0 = a0;
     y1 = a1;

@@ -43,7 +43,8 @@ class prcg_info(ctypes.Structure):
 class prcg_matrix_props(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("stored_entries", ctypes.c_int64),
                 ("format", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64)]
+                ("block", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
+                ("aligned_slices_frac", ctypes.c_double)]
 
 
 _VP = ctypes.c_void_p

@@ -82,6 +82,10 @@ SPMV_CASES = {
     "model_dense_48": lambda: P.model_dense(48, 0.8, 1e3, 0),
     "arrowhead_5000_long_row": lambda: P.arrowhead(5000, 2),
     "single_row": lambda: P.diagonal_csr(np.array([2.5])),
+    "empty_rows": lambda: P.CSR(5, np.array([0, 1, 1, 3, 3, 4], dtype=np.int32),
+                                np.array([0, 2, 4, 4], dtype=np.int32), np.array([1.0, 2.0, 3.0, 4.0])),
+    "unsorted_rows": lambda: P.CSR(3, np.array([0, 2, 3, 5], dtype=np.int32),
+                                   np.array([1, 0, 1, 2, 0], dtype=np.int32), np.array([1.0, 2.0, 3.0, 4.0, 5.0])),
 }
 
 
@@ -90,6 +94,10 @@ def test_spmv_matches_oracle(prcg, torch_cuda, case):
     A = SPMV_CASES[case]()
     x = np.random.default_rng(1).uniform(-1, 1, A.n)
     M = gpu_matrix(prcg, A)
+    if case.startswith(("poisson", "varcoef")):
+        assert M.props.aligned_slices_frac == 1.0  # stencils: offsets shared within every slice
+    if case.startswith("random"):
+        assert M.props.aligned_slices_frac == 0.0
     y = M.spmv(x).cpu().numpy()
     yo = oracle.spmv(A.row_ptr, A.col_idx, A.values, x)
     lens = np.diff(A.row_ptr)
