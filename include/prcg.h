@@ -187,11 +187,24 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props);
 prcg_status prcg_create_batch(prcg_matrix blockdiag, int32_t nsys, const int64_t* sys_row_offset,
                               prcg_batch* out);
 
-/* Solve every system of the batch with variant v (PR or HS), same
- * semantics per system as prcg_solve.  b, x: device float64[n].
- * iters, status: host int32[nsys], nullable. */
+/* Solve every system of the batch with variant v, same semantics per system
+ * as prcg_solve (the matrix handle's preconditioner applies).  b, x: device
+ * float64[n]; x holds x_0 on entry.  iters, status: host int32[nsys],
+ * nullable.  Returns the largest per-system status (OK < NOT_CONVERGED <
+ * BREAKDOWN).  The first call with a variant runs the autotuner: a few
+ * iterations of every system under each candidate launch shape (threads per
+ * workgroup x workgroups per compute unit), timed with HIP events; the
+ * fastest is kept for the batch.  The persistent launch is captured in a
+ * HIP graph.  Reductions are deterministic for a fixed configuration. */
 prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, double* x, double tol,
                                int32_t maxit, int32_t* iters, int32_t* status);
+
+/* The configuration the batched solver's autotuner chose for variant v
+ * (0, 0 before the first prcg_solve_batched with that variant): threads per
+ * workgroup (64 per wavefront) and workgroups of the persistent launch.
+ * The environment variable PRCG_BATCH_CONFIG="threads,per_cu" (threads in
+ * 256/512/1024, 1 <= per_cu <= 8) fixes it instead. */
+prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, int32_t* grid);
 
 /*
  * Adjoint of a solve (not in the paper): for L(x) with x = A^{-1} b and

@@ -1,0 +1,263 @@
+// Batched solve: many independent systems (one block-diagonal matrix) in one
+// persistent launch.  Not part of the paper; each system runs exactly the
+// single-system algorithm (Alg. 1, Alg. 2 or Alg. 3 with the initialisation of
+// Appendix D, same tests and scalar step), but inside one workgroup:
+// every reduction is a workgroup reduction (wavefront butterfly + LDS, fixed
+// order), and the kernel boundaries of the single-system path become
+// workgroup barriers.  No grid-wide synchronisation is needed because
+// systems are independent.
+//
+// Work distribution: workgroups take systems from a queue (an atomic
+// counter over a largest-first order) until it is empty; every workgroup
+// leaves once the counter passes the number of systems.
+#include "batched.h"
+#include "prcg_device.h"
+
+namespace prcg {
+
+namespace {
+
+// Calls f(row, y0, y1) for every row of the system's slices [sl0, sl1):
+// wavefront w takes slices sl0 + w, sl0 + w + NW, ...
+template <int NT, int NX, class F>
+__device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_t sl1, const double* __restrict__ x0,
+                                         const double* __restrict__ x1, F&& f)
+{
+    constexpr int NW = NT / 64;
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int64_t sl = sl0 + w; sl < sl1; sl += NW) {
+        const int64_t row = B.slice_row0[sl] + lane;
+        const bool valid = lane < B.slice_nrows[sl];
+        double y0, y1;
+        sell_row<NX>(B.A, sl, lane, row, x0, x1, y0, y1);
+        if (valid) f(row, y0, y1);
+    }
+}
+
+template <int NT, bool PRE, int KIND>
+__device__ void solve_system(const BatchView& B, const Vecs& v, const double* __restrict__ b, double tol,
+                             int maxit, int meurant, int sys, int32_t* __restrict__ iters_out,
+                             int32_t* __restrict__ status_out, double* lds)
+{
+    constexpr int NW = NT / 64;
+    const int64_t r0 = B.sys_row0[sys], r1 = B.sys_row0[sys + 1];
+    const int64_t sl0 = B.sys_slice0[sys], sl1 = B.sys_slice0[sys + 1];
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    double* __restrict__ rt = v.rt;
+    double* __restrict__ p = v.p;
+    double* __restrict__ s = v.s;
+    double* __restrict__ stv = v.st;
+    double* __restrict__ w = v.w;
+    double* __restrict__ u = v.u;
+    const double* __restrict__ d = v.d;
+
+    // ---- initialize (Appendix D): r0 = b - A x0, r~0 = M^{-1} r0, p0 = r~0
+    double bb[1] = {0.0};
+    sys_spmv<NT, 1>(B, sl0, sl1, x, nullptr, [&](int64_t i, double ax, double) {
+        const double bi = b[i];
+        const double ri = bi - ax;
+        r[i] = ri;
+        const double rti = PRE ? d[i] * ri : ri;
+        if (PRE && KIND != 0) rt[i] = rti;
+        p[i] = rti;
+        bb[0] = fma(bi, bi, bb[0]);
+    });
+    __syncthreads();
+    // s0 = A p0 and mu0, sigma0, gamma0, nu0, <r0, r0>, <b, b>
+    double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, bb[0]};
+    sys_spmv<NT, 1>(B, sl0, sl1, p, nullptr, [&](int64_t i, double si, double) {
+        s[i] = si;
+        const double ri = r[i];
+        const double di = PRE ? d[i] : 1.0;
+        const double sti = PRE ? di * si : si;
+        const double rti = PRE ? di * ri : ri;
+        if (PRE && KIND == 2) stv[i] = sti;
+        t[0] = fma(p[i], si, t[0]);
+        t[1] = fma(rti, si, t[1]);
+        t[2] = fma(sti, si, t[2]);
+        t[3] = fma(rti, ri, t[3]);
+        t[4] = fma(ri, ri, t[4]);
+    });
+    block_sum<6, NW>(t, lds);
+    State st = {};
+    st.bnorm = sqrt(t[5]);
+    st.tol = tol;
+    st.maxit = maxit;
+    st.k = -1;
+    st.status = kNotConverged;
+    if (t[5] == 0.0) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) x[i] = 0.0;
+        st.k = 0;
+        st.status = kOK;
+        st.done = 1;
+    } else if (KIND == 0) {
+        step_hs_nu(st, t[3], PRE ? t[4] : t[3], nullptr, false);
+        if (!st.done) step_hs_mu(st, t[0]);
+    } else {
+        double t5[5] = {t[0], t[1], t[2], t[3], t[4]};
+        if (KIND == 2) {
+            // w0 = A r~0 = s0; u0 = A s~0
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) w[i] = s[i];
+            sys_spmv<NT, 1>(B, sl0, sl1, PRE ? stv : s, nullptr, [&](int64_t i, double ui, double) { u[i] = ui; });
+            __syncthreads();
+        }
+        step_one_reduction(st, t5, PRE, meurant != 0, nullptr, false);
+    }
+
+    while (!st.done) {
+        const double alpha = st.alpha, beta = st.beta;
+        if (KIND == 1) {
+            // Alg. 2: vector updates, then s = A p and the four (five) inner products
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+                const double si = s[i], pi = p[i], xi = x[i], ri = r[i];
+                const double rn = fma(-alpha, si, ri);
+                const double rtn = PRE ? fma(-alpha, d[i] * si, rt[i]) : rn;
+                x[i] = fma(alpha, pi, xi);
+                r[i] = rn;
+                if (PRE) rt[i] = rtn;
+                p[i] = fma(beta, pi, rtn);
+            }
+            __syncthreads();
+            double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            sys_spmv<NT, 1>(B, sl0, sl1, p, nullptr, [&](int64_t i, double si, double) {
+                s[i] = si;
+                const double ri = r[i];
+                const double rti = PRE ? rt[i] : ri;
+                const double sti = PRE ? d[i] * si : si;
+                q[0] = fma(p[i], si, q[0]);
+                q[1] = fma(rti, si, q[1]);
+                q[2] = fma(sti, si, q[2]);
+                q[3] = fma(rti, ri, q[3]);
+                if (PRE) q[4] = fma(ri, ri, q[4]);
+            });
+            block_sum<5, NW>(q, lds);
+            step_one_reduction(st, q, PRE, meurant != 0, nullptr, false);
+        } else if (KIND == 2) {
+            // Alg. 3: all vector updates and the inner products in one pass
+            double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+                const double pi = p[i], si = s[i], wi = w[i], ui = u[i], xi = x[i], ri = r[i];
+                const double rn = fma(-alpha, si, ri);
+                const double wpi = fma(-alpha, ui, wi);
+                const double snew = fma(beta, si, wpi);
+                double rti = rn, sti = snew;
+                if (PRE) {
+                    const double di = d[i], sto = stv[i];
+                    rti = fma(-alpha, sto, rt[i]);
+                    sti = fma(beta, sto, fma(-alpha, di * ui, di * wi));
+                    rt[i] = rti;
+                    stv[i] = sti;
+                }
+                const double pnew = fma(beta, pi, rti);
+                x[i] = fma(alpha, pi, xi);
+                r[i] = rn;
+                p[i] = pnew;
+                s[i] = snew;
+                q[0] = fma(pnew, snew, q[0]);
+                q[1] = fma(rti, snew, q[1]);
+                q[2] = fma(sti, snew, q[2]);
+                q[3] = fma(rti, rn, q[3]);
+                if (PRE) q[4] = fma(rn, rn, q[4]);
+            }
+            block_sum<5, NW>(q, lds);  // its barriers also publish the updated vectors
+            step_one_reduction(st, q, PRE, meurant != 0, nullptr, false);
+            if (st.done) break;
+            // u = A s~, w = A r~ (one pass over the system's matrix)
+            sys_spmv<NT, 2>(B, sl0, sl1, PRE ? stv : s, PRE ? rt : r, [&](int64_t i, double ui, double wi) {
+                u[i] = ui;
+                w[i] = wi;
+            });
+            __syncthreads();
+        } else {
+            // Alg. 1: x, r, nu; then beta and p; then s = A p and mu
+            double q[2] = {0.0, 0.0};
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+                const double rn = fma(-alpha, s[i], r[i]);
+                x[i] = fma(alpha, p[i], x[i]);
+                r[i] = rn;
+                const double rti = PRE ? d[i] * rn : rn;
+                q[0] = fma(rti, rn, q[0]);
+                if (PRE) q[1] = fma(rn, rn, q[1]);
+            }
+            block_sum<2, NW>(q, lds);
+            step_hs_nu(st, q[0], PRE ? q[1] : q[0], nullptr, false);
+            if (st.done) break;
+            const double bk = st.beta;
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+                const double ri = r[i];
+                p[i] = fma(bk, p[i], PRE ? d[i] * ri : ri);
+            }
+            __syncthreads();
+            double m[1] = {0.0};
+            sys_spmv<NT, 1>(B, sl0, sl1, p, nullptr, [&](int64_t i, double si, double) {
+                s[i] = si;
+                m[0] = fma(p[i], si, m[0]);
+            });
+            block_sum<1, NW>(m, lds);
+            step_hs_mu(st, m[0]);
+        }
+    }
+    if (threadIdx.x == 0) {
+        iters_out[sys] = st.k < 0 ? 0 : st.k;
+        status_out[sys] = st.status;
+    }
+    __syncthreads();
+}
+
+template <int NT, bool PRE, int KIND>
+__global__ __launch_bounds__(NT) void k_batch(BatchView B, Vecs v, const double* __restrict__ b, double tol,
+                                              int maxit, int meurant, int32_t* __restrict__ queue,
+                                              int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out)
+{
+    __shared__ double lds[(NT / 64) * 6];
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int q = s_next;
+        __syncthreads();
+        if (q >= B.nsys) return;  // the queue only grows: every workgroup reaches this
+        solve_system<NT, PRE, KIND>(B, v, b, tol, maxit, meurant, B.order[q], iters_out, status_out, lds);
+    }
+}
+
+__global__ void k_batch_reset(int32_t* queue) { *queue = 0; }
+
+template <int NT, class F>
+hipError_t with_kind(int kind, int pre, F&& f)
+{
+    auto go = [&](auto P) -> hipError_t {
+        switch (kind) {
+        case 0: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 0>{});
+        case 1: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 1>{});
+        default: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 2>{});
+        }
+    };
+    return pre ? go(std::true_type{}) : go(std::false_type{});
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchView& B, const Vecs& v, const double* b, double tol, int maxit, int variant,
+                        int pre, int nt, int grid, int32_t* queue, int32_t* iters, int32_t* status, hipStream_t st)
+{
+    const int kind = variant == kHS ? 0 : (variant == kPR || variant == kM) ? 1 : 2;
+    const int meurant = variant == kM || variant == kPipeM;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, queue);
+    auto body = [&](auto NTc, auto P, auto Kc) -> hipError_t {
+        constexpr int T = decltype(NTc)::value;
+        hipLaunchKernelGGL((k_batch<T, decltype(P)::value, decltype(Kc)::value>), dim3(grid), dim3(T), 0, st, B, v, b,
+                           tol, maxit, meurant, queue, iters, status);
+        return hipGetLastError();
+    };
+    switch (nt) {
+    case 256: return with_kind<256>(kind, pre, body);
+    case 512: return with_kind<512>(kind, pre, body);
+    case 1024: return with_kind<1024>(kind, pre, body);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace prcg

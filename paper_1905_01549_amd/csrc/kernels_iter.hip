@@ -46,95 +46,6 @@ void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, const LaunchEvents*
         hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
 }
 
-__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
-
-// The scalar step after the reduction of iteration k of a one-reduction
-// variant (PR, M, pipe-PR, pipe-M): record ||r_k||, test convergence and
-// breakdown, then form alpha_k, nu'_{k+1} and beta_{k+1} (Alg. 2 / Alg. 3,
-// eq. nuk_simplified; Meurant: nu' = -nu + alpha^2 gamma).
-__device__ void step_one_reduction(State& st, const double (&t)[5], bool pre, bool meurant, double* hist,
-                                   bool writer)
-{
-    const double mu = t[0], sigma = t[1], gamma = t[2], nu = t[3];
-    const double rr = pre ? t[4] : nu;
-    const int k = st.k + 1;
-    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
-    if (writer) hist[k] = rnorm / st.bnorm;
-    st.k = k;
-    st.nu = nu;
-    st.mu = mu;
-    st.sigma = sigma;
-    st.gamma = gamma;
-    st.rr = rr;
-    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
-        st.done = 1;
-        st.status = kOK;
-        return;
-    }
-    if (st.last || !finite(nu) || !finite(mu) || !finite(rr) || !(nu > 0.0) || !(mu > 0.0)) {
-        st.done = 1;
-        st.status = kBreakdown;
-        return;
-    }
-    if (k == st.maxit) {
-        st.done = 1;
-        st.status = kNotConverged;
-        return;
-    }
-    const double alpha = nu / mu;
-    const double nup = meurant ? -nu + alpha * alpha * gamma : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
-    st.alpha = alpha;
-    st.nup = nup;
-    if (!finite(nup) || !(nup > 0.0)) {
-        st.last = 1;  // the next iteration's x and r updates are still taken
-        st.beta = 0.0;
-    } else {
-        st.beta = nup / nu;
-    }
-}
-
-// HS-CG after the reduction of nu_k (Alg. 1): record ||r_k||, test, beta_k.
-__device__ void step_hs_nu(State& st, double nu, double rr, double* hist, bool writer)
-{
-    const int k = st.k + 1;
-    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
-    if (writer) hist[k] = rnorm / st.bnorm;
-    st.k = k;
-    st.rr = rr;
-    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
-        st.done = 1;
-        st.status = kOK;
-        st.nu = nu;
-        return;
-    }
-    if (!finite(nu) || !finite(rr) || !(nu > 0.0)) {
-        st.done = 1;
-        st.status = kBreakdown;
-        st.nu = nu;
-        return;
-    }
-    if (k == st.maxit) {
-        st.done = 1;
-        st.status = kNotConverged;
-        st.nu = nu;
-        return;
-    }
-    if (k > 0) st.beta = nu / st.nu;  // beta_k = nu_k / nu_{k-1}
-    st.nu = nu;
-}
-
-// HS-CG after the reduction of mu_k: alpha_k = nu_k / mu_k.
-__device__ void step_hs_mu(State& st, double mu)
-{
-    st.mu = mu;
-    if (!finite(mu) || !(mu > 0.0)) {
-        st.done = 1;
-        st.status = kBreakdown;
-        return;
-    }
-    st.alpha = st.nu / mu;
-}
-
 __device__ __forceinline__ bool writer_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 // ------------------------------------------------------------------ init

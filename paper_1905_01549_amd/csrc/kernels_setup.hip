@@ -85,15 +85,28 @@ __device__ __forceinline__ int wave_max_i32(int v)
 
 __device__ __forceinline__ int offset_limit(int maxlen) { return min(kSlice, maxlen + maxlen / 2); }
 
+// Row of lane `lane` of slice s: 64 s + lane, or row0[s] + lane when the
+// slices follow a geometry of their own (batched systems); rows past the
+// slice's end are marked -1.
+__device__ __forceinline__ int64_t slice_lane_row(int64_t s, int lane, int64_t n, const int64_t* row0,
+                                                  const int32_t* nrows)
+{
+    if (row0) return lane < nrows[s] ? row0[s] + lane : -1;
+    const int64_t i = s * kSlice + lane;
+    return i < n ? i : -1;
+}
+
 __global__ void k_slice_plan(int64_t n, int64_t nslices, const int32_t* __restrict__ row_ptr,
-                             const int32_t* __restrict__ col, int32_t* __restrict__ width,
+                             const int32_t* __restrict__ col, const int64_t* __restrict__ row0,
+                             const int32_t* __restrict__ nrows, int32_t* __restrict__ width,
                              int32_t* __restrict__ aligned)
 {
-    const int64_t i = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
-    const int64_t s = i / kSlice;
+    const int64_t t = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
+    const int64_t s = t / kSlice;
     if (s >= nslices) return;  // whole wavefronts leave together (nslices * 64 threads are useful)
-    const int32_t a = i < n ? row_ptr[i] : 0;
-    const int32_t e = i < n ? row_ptr[i + 1] : 0;
+    const int64_t i = slice_lane_row(s, (int)(t % kSlice), n, row0, nrows);
+    const int32_t a = i >= 0 ? row_ptr[i] : 0;
+    const int32_t e = i >= 0 ? row_ptr[i + 1] : 0;
     const int len = e - a;
     int sorted = 1;
     for (int32_t q = a + 1; q < e; ++q)
@@ -126,18 +139,20 @@ __global__ void k_slice_plan(int64_t n, int64_t nslices, const int32_t* __restri
 // row) as column.
 __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restrict__ row_ptr,
                             const int32_t* __restrict__ col, const double* __restrict__ val,
+                            const int64_t* __restrict__ row0, const int32_t* __restrict__ nrows,
                             const int64_t* __restrict__ slice_ptr, const int32_t* __restrict__ slice_meta,
                             int32_t* __restrict__ soff, int32_t* __restrict__ scol, double* __restrict__ sval,
                             int write_cols)
 {
-    const int64_t i = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
-    const int64_t s = i / kSlice;
+    const int64_t t = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
+    const int64_t s = t / kSlice;
     if (s >= nslices) return;
-    const int lane = (int)(i % kSlice);
+    const int lane = (int)(t % kSlice);
+    const int64_t i = slice_lane_row(s, lane, n, row0, nrows);
     const int64_t base = slice_ptr[s];
     const int width = (int)((slice_ptr[s + 1] - base) / kSlice);
-    const int32_t a = i < n ? row_ptr[i] : 0;
-    const int32_t e = i < n ? row_ptr[i + 1] : 0;
+    const int32_t a = i >= 0 ? row_ptr[i] : 0;
+    const int32_t e = i >= 0 ? row_ptr[i + 1] : 0;
     const int meta = slice_meta[s];
     if (meta >= 0) {
         int32_t q = a;
@@ -155,7 +170,7 @@ __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restric
         }
     } else {
         const int len = e - a;
-        const int32_t pad_col = (int32_t)(i < n ? i : n - 1);
+        const int32_t pad_col = (int32_t)(i >= 0 ? i : n - 1);
         for (int j = 0; j < width; ++j) {
             const int64_t pos = base + (int64_t)j * kSlice + lane;
             if (j < len) {
@@ -214,22 +229,22 @@ hipError_t launch_jacobi(int64_t n, const int32_t* row_ptr, const int32_t* col, 
     return hipGetLastError();
 }
 
-hipError_t launch_slice_plan(int64_t n, const int32_t* row_ptr, const int32_t* col, int32_t* width, int32_t* aligned,
+hipError_t launch_slice_plan(int64_t n, int64_t nslices, const int32_t* row_ptr, const int32_t* col,
+                             const int64_t* row0, const int32_t* nrows, int32_t* width, int32_t* aligned,
                              hipStream_t st)
 {
-    const int64_t nslices = (n + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_slice_plan, rows_grid(nslices * kSlice), dim3(kSetupBlock), 0, st, n, nslices, row_ptr, col,
-                       width, aligned);
+                       row0, nrows, width, aligned);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_sell(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                            const int64_t* slice_ptr, const int32_t* slice_meta, int32_t* soff, int32_t* scol,
-                            double* sval, int write_cols, hipStream_t st)
+hipError_t launch_fill_sell(int64_t n, int64_t nslices, const int32_t* row_ptr, const int32_t* col, const double* val,
+                            const int64_t* row0, const int32_t* nrows, const int64_t* slice_ptr,
+                            const int32_t* slice_meta, int32_t* soff, int32_t* scol, double* sval, int write_cols,
+                            hipStream_t st)
 {
-    const int64_t nslices = (n + kSlice - 1) / kSlice;
     hipLaunchKernelGGL(k_fill_sell, rows_grid(nslices * kSlice), dim3(kSetupBlock), 0, st, n, nslices, row_ptr, col,
-                       val, slice_ptr, slice_meta, soff, scol, sval, write_cols);
+                       val, row0, nrows, slice_ptr, slice_meta, soff, scol, sval, write_cols);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/prcg.h"
+#include "batched.h"
 #include "prcg_common.h"
 
 using namespace prcg;
@@ -132,7 +133,75 @@ struct prcg_matrix_s {
     }
 };
 
+struct prcg_batch_s {
+    prcg_matrix A = nullptr;
+    int32_t nsys = 0;
+    int64_t nslices = 0;
+    int64_t stored = 0;
+    int num_cus = 256;
+    int64_t* slice_row0 = nullptr;
+    int32_t* slice_nrows = nullptr;
+    int64_t* sys_row0 = nullptr;
+    int64_t* sys_slice0 = nullptr;
+    int32_t* order = nullptr;
+    int64_t* slice_ptr = nullptr;
+    int32_t* slice_meta = nullptr;
+    int32_t* soff = nullptr;
+    int32_t* scol = nullptr;
+    double* sval = nullptr;
+    double* vecs = nullptr;  // x r rt p s st w u b
+    int32_t* queue = nullptr;
+    int32_t* iters = nullptr;
+    int32_t* status = nullptr;
+    int tuned_nt[3] = {0, 0, 0};
+    int tuned_grid[3] = {0, 0, 0};
+    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double graph_tol[5] = {0, 0, 0, 0, 0};
+    int32_t graph_maxit[5] = {0, 0, 0, 0, 0};
+
+    Vecs vecs_view() const
+    {
+        const size_t n8 = (size_t)A->n;
+        Vecs v;
+        v.x = vecs;
+        v.r = vecs + n8;
+        v.rt = vecs + 2 * n8;
+        v.p = vecs + 3 * n8;
+        v.s = vecs + 4 * n8;
+        v.st = vecs + 5 * n8;
+        v.w = vecs + 6 * n8;
+        v.u = vecs + 7 * n8;
+        v.d = A->d;
+        return v;
+    }
+    BatchView view() const
+    {
+        BatchView b;
+        b.A = SellView{slice_ptr, slice_meta, soff, scol, sval, A->n, nslices};
+        b.slice_row0 = slice_row0;
+        b.slice_nrows = slice_nrows;
+        b.sys_row0 = sys_row0;
+        b.sys_slice0 = sys_slice0;
+        b.order = order;
+        b.nsys = nsys;
+        return b;
+    }
+};
+
 namespace {
+
+void free_batch(prcg_batch B)
+{
+    if (!B) return;
+    (void)hipSetDevice(B->A->device);
+    for (auto& g : B->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
+                   B->slice_meta, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    delete B;
+}
 
 void free_matrix(prcg_matrix A)
 {
@@ -354,7 +423,8 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     {
         int32_t* dplan = nullptr;
         HTRY(hipMalloc(&dplan, sizeof(int32_t) * 2 * A->nslices));
-        hipError_t e1 = launch_slice_plan(n, A->row_ptr, A->col, dplan, dplan + A->nslices, A->stream);
+        hipError_t e1 = launch_slice_plan(n, A->nslices, A->row_ptr, A->col, nullptr, nullptr, dplan,
+                                          dplan + A->nslices, A->stream);
         if (e1 == hipSuccess)
             e1 = hipMemcpyAsync(width.data(), dplan, sizeof(int32_t) * A->nslices, hipMemcpyDeviceToHost, A->stream);
         if (e1 == hipSuccess)
@@ -399,8 +469,8 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
                             A->stream));
         HTRY(hipMemcpyAsync(A->slice_meta, hmeta.data(), sizeof(int32_t) * A->nslices, hipMemcpyHostToDevice,
                             A->stream));
-        HTRY(launch_fill_sell(n, A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol, A->sval,
-                              1, A->stream));
+        HTRY(launch_fill_sell(n, A->nslices, A->row_ptr, A->col, A->val, nullptr, nullptr, A->slice_ptr,
+                              A->slice_meta, A->soff, A->scol, A->sval, 1, A->stream));
         HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
     }
     A->sp = make_split(n, lanes);
@@ -435,8 +505,8 @@ prcg_status prcg_set_values(prcg_matrix A, const double* values)
     if (A->nnz > 0)
         HIP_TRY(hipMemcpyAsync(A->val, values, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, A->stream));
     if (A->sp.lanes == 1)
-        HIP_TRY(launch_fill_sell(A->n, A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol,
-                                 A->sval, 0, A->stream));
+        HIP_TRY(launch_fill_sell(A->n, A->nslices, A->row_ptr, A->col, A->val, nullptr, nullptr, A->slice_ptr,
+                                 A->slice_meta, A->soff, A->scol, A->sval, 0, A->stream));
     if (A->precond == PRCG_PRECOND_JACOBI) {
         HIP_TRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), A->stream));
         HIP_TRY(launch_jacobi(A->n, A->row_ptr, A->col, A->val, A->d, A->dflags, A->stream));
@@ -583,17 +653,225 @@ prcg_status prcg_adjoint(prcg_matrix A, prcg_variant v, const double* x, const d
 
 void prcg_destroy(prcg_matrix A) { free_matrix(A); }
 
-prcg_status prcg_create_batch(prcg_matrix, int32_t, const int64_t*, prcg_batch* out)
+prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_row_offset, prcg_batch* out)
 {
-    if (out) *out = nullptr;
-    return fail(PRCG_EINVAL, "batched solver not available in this build");
+    if (!out) return fail(PRCG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A || nsys < 1 || !sys_row_offset) return fail(PRCG_EINVAL, "need a matrix, nsys >= 1 and offsets");
+    if (sys_row_offset[0] != 0 || sys_row_offset[nsys] != A->n)
+        return fail(PRCG_EINVAL, "sys_row_offset must start at 0 and end at n");
+    for (int32_t q = 0; q < nsys; ++q)
+        if (sys_row_offset[q + 1] <= sys_row_offset[q])
+            return fail(PRCG_EINVAL, "sys_row_offset must be strictly increasing");
+    HIP_TRY(hipSetDevice(A->device));
+    prcg_batch B = new prcg_batch_s();
+    B->A = A;
+    B->nsys = nsys;
+    auto bail = [&](prcg_status st) {
+        free_batch(B);
+        return st;
+    };
+#define BTRY(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return bail(fail(e_ == hipErrorOutOfMemory ? PRCG_ENOMEM : PRCG_EDEVICE,                \
+                             std::string(#expr) + ": " + hipGetErrorString(e_)));                   \
+    } while (0)
+    const int64_t n = A->n;
+    hipStream_t st = A->stream;
+    // block structure: no column may leave its system
+    {
+        std::vector<int32_t> row_sys((size_t)n);
+        for (int32_t q = 0; q < nsys; ++q)
+            for (int64_t i = sys_row_offset[q]; i < sys_row_offset[q + 1]; ++i) row_sys[(size_t)i] = q;
+        int32_t* drs = nullptr;
+        int64_t* doff = nullptr;
+        BTRY(hipMalloc(&drs, sizeof(int32_t) * n));
+        hipError_t e = hipMalloc(&doff, sizeof(int64_t) * (nsys + 1));
+        if (e == hipSuccess) e = hipMemcpyAsync(drs, row_sys.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(doff, sys_row_offset, sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(A->dflags, 0, sizeof(int32_t), st);
+        if (e == hipSuccess) e = launch_block_check(n, A->row_ptr, A->col, drs, doff, A->dflags, st);
+        int32_t hf = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&hf, A->dflags, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(drs);
+        if (doff) (void)hipFree(doff);
+        BTRY(e);
+        if (hf & 32) return bail(fail(PRCG_EINVAL, "a column index leaves its system's block"));
+    }
+    // slice geometry: slices restart at every system
+    std::vector<int64_t> sys_slice0((size_t)nsys + 1), slice_row0;
+    std::vector<int32_t> slice_nrows;
+    sys_slice0[0] = 0;
+    for (int32_t q = 0; q < nsys; ++q) {
+        for (int64_t r0 = sys_row_offset[q]; r0 < sys_row_offset[q + 1]; r0 += kSlice) {
+            slice_row0.push_back(r0);
+            slice_nrows.push_back((int32_t)std::min<int64_t>(kSlice, sys_row_offset[q + 1] - r0));
+        }
+        sys_slice0[q + 1] = (int64_t)slice_row0.size();
+    }
+    const int64_t ns = (int64_t)slice_row0.size();
+    B->nslices = ns;
+    BTRY(hipMalloc(&B->slice_row0, sizeof(int64_t) * ns));
+    BTRY(hipMalloc(&B->slice_nrows, sizeof(int32_t) * ns));
+    BTRY(hipMalloc(&B->sys_row0, sizeof(int64_t) * (nsys + 1)));
+    BTRY(hipMalloc(&B->sys_slice0, sizeof(int64_t) * (nsys + 1)));
+    BTRY(hipMemcpyAsync(B->slice_row0, slice_row0.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->slice_nrows, slice_nrows.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->sys_row0, sys_row_offset, sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->sys_slice0, sys_slice0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
+    // plan and fill the slices (offset-aligned or packed, as for a single matrix)
+    std::vector<int32_t> width((size_t)ns), aligned((size_t)ns);
+    {
+        int32_t* dplan = nullptr;
+        BTRY(hipMalloc(&dplan, sizeof(int32_t) * 2 * ns));
+        hipError_t e = launch_slice_plan(n, ns, A->row_ptr, A->col, B->slice_row0, B->slice_nrows, dplan, dplan + ns,
+                                         st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(width.data(), dplan, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(aligned.data(), dplan + ns, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(dplan);
+        BTRY(e);
+    }
+    std::vector<int64_t> hptr((size_t)ns + 1);
+    std::vector<int32_t> hmeta((size_t)ns);
+    int64_t noff = 0;
+    hptr[0] = 0;
+    for (int64_t q = 0; q < ns; ++q) {
+        hptr[q + 1] = hptr[q] + (int64_t)kSlice * width[q];
+        hmeta[q] = aligned[q] ? (int32_t)noff : -1;
+        if (aligned[q]) noff += width[q];
+    }
+    B->stored = hptr[ns];
+    BTRY(hipMalloc(&B->slice_ptr, sizeof(int64_t) * (ns + 1)));
+    BTRY(hipMalloc(&B->slice_meta, sizeof(int32_t) * ns));
+    BTRY(hipMalloc(&B->soff, sizeof(int32_t) * std::max<int64_t>(noff, 1)));
+    BTRY(hipMalloc(&B->scol, sizeof(int32_t) * std::max<int64_t>(B->stored, 1)));
+    BTRY(hipMalloc(&B->sval, sizeof(double) * std::max<int64_t>(B->stored, 1)));
+    BTRY(hipMemcpyAsync(B->slice_ptr, hptr.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->slice_meta, hmeta.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    BTRY(launch_fill_sell(n, ns, A->row_ptr, A->col, A->val, B->slice_row0, B->slice_nrows, B->slice_ptr,
+                          B->slice_meta, B->soff, B->scol, B->sval, 1, st));
+    // largest systems first
+    std::vector<int32_t> order((size_t)nsys);
+    for (int32_t q = 0; q < nsys; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return sys_row_offset[a + 1] - sys_row_offset[a] > sys_row_offset[b + 1] - sys_row_offset[b];
+    });
+    BTRY(hipMalloc(&B->order, sizeof(int32_t) * nsys));
+    BTRY(hipMemcpyAsync(B->order, order.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+    BTRY(hipMalloc(&B->vecs, sizeof(double) * 9 * (size_t)n));
+    BTRY(hipMalloc(&B->queue, sizeof(int32_t) * 4));
+    BTRY(hipMalloc(&B->iters, sizeof(int32_t) * nsys));
+    BTRY(hipMalloc(&B->status, sizeof(int32_t) * nsys));
+    BTRY(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
+    hipDeviceProp_t prop;
+    BTRY(hipGetDeviceProperties(&prop, A->device));
+    B->num_cus = prop.multiProcessorCount;
+    *out = B;
+    return PRCG_OK;
+#undef BTRY
 }
 
-prcg_status prcg_solve_batched(prcg_batch, prcg_variant, const double*, double*, double, int32_t, int32_t*, int32_t*)
+prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, double* x, double tol, int32_t maxit,
+                               int32_t* iters, int32_t* status)
 {
-    return fail(PRCG_EINVAL, "batched solver not available in this build");
+    if (!B) return fail(PRCG_EINVAL, "null batch");
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (!(tol >= 0.0) || maxit < 0) return fail(PRCG_EINVAL, "tol must be >= 0 and maxit >= 0");
+    if (!is_device_pointer(b) || !is_device_pointer(x)) return fail(PRCG_EINVAL, "b and x must be device pointers");
+    prcg_matrix A = B->A;
+    HIP_TRY(hipSetDevice(A->device));
+    hipStream_t st = A->stream;
+    const size_t nb = sizeof(double) * (size_t)A->n;
+    double* bvec = B->vecs + 8 * (size_t)A->n;
+    const Vecs vv = B->vecs_view();
+    const BatchView view = B->view();
+    const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
+    HIP_TRY(hipMemcpyAsync(bvec, b, nb, hipMemcpyDeviceToDevice, st));
+    // autotune once per kind: workgroup size x workgroups per CU, timed on a
+    // short run of this batch (tol = 0, a few iterations per system)
+    if (B->tuned_nt[kind] == 0) {
+        const char* force = std::getenv("PRCG_BATCH_CONFIG");
+        int fnt = 0, fper = 0;
+        if (force && std::sscanf(force, "%d,%d", &fnt, &fper) == 2 && (fnt == 256 || fnt == 512 || fnt == 1024) &&
+            fper >= 1 && fper <= 8) {
+            B->tuned_nt[kind] = fnt;
+            B->tuned_grid[kind] = std::min<int64_t>(B->nsys, (int64_t)B->num_cus * fper);
+        } else {
+            const int cand[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+            hipEvent_t e0, e1;
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            float best = 1e30f;
+            const int trial_it = std::min<int32_t>(maxit, 12);
+            for (auto& c : cand) {
+                const int grid = (int)std::min<int64_t>(B->nsys, (int64_t)B->num_cus * c[1]);
+                HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipEventRecord(e0, st));
+                HIP_TRY(launch_batch(view, vv, bvec, 0.0, trial_it, v, A->precond, c[0], grid, B->queue, B->iters,
+                                     B->status, st));
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    B->tuned_nt[kind] = c[0];
+                    B->tuned_grid[kind] = grid;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+    }
+    // one graph per (kind, variant, tol, maxit): reset the queue + persistent kernel
+    if (!B->graph[v] || B->graph_tol[v] != tol || B->graph_maxit[v] != maxit) {
+        if (B->graph[v]) (void)hipGraphExecDestroy(B->graph[v]);
+        B->graph[v] = nullptr;
+        HIP_TRY(hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t err = launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
+                                      B->tuned_grid[kind], B->queue, B->iters, B->status, A->capture);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(A->capture, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(PRCG_EDEVICE, "batched graph capture failed");
+        }
+        hipError_t e3 = hipGraphInstantiate(&B->graph[v], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_TRY(e3);
+        B->graph_tol[v] = tol;
+        B->graph_maxit[v] = maxit;
+    }
+    HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGraphLaunch(B->graph[v], st));
+    HIP_TRY(hipMemcpyAsync(x, vv.x, nb, hipMemcpyDeviceToDevice, st));
+    std::vector<int32_t> hst((size_t)B->nsys);
+    HIP_TRY(hipMemcpyAsync(hst.data(), B->status, sizeof(int32_t) * B->nsys, hipMemcpyDeviceToHost, st));
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, B->iters, sizeof(int32_t) * B->nsys, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (status) std::memcpy(status, hst.data(), sizeof(int32_t) * B->nsys);
+    int worst = PRCG_OK;
+    for (int32_t q = 0; q < B->nsys; ++q) worst = std::max(worst, (int)hst[q]);
+    return (prcg_status)worst;
 }
 
-void prcg_batch_destroy(prcg_batch) {}
+prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, int32_t* grid)
+{
+    if (!B || !threads || !grid) return fail(PRCG_EINVAL, "null argument");
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
+    *threads = B->tuned_nt[kind];
+    *grid = B->tuned_grid[kind];
+    return PRCG_OK;
+}
+
+void prcg_batch_destroy(prcg_batch B) { free_batch(B); }
 
 }  // extern "C"

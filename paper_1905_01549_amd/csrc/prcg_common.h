@@ -82,9 +82,13 @@ hipError_t launch_validate(int64_t n, int64_t nnz, const int32_t* row_ptr, const
                            int32_t* flags, int32_t* maxlen, hipStream_t st);
 hipError_t launch_jacobi(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                          double* d, int32_t* flags, hipStream_t st);
-hipError_t launch_slice_plan(int64_t n, const int32_t* row_ptr, const int32_t* col, int32_t* width,
-                             int32_t* aligned, hipStream_t st);
-hipError_t launch_fill_sell(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+// Slice planning / filling.  row0/nrows (nullable) give each slice's first
+// row and row count; when null, slice s covers rows 64 s .. 64 s + 63.
+hipError_t launch_slice_plan(int64_t n, int64_t nslices, const int32_t* row_ptr, const int32_t* col,
+                             const int64_t* row0, const int32_t* nrows, int32_t* width, int32_t* aligned,
+                             hipStream_t st);
+hipError_t launch_fill_sell(int64_t n, int64_t nslices, const int32_t* row_ptr, const int32_t* col,
+                            const double* val, const int64_t* row0, const int32_t* nrows,
                             const int64_t* slice_ptr, const int32_t* slice_meta, int32_t* soff, int32_t* scol,
                             double* sval, int write_cols, hipStream_t st);
 hipError_t launch_block_check(int64_t n, const int32_t* row_ptr, const int32_t* col,

@@ -17,10 +17,10 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum of NV values over the workgroup (256 threads); every thread receives
+// Sum of NV values over a workgroup of NW wavefronts; every thread receives
 // the totals.  The order of additions is fixed, so results are repeatable.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* kWaves * NV */)
+template <int NV, int NW = kWaves>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * NV */)
 {
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
@@ -34,7 +34,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* kWaves
     for (int i = 0; i < NV; ++i) {
         double t = lds[i];
 #pragma unroll
-        for (int q = 1; q < kWaves; ++q) t += lds[q * NV + i];
+        for (int q = 1; q < NW; ++q) t += lds[q * NV + i];
         v[i] = t;
     }
     __syncthreads();
@@ -91,8 +91,9 @@ __device__ __forceinline__ void chunk_of(int b, int G, int64_t ngroups, int64_t&
 // Products of one SELL-64 row with NX vectors (entries summed in stored
 // column order; zero slots add nothing).
 template <int NX>
-__device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, const double* __restrict__ x0,
-                                         const double* __restrict__ x1, double& y0, double& y1)
+__device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, int64_t row64,
+                                         const double* __restrict__ x0, const double* __restrict__ x1, double& y0,
+                                         double& y1)
 {
     const int64_t base = A.slice_ptr[slice];
     const int width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
@@ -102,7 +103,7 @@ __device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int l
     if (meta >= 0) {
         // offset-aligned: the column is row + offset, clamped into [0, n) so
         // that zero slots of boundary rows read a valid entry
-        const int row = (int)(slice * kSlice + lane);
+        const int row = (int)row64;
         const int last = (int)A.n - 1;
         const int32_t* __restrict__ off = A.soff + meta;
 #pragma unroll 4
@@ -137,8 +138,8 @@ __device__ __forceinline__ void sell_group(const SellView& A, int64_t g, const d
     if (slice >= A.nslices) return;
     const int lane = threadIdx.x & 63;
     double y0, y1;
-    sell_row<NX>(A, slice, lane, x0, x1, y0, y1);
     const int64_t row = slice * kSlice + lane;
+    sell_row<NX>(A, slice, lane, row, x0, x1, y0, y1);
     if (row < A.n) f(row, y0, y1);
 }
 
@@ -180,6 +181,95 @@ __device__ __forceinline__ void rows_of_group(const SellView& S, const CsrView& 
         sell_group<NX>(S, g, x0, x1, f);
     else
         csr_group<LANES, NX>(C, g, x0, x1, f);
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// The scalar step after the reduction of iteration k of a one-reduction
+// variant (PR, M, pipe-PR, pipe-M): record ||r_k||, test convergence and
+// breakdown, then form alpha_k, nu'_{k+1} and beta_{k+1} (Alg. 2 / Alg. 3,
+// eq. nuk_simplified; Meurant: nu' = -nu + alpha^2 gamma).
+__device__ inline void step_one_reduction(State& st, const double (&t)[5], bool pre, bool meurant, double* hist,
+                                   bool writer)
+{
+    const double mu = t[0], sigma = t[1], gamma = t[2], nu = t[3];
+    const double rr = pre ? t[4] : nu;
+    const int k = st.k + 1;
+    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
+    if (writer) hist[k] = rnorm / st.bnorm;
+    st.k = k;
+    st.nu = nu;
+    st.mu = mu;
+    st.sigma = sigma;
+    st.gamma = gamma;
+    st.rr = rr;
+    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
+        st.done = 1;
+        st.status = kOK;
+        return;
+    }
+    if (st.last || !finite(nu) || !finite(mu) || !finite(rr) || !(nu > 0.0) || !(mu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        return;
+    }
+    if (k == st.maxit) {
+        st.done = 1;
+        st.status = kNotConverged;
+        return;
+    }
+    const double alpha = nu / mu;
+    const double nup = meurant ? -nu + alpha * alpha * gamma : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
+    st.alpha = alpha;
+    st.nup = nup;
+    if (!finite(nup) || !(nup > 0.0)) {
+        st.last = 1;  // the next iteration's x and r updates are still taken
+        st.beta = 0.0;
+    } else {
+        st.beta = nup / nu;
+    }
+}
+
+// HS-CG after the reduction of nu_k (Alg. 1): record ||r_k||, test, beta_k.
+__device__ inline void step_hs_nu(State& st, double nu, double rr, double* hist, bool writer)
+{
+    const int k = st.k + 1;
+    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
+    if (writer) hist[k] = rnorm / st.bnorm;
+    st.k = k;
+    st.rr = rr;
+    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
+        st.done = 1;
+        st.status = kOK;
+        st.nu = nu;
+        return;
+    }
+    if (!finite(nu) || !finite(rr) || !(nu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        st.nu = nu;
+        return;
+    }
+    if (k == st.maxit) {
+        st.done = 1;
+        st.status = kNotConverged;
+        st.nu = nu;
+        return;
+    }
+    if (k > 0) st.beta = nu / st.nu;  // beta_k = nu_k / nu_{k-1}
+    st.nu = nu;
+}
+
+// HS-CG after the reduction of mu_k: alpha_k = nu_k / mu_k.
+__device__ inline void step_hs_mu(State& st, double mu)
+{
+    st.mu = mu;
+    if (!finite(mu) || !(mu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        return;
+    }
+    st.alpha = st.nu / mu;
 }
 
 }  // namespace prcg

@@ -26,7 +26,7 @@ STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem
 
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_stream", "prcg_spmv", "prcg_solve",
             "prcg_time_kernels", "prcg_get_props", "prcg_create_batch", "prcg_solve_batched",
-            "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error")
+            "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config")
 
 
 class PrcgError(RuntimeError):
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH):
         "prcg_destroy": (None, [_VP]),
         "prcg_batch_destroy": (None, [_VP]),
         "prcg_last_error": (ctypes.c_char_p, []),
+        "prcg_batch_config": (i32, [_VP, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,6 +142,12 @@ def prcg_create_batch(A, nsys, sys_row_offset_host) -> int:
 def prcg_solve_batched(B, variant, b, x, tol, maxit, iters=None, status=None) -> int:
     return _check(load_library().prcg_solve_batched(B, variant, b, x, tol, maxit, iters, status),
                   allow_numeric=True)
+
+
+def prcg_batch_config(B, variant):
+    t, g = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load_library().prcg_batch_config(B, variant, ctypes.byref(t), ctypes.byref(g)))
+    return t.value, g.value
 
 
 def prcg_adjoint(A, variant, x, gx, gb, gvals, tol, maxit, info=None) -> int:
@@ -269,3 +276,41 @@ class Matrix:
     def time_kernels(self, variant: str = "pr", iters: int = 50):
         prcg_set_stream(self.handle, _stream_ptr())
         return prcg_time_kernels(self.handle, VARIANTS[variant], iters)
+
+
+class Batch:
+    """Independent systems stored as one block-diagonal matrix (rows of
+    system s: sys_row_offset[s] .. sys_row_offset[s+1])."""
+
+    def __init__(self, matrix: Matrix, sys_row_offset):
+        self.matrix = matrix
+        self.offsets = np.ascontiguousarray(sys_row_offset, dtype=np.int64)
+        self.nsys = self.offsets.size - 1
+        self.handle = None
+        self.handle = prcg_create_batch(matrix.handle, self.nsys, self.offsets)
+
+    def close(self):
+        if self.handle:
+            prcg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, variant: str = "pr", tol: float = 1e-10, maxit: int = 10000, x0=None):
+        """Returns (x, iters[nsys], status[nsys] as strings)."""
+        torch = _torch()
+        bd = _dev(b, torch.float64)
+        x = torch.zeros_like(bd) if x0 is None else _dev(x0, torch.float64).clone()
+        iters = np.zeros(self.nsys, dtype=np.int32)
+        status = np.zeros(self.nsys, dtype=np.int32)
+        prcg_set_stream(self.matrix.handle, _stream_ptr())
+        prcg_solve_batched(self.handle, VARIANTS[variant], bd.data_ptr(), x.data_ptr(), float(tol), int(maxit),
+                           iters.ctypes.data, status.ctypes.data)
+        return x, iters, [STATUS[int(c)] for c in status]
+
+    def config(self, variant: str = "pr"):
+        return prcg_batch_config(self.handle, VARIANTS[variant])

@@ -1,0 +1,130 @@
+"""GPU parity of the batched persistent solver against the oracle, system by
+system: at the GPU's iteration count the solution matches the oracle to
+1e-10 relative, the stopping iteration agrees to +-1 and the status agrees."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_01549_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prcg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_01549_amd import prcg as mod
+    mod.load_library()
+    return mod
+
+
+def small_batch(nsys=12, nmin=64, nmax=3000):
+    mats, bs = [], []
+    for s in range(nsys):
+        A, b, xs, eps = P.batch_system(s, nmin, nmax)
+        mats.append(A)
+        bs.append(b)
+    A, offs = P.block_diag(mats)
+    return A, offs, np.concatenate(bs), mats, bs
+
+
+def check_systems(x, iters, status, mats, bs, offs, variant, precond, tol, which=None):
+    which = range(len(mats)) if which is None else which
+    for s in which:
+        A, b = mats[s], bs[s]
+        xs = x[offs[s]:offs[s + 1]]
+        ref_stop = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, precond, tol, 20000)
+        assert status[s] == ref_stop["status"], (s, status[s], ref_stop["status"])
+        assert abs(int(iters[s]) - ref_stop["iters"]) <= 1, (s, iters[s], ref_stop["iters"])
+        ref = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, precond, 0.0, int(iters[s]))
+        assert np.linalg.norm(xs - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"]), s
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+@pytest.mark.parametrize("variant", ["pr", "hs", "pipe_pr", "m", "pipe_m"])
+def test_batched_matches_oracle(prcg, variant, precond):
+    A, offs, b, mats, bs = small_batch()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
+    B = prcg.Batch(M, offs)
+    x, iters, status = B.solve(b, variant, 1e-10, 5000)
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, variant, precond, 1e-10)
+    nt, grid = B.config(variant)
+    assert nt in (256, 512, 1024) and grid >= 1
+
+
+@pytest.mark.parametrize("config", ["256,1", "512,2", "1024,1"])
+def test_every_workgroup_size(prcg, config, monkeypatch):
+    monkeypatch.setenv("PRCG_BATCH_CONFIG", config)
+    A, offs, b, mats, bs = small_batch(9)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000)
+    assert B.config("pr")[0] == int(config.split(",")[0])
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", "none", 1e-10)
+
+
+def test_batched_is_repeatable_and_x0_is_used(prcg, monkeypatch):
+    monkeypatch.setenv("PRCG_BATCH_CONFIG", "512,2")
+    A, offs, b, mats, bs = small_batch(7)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    B = prcg.Batch(M, offs)
+    x1, i1, _ = B.solve(b, "pipe_pr", 1e-10, 5000)
+    x2, i2, _ = B.solve(b, "pipe_pr", 1e-10, 5000)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy()) and np.array_equal(i1, i2)
+    # starting from the solution: every system converges at k = 0
+    x3, i3, s3 = B.solve(b, "pr", 1e-6, 5000, x0=x1)
+    assert np.all(i3 == 0) and all(st == "ok" for st in s3)
+
+
+def test_zero_block_and_maxit(prcg, monkeypatch):
+    monkeypatch.setenv("PRCG_BATCH_CONFIG", "256,2")
+    A, offs, b, mats, bs = small_batch(5)
+    b = b.copy()
+    b[offs[2]:offs[3]] = 0.0
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000, x0=np.ones(A.n))
+    x = x.cpu().numpy()
+    assert iters[2] == 0 and status[2] == "ok" and np.all(x[offs[2]:offs[3]] == 0.0)
+    x, iters, status = B.solve(b, "hs", 0.0, 7)
+    assert all(int(k) == 7 for s, k in enumerate(iters) if s != 2)
+    assert all(st == "not_converged" for s, st in enumerate(status) if s != 2)
+
+
+def test_block_structure_is_checked(prcg):
+    A, offs, b, mats, bs = small_batch(3)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    bad = offs.copy()
+    bad[1] += 5  # splits a system: its couplings now cross a block boundary
+    with pytest.raises(prcg.PrcgError):
+        prcg.Batch(M, bad)
+    with pytest.raises(prcg.PrcgError):
+        prcg.Batch(M, offs[::-1].copy())
+
+
+def test_full_batched_workload_sampled(prcg):
+    """All 512 systems (n from 1k to 64k) in one launch; the oracle checks the
+    largest, the smallest and two more systems; every system's true residual
+    is checked on the host."""
+    A, offs, b, xstar, eps = P.config4()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    x, iters, status = B.solve(b, "pr", 1e-10, 20000)
+    x = x.cpu().numpy()
+    assert all(st == "ok" for st in status)
+    sizes = np.diff(offs)
+    sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 17, 300})
+    mats = {s: P.batch_system(s)[0] for s in sample}
+    for s in sample:
+        As = mats[s]
+        bsys = b[offs[s]:offs[s + 1]]
+        ref = oracle.solve(As.row_ptr, As.col_idx, As.values, bsys, "pr", "none", 0.0, int(iters[s]))
+        xs = x[offs[s]:offs[s + 1]]
+        assert np.linalg.norm(xs - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"]), s
+    S = A.scipy()
+    res = S @ x - b
+    for s in range(len(sizes)):
+        sl = slice(offs[s], offs[s + 1])
+        assert np.linalg.norm(res[sl]) <= 2e-10 * np.linalg.norm(b[sl]), s
