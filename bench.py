@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--variant", default="pr")
     ap.add_argument("--grid", type=int, default=0, help="override the workgroup count (tuning)")
+    ap.add_argument("--kernels", default="two_pass", help="kernel structure of the flagship run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--m", type=int, default=128, help="grid edge (128 = the benchmark workload)")
@@ -70,8 +71,6 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    if args.grid:
-        os.environ["PRCG_GRID"] = str(args.grid)
     import torch
 
     from paper_1905_01549_amd import prcg, problems, traffic
@@ -81,9 +80,13 @@ def main():
     A = pr.A
     workload = f"poisson3d_{args.m}_jacobi"
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    if args.grid:
+        M.set_grid(args.grid)
+    M.set_kernels(args.kernels)
     b = torch.as_tensor(pr.b, device="cuda")
     props = M.props
     n = A.n
+    fused = args.kernels == "fused"
 
     if args.kernels_only:
         # a plain copy of known size (256 MiB read + 256 MiB written) to
@@ -93,7 +96,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         kt = M.time_kernels(args.variant, 200)
-        kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes)
+        kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused)
         print(json.dumps({"workload": workload, "variant": args.variant, "launches": 200,
                           "kernels": {k: {"us": ms * 1e3, "bytes": kb.get(k, 0),
                                           "GBps": kb.get(k, 0) / (ms * 1e-3) / 1e9} for k, ms in kt}}))
@@ -123,34 +126,38 @@ def main():
     iters_per_s = total_iters / elapsed
     flagship = info
 
-    # every variant, same workload (2 solves each, best time)
+    # every variant under both kernel structures, same workload (best of 2 solves)
     variants = {}
-    for v in ("hs", "pr", "pipe_pr"):
-        vi = solve(v)
-        best = float("inf")
-        for _ in range(2):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
+    for kern in ("two_pass", "fused", "textbook"):
+        M.set_kernels(kern)
+        for v in (("hs",) if kern == "textbook" else ("hs", "pr", "pipe_pr")):
             vi = solve(v)
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t)
-        it_bytes = traffic.iteration_bytes(v, True, n, props.matrix_bytes)
-        kt = M.time_kernels(v, 50)
-        kb = traffic.kernel_bytes(v, True, n, props.matrix_bytes)
-        variants[v] = {
-            "iters": vi.iters,
-            "relres_true": vi.relres_true,
-            "solve_ms": best * 1e3,
-            "us_per_iter": best / vi.iters * 1e6,
-            "iters_per_s": vi.iters / best,
-            "algorithmic_GBps": it_bytes / (best / vi.iters) / 1e9,
-            "bytes_per_iter": it_bytes,
-            "kernels": {name: {"us": ms * 1e3, "GBps": kb.get(name, 0) / (ms * 1e-3) / 1e9} for name, ms in kt},
-        }
+            best = float("inf")
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                vi = solve(v)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t)
+            fz = kern == "fused"
+            it_bytes = traffic.iteration_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook")
+            kt = M.time_kernels(v, 50)
+            kb = traffic.kernel_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook")
+            variants[f"{v}/{kern}"] = {
+                "iters": vi.iters,
+                "relres_true": vi.relres_true,
+                "solve_ms": best * 1e3,
+                "us_per_iter": best / vi.iters * 1e6,
+                "iters_per_s": vi.iters / best,
+                "algorithmic_GBps": it_bytes / (best / vi.iters) / 1e9,
+                "bytes_per_iter": it_bytes,
+                "kernels": {name: {"us": ms * 1e3, "GBps": kb.get(name, 0) / (ms * 1e-3) / 1e9} for name, ms in kt},
+            }
+    M.set_kernels(args.kernels)
 
     # dominant kernel of the flagship variant: the SpMV + inner-product kernel
     kt = dict(M.time_kernels(args.variant, 200))
-    kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes)
+    kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused)
     dom = max((k for k in kt if k in kb), key=lambda k: kt[k])
     achieved = kb[dom] / (kt[dom] * 1e-3) / 1e9
     tb = load_traffic(dom, workload)
@@ -184,10 +191,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "nnz": A.nnz, "precond": "jacobi", "variant": args.variant,
                    "tol": TOL, "iters_per_solve": flagship.iters, "relres_true": flagship.relres_true,
-                   "format": "sell64" if props.format == 0 else
+                   "kernels": args.kernels, "format": "sell64" if props.format == 0 else
                    f"csr{props.lanes_per_row}", "grid": props.grid, "parallelism": "single GPU"},
-        "hbm_GBps_algorithmic": variants[args.variant]["algorithmic_GBps"],
-        "hbm_frac": variants[args.variant]["algorithmic_GBps"] / HBM_PEAK_GBS,
+        "hbm_GBps_algorithmic": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"],
+        "hbm_frac": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"] / HBM_PEAK_GBS,
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -97,7 +97,37 @@ typedef struct {
     double aligned_slices_frac; /* SELL-64: share of slots in offset-aligned slices,
                                    which store one column offset per slot and slice
                                    instead of a column index per entry              */
+    int32_t kernels;          /* kernel structure in use (PRCG_KERNELS_*)           */
+    int32_t pad;
 } prcg_matrix_props;
+
+/* Options (prcg_set_option).
+ *   PRCG_OPT_KERNELS  kernel structure of an iteration:
+ *     PRCG_KERNELS_FUSED: PR-CG and pipe-PR-CG run one kernel per
+ *       iteration, HS-CG two; the sparse product recomputes the new
+ *       direction at neighbouring rows from double-buffered vectors, with
+ *       the owner's exact operations.  Needs the SELL-64 layout; matrices
+ *       stored as vector CSR use the two-pass structure.
+ *     PRCG_KERNELS_TWO_PASS (default): an update kernel and a product kernel
+ *       per reduction (PR: 2, pipe-PR: 2, HS: 3 kernels per iteration).  On
+ *       MI355X this moves more bytes than FUSED but runs faster: the fused
+ *       product's neighbour recomputation gathers three to five vectors per
+ *       stored entry.
+ *     PRCG_KERNELS_TWO_PASS_STAGE2: as TWO_PASS, with PR's stage-2
+ *       reduction in a one-workgroup kernel of its own.
+ *     PRCG_KERNELS_TEXTBOOK: HS-CG as one kernel per line of Alg. 1 (AXPYs,
+ *       preconditioner, each inner product, a one-workgroup reduction
+ *       kernel per synchronisation, the product): the unfused baseline.
+ *       Other variants run TWO_PASS under this setting.
+ *   PRCG_OPT_GRID  largest number of workgroups of the row-parallel kernels
+ *     (8..1024, default 1024; the actual count is a multiple of 8). */
+typedef enum { PRCG_OPT_KERNELS = 0, PRCG_OPT_GRID = 1 } prcg_option;
+typedef enum {
+    PRCG_KERNELS_FUSED = 0,
+    PRCG_KERNELS_TWO_PASS = 1,
+    PRCG_KERNELS_TWO_PASS_STAGE2 = 2,
+    PRCG_KERNELS_TEXTBOOK = 3
+} prcg_kernels;
 
 /*
  * Create a matrix handle from CSR arrays (Section 1: A sparse SPD).
@@ -122,6 +152,10 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
 /* Replace the values of A (same sparsity pattern, CSR order as at
  * creation; device float64[nnz]) and refresh the Jacobi diagonal. */
 prcg_status prcg_set_values(prcg_matrix A, const double* values);
+
+/* Set an option of A (see prcg_option); results of later solves are
+ * bitwise repeatable for a fixed option set. */
+prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value);
 
 /* Change the stream used by later calls on A. */
 prcg_status prcg_set_stream(prcg_matrix A, void* hip_stream);
@@ -161,13 +195,15 @@ prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x
  * work; PRCG_EDEVICE if the run ends early).  Each launch carries dispatch
  * start/stop timestamps (hipExtLaunchKernelGGL events), so the times are
  * kernel execution times.  Overwrites the solver state of A.
- *   ms_per_launch  host float64[8]: average milliseconds per launch of each
- *                  kernel of one iteration, in launch order.
- *   names          host, nullable, char[8][48]: kernel names.
+ *   ms_per_launch  host float64[capacity]: average milliseconds per launch
+ *                  of each kernel of one iteration, in launch order.
+ *   names          host, nullable, char[capacity][48]: kernel names.
+ *   capacity       entries of ms_per_launch / names; PRCG_EINVAL (nothing
+ *                  written) if an iteration has more kernels (at most 10).
  *   nkernels       host: number of kernels per iteration.
  */
 prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, double* ms_per_launch,
-                              char (*names)[48], int32_t* nkernels);
+                              char (*names)[48], int32_t capacity, int32_t* nkernels);
 
 /* Describe the storage chosen for A. */
 prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props);

@@ -1,0 +1,348 @@
+// Fused iterations on the SELL-64 layout: one kernel per iteration of PR-CG
+// and of pipe-PR-CG, two per iteration of HS-CG.
+//
+// The sparse product of an iteration needs the iteration's new direction
+// (PR: p_k; pipe-PR: s~_k and r~_k; HS: p_k) at neighbouring rows, which other
+// workgroups produce in the same kernel.  Instead of a kernel boundary, each
+// row recomputes those neighbour entries from the previous iteration's
+// vectors with exactly the owner's expression (same operations, same
+// order, so the same bits), and the vectors involved are double-buffered:
+// iteration k reads copy k mod 2 and writes copy (k+1) mod 2, so no row ever
+// reads an entry another row is overwriting.  Vectors read only at the own
+// row (x always; p, r, s where no neighbour needs them) are updated in place.
+//
+// Every kernel starts with stage 2 of the previous reduction (every
+// workgroup sums the partials in the same fixed order) and the scalar step;
+// the partial buffers are double-buffered as well.
+#include <hip/hip_ext.h>
+
+#include "prcg_device.h"
+#include "prcg_fused.h"
+
+namespace prcg {
+
+namespace {
+
+__device__ __forceinline__ bool writer() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// Start of a one-reduction kernel: stage 2 + scalar step; false if done.
+template <bool PRE>
+__device__ __forceinline__ bool enter_one_reduction(const Split& sp, const State* __restrict__ in,
+                                                    State* __restrict__ out, double* __restrict__ hist,
+                                                    const double* __restrict__ Pin, int meurant, State& st,
+                                                    double* lds)
+{
+    st = *in;
+    if (st.done) {
+        if (writer()) *out = st;
+        return false;
+    }
+    double t[5];
+    reduce_partials<5>(Pin, sp.G, sp.Gs, t, lds);
+    step_one_reduction(st, t, PRE, meurant != 0, hist, writer());
+    if (writer()) *out = st;
+    return !st.done;
+}
+
+// Offset-aligned or packed slot j of a SELL row: column and value.
+struct SlotIter {
+    const int32_t* off;   // aligned: slice offsets, else nullptr
+    const int32_t* col;   // packed: column of the first slot of this lane
+    const double* val;
+    int row, last;
+    __device__ __forceinline__ int column(int j) const
+    {
+        return off ? min(max(row + off[j], 0), last) : col[(int64_t)j * 64];
+    }
+    __device__ __forceinline__ double value(int j) const { return val[(int64_t)j * 64]; }
+};
+
+__device__ __forceinline__ SlotIter slots_of(const SellView& A, int64_t slice, int lane, int64_t row, int& width)
+{
+    const int64_t base = A.slice_ptr[slice];
+    width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
+    const int meta = A.slice_meta[slice];
+    SlotIter it;
+    it.off = meta >= 0 ? A.soff + meta : nullptr;
+    it.col = A.col + base + lane;
+    it.val = A.val + base + lane;
+    it.row = (int)row;
+    it.last = (int)A.n - 1;
+    return it;
+}
+
+// PR-CG, one kernel per iteration (Alg. 2):
+//   x += alpha p; r -= alpha s; r~ -= alpha s~ (s~ = d s); p' = r~ + beta p;
+//   s' = A p' with p' at neighbour j recomputed from p, s, r~ (and d);
+//   partials of mu, sigma, gamma, nu (+ <r, r>) for the next kernel.
+// Double-buffered: p, s, r~ (r~ is r without a preconditioner).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const State* __restrict__ in,
+                                                     State* __restrict__ out, double* __restrict__ hist,
+                                                     const double* __restrict__ Pin, double* __restrict__ Pout,
+                                                     int meurant, FusedVecs f, int q)
+{
+    __shared__ double lds[kWaves * 5];
+    State st;
+    if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, meurant, st, lds)) return;
+    const double alpha = st.alpha, beta = st.beta;
+    const double* __restrict__ p_o = f.p[q];
+    double* __restrict__ p_n = f.p[1 - q];
+    const double* __restrict__ s_o = f.s[q];
+    double* __restrict__ s_n = f.s[1 - q];
+    const double* __restrict__ t_o = PRE ? f.rt[q] : f.r[q];   // r~ (old)
+    double* __restrict__ t_n = PRE ? f.rt[1 - q] : f.r[1 - q];  // r~ (new)
+    double* __restrict__ r = f.r[0];                            // r in place (with a preconditioner)
+    double* __restrict__ x = f.x;
+    const double* __restrict__ d = f.d;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int64_t g = g0; g < g1; ++g) {
+        const int64_t slice = g * kWaves + w;
+        if (slice >= S.nslices) break;
+        const int64_t i = slice * kSlice + lane;
+        const bool own = i < S.n;
+        // own row: the vector updates
+        double pn = 0.0, rn = 0.0, tn = 0.0, di = 0.0;
+        if (own) {
+            const double pi = p_o[i], si = s_o[i], ti = t_o[i], xi = x[i];
+            const double ri = PRE ? r[i] : ti;
+            di = PRE ? d[i] : 1.0;
+            rn = fma(-alpha, si, ri);
+            tn = PRE ? fma(-alpha, di * si, ti) : rn;
+            pn = fma(beta, pi, tn);
+            x[i] = fma(alpha, pi, xi);
+            if (PRE) {
+                r[i] = rn;
+                t_n[i] = tn;
+            } else {
+                t_n[i] = rn;
+            }
+            p_n[i] = pn;
+        }
+        // s' = A p', p' at neighbours from the previous vectors
+        int width;
+        const SlotIter it = slots_of(S, slice, lane, i, width);
+        double sn = 0.0;
+#pragma unroll 2
+        for (int j = 0; j < width; ++j) {
+            const int c = it.column(j);
+            const double a = it.value(j);
+            const double sc = s_o[c];
+            const double tc = t_o[c];
+            const double pc = p_o[c];
+            const double dc = PRE ? d[c] : 1.0;
+            const double tnc = PRE ? fma(-alpha, dc * sc, tc) : fma(-alpha, sc, tc);
+            sn = fma(a, fma(beta, pc, tnc), sn);
+        }
+        if (own) {
+            s_n[i] = sn;
+            const double stn = PRE ? di * sn : sn;
+            acc[0] = fma(pn, sn, acc[0]);   // mu    = <p, s>
+            acc[1] = fma(tn, sn, acc[1]);   // sigma = <r~, s>
+            acc[2] = fma(stn, sn, acc[2]);  // gamma = <s~, s>
+            acc[3] = fma(tn, rn, acc[3]);   // nu    = <r~, r>
+            if (PRE) acc[4] = fma(rn, rn, acc[4]);
+        }
+    }
+    write_partials<5>(acc, Pout, sp.Gs, blockIdx.x, lds);
+}
+
+// pipe-PR-CG, one kernel per iteration (Alg. 3): all vector updates of the
+// own row, the inner products, then u' = A s~' and w' = A r~' with s~' and
+// r~' at neighbour j recomputed from r~, s~, w, u (and d).  Double-buffered:
+// r~, s~, w, u (r~ = r and s~ = s without a preconditioner).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, const State* __restrict__ in,
+                                                       State* __restrict__ out, double* __restrict__ hist,
+                                                       const double* __restrict__ Pin, double* __restrict__ Pout,
+                                                       int meurant, FusedVecs f, int q)
+{
+    __shared__ double lds[kWaves * 5];
+    State st;
+    if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, meurant, st, lds)) return;
+    const double alpha = st.alpha, beta = st.beta;
+    const double* __restrict__ t_o = PRE ? f.rt[q] : f.r[q];
+    double* __restrict__ t_n = PRE ? f.rt[1 - q] : f.r[1 - q];
+    const double* __restrict__ z_o = PRE ? f.st[q] : f.s[q];    // s~ (old)
+    double* __restrict__ z_n = PRE ? f.st[1 - q] : f.s[1 - q];
+    const double* __restrict__ w_o = f.w[q];
+    double* __restrict__ w_n = f.w[1 - q];
+    const double* __restrict__ u_o = f.u[q];
+    double* __restrict__ u_n = f.u[1 - q];
+    double* __restrict__ r = f.r[0];
+    double* __restrict__ s = f.s[0];
+    double* __restrict__ p = f.p[0];
+    double* __restrict__ x = f.x;
+    const double* __restrict__ d = f.d;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int64_t g = g0; g < g1; ++g) {
+        const int64_t slice = g * kWaves + w;
+        if (slice >= S.nslices) break;
+        const int64_t i = slice * kSlice + lane;
+        const bool own = i < S.n;
+        if (own) {
+            const double pi = p[i], xi = x[i], wi = w_o[i], ui = u_o[i], ti = t_o[i], zi = z_o[i];
+            const double si = PRE ? s[i] : zi;
+            const double ri = PRE ? r[i] : ti;
+            const double rn = fma(-alpha, si, ri);                 // r_k
+            const double sn = fma(beta, si, fma(-alpha, ui, wi));  // s_k = w'_k + beta s_{k-1}
+            double tn = rn, zn = sn;
+            if (PRE) {
+                const double di = d[i];
+                tn = fma(-alpha, zi, ti);                                // r~_k
+                zn = fma(beta, zi, fma(-alpha, di * ui, di * wi));       // s~_k
+            }
+            const double pn = fma(beta, pi, tn);                   // p_k
+            x[i] = fma(alpha, pi, xi);
+            p[i] = pn;
+            if (PRE) {
+                r[i] = rn;
+                s[i] = sn;
+            }
+            t_n[i] = tn;
+            z_n[i] = zn;
+            acc[0] = fma(pn, sn, acc[0]);
+            acc[1] = fma(tn, sn, acc[1]);
+            acc[2] = fma(zn, sn, acc[2]);
+            acc[3] = fma(tn, rn, acc[3]);
+            if (PRE) acc[4] = fma(rn, rn, acc[4]);
+        }
+        int width;
+        const SlotIter it = slots_of(S, slice, lane, i, width);
+        double un = 0.0, wn = 0.0;
+#pragma unroll 2
+        for (int j = 0; j < width; ++j) {
+            const int c = it.column(j);
+            const double a = it.value(j);
+            const double tc = t_o[c], zc = z_o[c], wc = w_o[c], uc = u_o[c];
+            double tnc, znc;
+            if (PRE) {
+                const double dc = d[c];
+                tnc = fma(-alpha, zc, tc);
+                znc = fma(beta, zc, fma(-alpha, dc * uc, dc * wc));
+            } else {
+                tnc = fma(-alpha, zc, tc);
+                znc = fma(beta, zc, fma(-alpha, uc, wc));
+            }
+            un = fma(a, znc, un);
+            wn = fma(a, tnc, wn);
+        }
+        if (own) {
+            u_n[i] = un;
+            w_n[i] = wn;
+        }
+    }
+    write_partials<5>(acc, Pout, sp.Gs, blockIdx.x, lds);
+}
+
+// HS-CG, second kernel of an iteration: stage 2 of nu (beta, tests), then
+// s = A p' with p' = r~ + beta p at neighbours from r (final in this kernel)
+// and the previous p; writes p' (double-buffered) and s; partials of mu.
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_hs_fused(SellView S, Split sp, const State* __restrict__ in,
+                                                     State* __restrict__ out, double* __restrict__ hist,
+                                                     const double* __restrict__ PU, double* __restrict__ PS,
+                                                     FusedVecs f, int q)
+{
+    __shared__ double lds[kWaves * 2];
+    State st = *in;
+    if (st.done) {
+        if (writer()) *out = st;
+        return;
+    }
+    double t[2];
+    reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+    step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, writer());
+    if (writer()) *out = st;
+    if (st.done) return;
+    const double beta = st.beta;
+    const double* __restrict__ p_o = f.p[q];
+    double* __restrict__ p_n = f.p[1 - q];
+    const double* __restrict__ r = f.r[0];
+    double* __restrict__ s = f.s[0];
+    const double* __restrict__ d = f.d;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double acc[1] = {0.0};
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int64_t g = g0; g < g1; ++g) {
+        const int64_t slice = g * kWaves + w;
+        if (slice >= S.nslices) break;
+        const int64_t i = slice * kSlice + lane;
+        const bool own = i < S.n;
+        double pn = 0.0;
+        if (own) {
+            const double ri = r[i];
+            pn = fma(beta, p_o[i], PRE ? d[i] * ri : ri);
+            p_n[i] = pn;
+        }
+        int width;
+        const SlotIter it = slots_of(S, slice, lane, i, width);
+        double sn = 0.0;
+#pragma unroll 2
+        for (int j = 0; j < width; ++j) {
+            const int c = it.column(j);
+            const double rc = r[c];
+            sn = fma(it.value(j), fma(beta, p_o[c], PRE ? d[c] * rc : rc), sn);
+        }
+        if (own) {
+            s[i] = sn;
+            acc[0] = fma(pn, sn, acc[0]);
+        }
+    }
+    write_partials<1>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+}  // namespace
+
+hipError_t launch_fused_kernel(int variant, int pre, int j, int it, int& cur, const SellView& S, const Split& sp,
+                               const FusedVecs& f, const Bufs& B, double* PS2, hipStream_t st,
+                               const LaunchEvents* ev)
+{
+    const dim3 grid(sp.G), block(kBlock);
+    const int q = it & 1;
+    const int nxt = 1 - cur;
+    const int meurant = variant == kM || variant == kPipeM;
+    double* Pq[2] = {B.PS, PS2};
+    auto go = [&](auto kernel, auto... args) {
+        if (ev && ev->start)
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev->start, ev->stop, 0, args...);
+        else
+            hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+        return hipGetLastError();
+    };
+    hipError_t e = hipSuccess;
+    if (variant == kPR || variant == kM) {
+        e = pre ? go(k_pr_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
+                     Pq[1 - q], meurant, f, q)
+                : go(k_pr_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
+                     Pq[1 - q], meurant, f, q);
+        cur = nxt;
+    } else if (variant == kPipePR || variant == kPipeM) {
+        e = pre ? go(k_pipe_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
+                     Pq[1 - q], meurant, f, q)
+                : go(k_pipe_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
+                     Pq[1 - q], meurant, f, q);
+        cur = nxt;
+    } else {
+        // HS: the first kernel is the two-pass k_hs_xr on the current buffers
+        if (j == 0) return hipErrorInvalidValue;
+        e = pre ? go(k_hs_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)B.PU, B.PS,
+                     f, q)
+                : go(k_hs_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)B.PU, B.PS,
+                     f, q);
+        cur = nxt;
+    }
+    return e;
+}
+
+}  // namespace prcg

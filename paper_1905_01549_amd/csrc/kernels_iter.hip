@@ -30,6 +30,7 @@
 #include <hip/hip_ext.h>
 
 #include "prcg_device.h"
+#include "prcg_textbook.h"
 
 namespace prcg {
 
@@ -104,25 +105,32 @@ __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split 
     write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
 }
 
-// pipe-PR-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0.
+// pipe-PR-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0; the block
+// vectors (s~0, r~0) and (u0, w0) are filled as well.
 template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split sp, Vecs v)
 {
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     const double* st = PRE ? v.st : v.s;
+    const double* rt = PRE ? v.rt : v.r;
     for (int64_t g = g0; g < g1; ++g) {
         rows_of_group<LANES, 1>(S, C, g, st, nullptr, [&](int64_t i, double ui, double) {
+            const double si = v.s[i];
             v.u[i] = ui;
-            v.w[i] = v.s[i];
+            v.w[i] = si;
+            v.uw[i] = make_double2(ui, si);
+            v.zr[i] = make_double2(st[i], rt[i]);
         });
     }
 }
 
 // One workgroup: ||b||, the b = 0 case, and the first scalar step where the
 // variant's first iteration kernel does not perform it.
+// step0: 1 when this kernel performs the scalar step of k = 0 (pipe-PR
+// two-pass and HS); otherwise the first iteration kernel does.
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_init_finish(int variant, Split sp, const double* __restrict__ PB,
+__global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
                                                         const double* __restrict__ PS, State* __restrict__ out,
                                                         double* __restrict__ hist, double tol, int maxit)
 {
@@ -145,12 +153,12 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, Split sp, c
         st.zero_x = 1;
         st.rr = 0.0;
         if (w) hist[0] = 0.0;
-    } else if (variant == kPipePR || variant == kPipeM) {
+    } else if (step0 && (variant == kPipePR || variant == kPipeM)) {
         step_one_reduction(st, t, PRE, variant == kPipeM, hist, w);
     } else if (variant == kHS) {
         step_hs_nu(st, t[3], PRE ? t[4] : t[3], hist, w);
     }
-    // PR / M: the first update kernel performs the step for k = 0.
+    // otherwise the first iteration kernel performs the step for k = 0
     if (w) *out = st;
 }
 
@@ -293,52 +301,48 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double* __restrict__ x = v.x;
     double* __restrict__ r = v.r;
-    double* __restrict__ rt = v.rt;
     double* __restrict__ p = v.p;
     double* __restrict__ s = v.s;
-    double* __restrict__ stv = v.st;
-    const double* __restrict__ w = v.w;
-    const double* __restrict__ u = v.u;
+    double2* __restrict__ zr = v.zr;
+    const double2* __restrict__ uw = v.uw;
     const double* __restrict__ d = v.d;
     for (int64_t i = i0; i < i1; i += kBlock) {
-        const double pi = p[i], si = s[i], wi = w[i], ui = u[i], xi = x[i], ri = r[i];
-        double di = 0.0, sti_old = 0.0, rti_old = 0.0;
-        if (PRE) {
-            di = d[i];
-            sti_old = stv[i];
-            rti_old = rt[i];
-        }
-        const double rn = fma(-alpha, si, ri);
-        const double wpi = fma(-alpha, ui, wi);              // w'_k = w_{k-1} - alpha u_{k-1}
-        const double snew = fma(beta, si, wpi);              // s_k = w'_k + beta s_{k-1}
+        const double pi = p[i], xi = x[i];
+        const double2 zri = zr[i], uwi = uw[i];
+        const double ui = uwi.x, wi = uwi.y;
+        const double si = PRE ? s[i] : zri.x;
+        const double ri = PRE ? r[i] : zri.y;
+        const double rn = fma(-alpha, si, ri);                 // r_k
+        const double snew = fma(beta, si, fma(-alpha, ui, wi));  // s_k = w'_k + beta s_{k-1}
         double rti = rn, sti = snew;
         if (PRE) {
-            rti = fma(-alpha, sti_old, rti_old);             // r~_k = r~_{k-1} - alpha s~_{k-1}
-            const double wtpi = fma(-alpha, di * ui, di * wi);  // w~'_k = w~_{k-1} - alpha u~_{k-1}
-            sti = fma(beta, sti_old, wtpi);                  // s~_k = w~'_k + beta s~_{k-1}
+            const double di = d[i];
+            rti = fma(-alpha, zri.x, zri.y);                   // r~_k = r~_{k-1} - alpha s~_{k-1}
+            sti = fma(beta, zri.x, fma(-alpha, di * ui, di * wi));  // s~_k = w~'_k + beta s~_{k-1}
         }
-        const double pnew = fma(beta, pi, rti);              // p_k = r~_k + beta p_{k-1}
+        const double pnew = fma(beta, pi, rti);                // p_k
         x[i] = fma(alpha, pi, xi);
-        r[i] = rn;
-        if (PRE) {
-            rt[i] = rti;
-            stv[i] = sti;
-        }
         p[i] = pnew;
-        s[i] = snew;
-        acc[0] = fma(pnew, snew, acc[0]);                    // mu_k    = <p_k, s_k>
-        acc[1] = fma(rti, snew, acc[1]);                     // sigma_k = <r~_k, s_k>
-        acc[2] = fma(sti, snew, acc[2]);                     // gamma_k = <s~_k, s_k>
-        acc[3] = fma(rti, rn, acc[3]);                       // nu_k    = <r~_k, r_k>
+        if (PRE) {
+            r[i] = rn;
+            s[i] = snew;
+        }
+        zr[i] = make_double2(sti, rti);
+        acc[0] = fma(pnew, snew, acc[0]);                      // mu_k    = <p_k, s_k>
+        acc[1] = fma(rti, snew, acc[1]);                       // sigma_k = <r~_k, s_k>
+        acc[2] = fma(sti, snew, acc[2]);                       // gamma_k = <s~_k, s_k>
+        acc[3] = fma(rti, rn, acc[3]);                         // nu_k    = <r~_k, r_k>
         if (PRE) acc[4] = fma(rn, rn, acc[4]);
     }
     write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
 }
 
-// u_k = A s~_k and w_k = A r~_k (the recompute) in one pass over A, run by
-// workgroups 1..G, while workgroup 0 reduces the inner products of
-// iteration k and performs the scalar step (Section 2.2.1: the products and
-// the reduction proceed simultaneously).
+// u_k = A s~_k and w_k = A r~_k (the recompute) in one pass over A with the
+// block vector (s~, r~).  Workgroup 0 also reduces the inner products of
+// iteration k and performs the scalar step once its share of the product is
+// issued (Section 2.2.1: the products and the reduction proceed at the same
+// time); the grid stays at G workgroups so every compute unit gets the same
+// share of the product.
 template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
@@ -346,6 +350,16 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
 {
     __shared__ double lds[kWaves * 5];
     State st = *in;
+    if (!st.done) {
+        int64_t g0, g1;
+        chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+        double2* __restrict__ uw = v.uw;
+        for (int64_t g = g0; g < g1; ++g) {
+            rows_of_group_pair<LANES>(S, C, g, v.zr, [&](int64_t i, double ui, double wi) {
+                uw[i] = make_double2(ui, wi);
+            });
+        }
+    }
     if (blockIdx.x == 0) {
         if (!st.done) {
             double t[5];
@@ -353,18 +367,6 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
             step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
         }
         if (threadIdx.x == 0) *out = st;
-        return;
-    }
-    if (st.done) return;
-    int64_t g0, g1;
-    chunk_of(blockIdx.x - 1, sp.G, sp.ngroups, g0, g1);
-    const double* st_vec = PRE ? v.st : v.s;
-    const double* rt_vec = PRE ? v.rt : v.r;
-    for (int64_t g = g0; g < g1; ++g) {
-        rows_of_group<LANES, 2>(S, C, g, st_vec, rt_vec, [&](int64_t i, double ui, double wi) {
-            v.u[i] = ui;
-            v.w[i] = wi;
-        });
     }
 }
 
@@ -562,14 +564,17 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     });
     if (e != hipSuccess) return e;
     return with_pre(pre, [&](auto P) {
-        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, sp, B.PB,
-                           B.PS, B.S[0], B.hist, tol, (int)maxit);
+        const int step0 = variant == kHS || ((variant == kPipePR || variant == kPipeM) && !sp.fused);
+        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
+                           B.PB, B.PS, B.S[0], B.hist, tol, (int)maxit);
         return hipGetLastError();
     });
 }
 
 int iter_kernel_count(int variant, const Split& sp)
 {
+    if (sp.textbook && variant == kHS) return textbook_kernel_count(sp.textbook_pre);
+    if (sp.fused) return variant == kHS ? 2 : 1;
     if (variant == kHS) return 3;
     if ((variant == kPR || variant == kM) && sp.stage2) return 3;
     return 2;
@@ -577,6 +582,11 @@ int iter_kernel_count(int variant, const Split& sp)
 
 const char* iter_kernel_name(int variant, const Split& sp, int j)
 {
+    if (sp.textbook && variant == kHS) return textbook_kernel_name(sp.textbook_pre, j);
+    if (sp.fused) {
+        if (variant == kHS) return j == 0 ? "k_hs_xr" : "k_hs_fused";
+        return (variant == kPR || variant == kM) ? "k_pr_fused" : "k_pipe_fused";
+    }
     switch (variant) {
     case kHS: return j == 0 ? "k_hs_xr" : (j == 1 ? "k_hs_p" : "k_hs_spmv");
     case kPR:
@@ -588,7 +598,8 @@ const char* iter_kernel_name(int variant, const Split& sp, int j)
 }
 
 hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellView* sell, const CsrView* csr,
-                              const Split& sp, const Vecs& v, const Bufs& B, hipStream_t st, const LaunchEvents* ev)
+                              const Split& sp, const Vecs& v, const Bufs& B, hipStream_t st, const LaunchEvents* ev,
+                              int)
 {
     const SellView S = sell_or_empty(sell);
     const CsrView C = csr_or_empty(csr);
@@ -622,7 +633,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 if (j == 0) {
                     launch(k_pipe_update<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.PS, v);
                 } else {
-                    launch(k_pipe_spmv<LL, PP>, dim3(sp.G + 1), block, st, ev, S, C, sp, (const State*)B.S[cur],
+                    launch(k_pipe_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
                            B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
                     cur = nxt;
                 }

@@ -21,6 +21,8 @@
 #include "../../include/prcg.h"
 #include "batched.h"
 #include "prcg_common.h"
+#include "prcg_fused.h"
+#include "prcg_textbook.h"
 
 using namespace prcg;
 
@@ -43,12 +45,6 @@ prcg_status fail(prcg_status s, const std::string& msg)
     } while (0)
 
 constexpr int kGraphIters = 16;  // iterations per graph replay (even: the state copy returns to 0)
-
-int env_int(const char* name, int dflt)
-{
-    const char* v = std::getenv(name);
-    return v && *v ? std::atoi(v) : dflt;
-}
 
 bool is_device_pointer(const void* p)
 {
@@ -86,7 +82,10 @@ struct prcg_matrix_s {
     double* d = nullptr;
     Split sp{};
     // solver workspace
-    double* vecs = nullptr;  // x r rt p s st w u spare
+    double* vecs = nullptr;  // x r rt p s st w u spare | second copies r rt p s st w u
+    int kernels_mode = 0;    // PRCG_KERNELS_*
+    double2* pairs = nullptr;  // pipe-PR block vectors: (s~, r~) then (u, w)
+    int grid_opt = 1024;     // largest workgroup count
     State* S = nullptr;      // two copies
     double* hist = nullptr;
     int64_t hist_cap = 0;
@@ -116,9 +115,25 @@ struct prcg_matrix_s {
         v.w = vecs + 6 * n8;
         v.u = vecs + 7 * n8;
         v.d = d;
+        v.zr = pairs;
+        v.uw = pairs + n8;
         return v;
     }
     double* spare() const { return vecs + 8 * (size_t)n; }
+
+    FusedVecs fused_view() const
+    {
+        const size_t n8 = (size_t)n;
+        FusedVecs f;
+        f.x = vecs;
+        double** two[] = {f.r, f.rt, f.p, f.s, f.st, f.w, f.u};
+        for (int q = 0; q < 7; ++q) {
+            two[q][0] = vecs + (size_t)(1 + q) * n8;
+            two[q][1] = vecs + (size_t)(9 + q) * n8;
+        }
+        f.d = d;
+        return f;
+    }
 
     Bufs bufs() const
     {
@@ -127,8 +142,9 @@ struct prcg_matrix_s {
         B.S[1] = S + 1;
         B.hist = hist;
         B.PS = partials;
-        B.PU = partials + (size_t)kMaxDots * sp.Gs;
-        B.PB = partials + (size_t)(kMaxDots + 2) * sp.Gs;
+        B.PU = partials + (size_t)kMaxDots * kMaxGrid;
+        B.PB = partials + (size_t)(kMaxDots + 2) * kMaxGrid;
+        B.PS2 = partials + (size_t)(kMaxDots + 3) * kMaxGrid;
         return B;
     }
 };
@@ -172,6 +188,8 @@ struct prcg_batch_s {
         v.w = vecs + 6 * n8;
         v.u = vecs + 7 * n8;
         v.d = A->d;
+        v.zr = nullptr;
+        v.uw = nullptr;
         return v;
     }
     BatchView view() const
@@ -212,7 +230,7 @@ void free_matrix(prcg_matrix A)
     for (auto& e : A->ev)
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol, A->sval, A->d,
-                   A->vecs, A->S, A->hist, A->partials, A->dflags};
+                   A->vecs, A->pairs, A->S, A->hist, A->partials, A->dflags};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (A->hstate) (void)hipHostFree(A->hstate);
@@ -229,19 +247,21 @@ void invalidate_graphs(prcg_matrix A)
 }
 
 // Choose the work split: G workgroups (multiple of 8 when G >= 8, so every
-// XCD gets the same number), at most PRCG_GRID (default 1024, cap kMaxGrid).
-Split make_split(int64_t n, int lanes)
+// XCD gets the same number), at most gmax_opt (PRCG_OPT_GRID, default 1024).
+Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
 {
     Split sp{};
     sp.n = n;
     sp.lanes = lanes;
     sp.ngroups = (n + kGroupRows - 1) / kGroupRows;
-    int gmax = std::min(kMaxGrid, std::max(8, env_int("PRCG_GRID", 1024)));
+    int gmax = std::min(kMaxGrid, std::max(8, gmax_opt));
     int64_t G = std::min<int64_t>(sp.ngroups, gmax);
     if (G >= 8) G -= G % 8;
     sp.G = (int)std::max<int64_t>(G, 1);
     sp.Gs = (sp.G + 63) / 64 * 64;
-    sp.stage2 = env_int("PRCG_STAGE2", 0) != 0 ? 1 : 0;
+    sp.fused = (kernels_mode == PRCG_KERNELS_FUSED && lanes == 1) ? 1 : 0;
+    sp.stage2 = kernels_mode == PRCG_KERNELS_TWO_PASS_STAGE2 ? 1 : 0;
+    sp.textbook = kernels_mode == PRCG_KERNELS_TEXTBOOK ? 1 : 0;
     return sp;
 }
 
@@ -265,17 +285,35 @@ prcg_status ensure_hist(prcg_matrix A, int64_t need)
     return PRCG_OK;
 }
 
+// Kernel j of the iteration at position `it` (its parity selects the buffer
+// copies of the fused kernels).
+hipError_t launch_iteration(prcg_matrix A, int variant, int j, int it, int& cur, hipStream_t st,
+                            const LaunchEvents* ev = nullptr)
+{
+    const Bufs B = A->bufs();
+    if (A->sp.textbook && variant == kHS)
+        return launch_textbook_kernel(A->precond, j, cur, A->sellp(), A->csrp(), A->sp, A->vecs_view(), B, st, ev);
+    if (A->sp.fused) {
+        const FusedVecs f = A->fused_view();
+        if (variant == kHS && j == 0) {
+            Vecs v = A->vecs_view();
+            v.p = f.p[it & 1];
+            return launch_iter_kernel(variant, A->precond, 0, cur, A->sellp(), A->csrp(), A->sp, v, B, st, ev);
+        }
+        return launch_fused_kernel(variant, A->precond, j, it, cur, A->sell_storage, A->sp, f, B, B.PS2, st, ev);
+    }
+    return launch_iter_kernel(variant, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, A->vecs_view(), B, st, ev);
+}
+
 prcg_status build_graph(prcg_matrix A, int variant)
 {
     if (A->graph[variant]) return PRCG_OK;
-    const Vecs v = A->vecs_view();
-    const Bufs B = A->bufs();
     HIP_TRY(hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal));
     int cur = 0;
     hipError_t err = hipSuccess;
     for (int it = 0; it < kGraphIters && err == hipSuccess; ++it)
         for (int j = 0; j < iter_kernel_count(variant, A->sp) && err == hipSuccess; ++j)
-            err = launch_iter_kernel(variant, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, v, B, A->capture);
+            err = launch_iteration(A, variant, j, it, cur, A->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(A->capture, &g);
     if (err != hipSuccess) {
@@ -473,21 +511,47 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
                               A->slice_meta, A->soff, A->scol, A->sval, 1, A->stream));
         HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
     }
-    A->sp = make_split(n, lanes);
+    A->kernels_mode = PRCG_KERNELS_TWO_PASS;
+    A->grid_opt = 1024;
+    A->sp = make_split(n, lanes, A->grid_opt, A->kernels_mode);
+    A->sp.textbook_pre = precond;
     A->sell_storage = A->sell();
     A->csr_storage = A->csr();
 
-    HTRY(hipMalloc(&A->vecs, sizeof(double) * 9 * (size_t)n));
-    HTRY(hipMemsetAsync(A->vecs, 0, sizeof(double) * 9 * (size_t)n, A->stream));
+    HTRY(hipMalloc(&A->vecs, sizeof(double) * 16 * (size_t)n));
+    HTRY(hipMemsetAsync(A->vecs, 0, sizeof(double) * 16 * (size_t)n, A->stream));
+    HTRY(hipMalloc(&A->pairs, sizeof(double2) * 2 * (size_t)n));
     HTRY(hipMalloc(&A->S, sizeof(State) * 2));
     HTRY(hipMemsetAsync(A->S, 0, sizeof(State) * 2, A->stream));
-    HTRY(hipMalloc(&A->partials, sizeof(double) * (kMaxDots + 3) * (size_t)A->sp.Gs));
+    // partials sized for the largest grid, so the grid can change later
+    HTRY(hipMalloc(&A->partials, sizeof(double) * (2 * kMaxDots + 3) * (size_t)kMaxGrid));
     HTRY(hipStreamSynchronize(A->stream));
     TRY(ensure_hist(A, 1024));
     *out = A;
     return PRCG_OK;
 #undef TRY
 #undef HTRY
+}
+
+prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    if (option == PRCG_OPT_KERNELS) {
+        if (value < PRCG_KERNELS_FUSED || value > PRCG_KERNELS_TEXTBOOK)
+            return fail(PRCG_EINVAL, "unknown kernel structure");
+        A->kernels_mode = value;
+    } else if (option == PRCG_OPT_GRID) {
+        if (value < 8 || value > kMaxGrid) return fail(PRCG_EINVAL, "grid must be in [8, 1024]");
+        A->grid_opt = value;
+    } else {
+        return fail(PRCG_EINVAL, "unknown option");
+    }
+    HIP_TRY(hipSetDevice(A->device));
+    HIP_TRY(hipStreamSynchronize(A->stream));
+    A->sp = make_split(A->n, A->sp.lanes, A->grid_opt, A->kernels_mode);
+    A->sp.textbook_pre = A->precond;
+    invalidate_graphs(A);
+    return PRCG_OK;
 }
 
 prcg_status prcg_set_stream(prcg_matrix A, void* hip_stream)
@@ -559,6 +623,7 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
     props->lanes_per_row = A->sp.lanes;
     props->stored_entries = A->sp.lanes == 1 ? A->stored : A->nnz;
     props->grid = A->sp.G;
+    props->kernels = A->sp.fused ? PRCG_KERNELS_FUSED : A->kernels_mode;
     props->block = kBlock;
     // bytes one product reads: values, the column indices of packed slices,
     // the offsets of aligned slices and the per-slice metadata
@@ -572,11 +637,13 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
 }
 
 prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, double* ms_per_launch,
-                              char (*names)[48], int32_t* nkernels)
+                              char (*names)[48], int32_t capacity, int32_t* nkernels)
 {
     if (!A || !ms_per_launch || !nkernels) return fail(PRCG_EINVAL, "null argument");
     if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
     if (iters < 1) return fail(PRCG_EINVAL, "iters must be >= 1");
+    if (capacity < iter_kernel_count(v, A->sp))
+        return fail(PRCG_EINVAL, "capacity is smaller than the number of kernels per iteration");
     HIP_TRY(hipSetDevice(A->device));
     prcg_status s = ensure_hist(A, (int64_t)iters + 2);
     if (s != PRCG_OK) return s;
@@ -597,7 +664,7 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
         for (int j = 0; j < nk && err == hipSuccess; ++j) {
             const size_t q = (size_t)2 * (it * nk + j);
             const LaunchEvents le{ev[q], ev[q + 1]};
-            err = launch_iter_kernel(v, A->precond, j, cur, A->sellp(), A->csrp(), A->sp, vv, B, A->stream, &le);
+            err = launch_iteration(A, v, j, it, cur, A->stream, &le);
         }
     if (err == hipSuccess) err = hipStreamSynchronize(A->stream);
     std::vector<double> tot((size_t)nk, 0.0);

@@ -73,8 +73,11 @@ struct Split {
     int Gs;         // stride between reduction values in a partials buffer
     int64_t ngroups;
     int lanes;      // 1 = SELL-64, else lanes per row of vector CSR
-    int stage2;     // PR/M: 0 = every update workgroup reduces the partials,
-                    // 1 = a one-workgroup kernel reduces them before the update
+    int stage2;     // PR/M two-pass: 0 = every update workgroup reduces the
+                    // partials, 1 = a one-workgroup kernel reduces them first
+    int fused;      // 1 = fused kernels (SELL-64 only), 0 = two-pass kernels
+    int textbook;   // 1 = HS-CG as one kernel per algorithm line
+    int textbook_pre;  // preconditioned (the textbook kernel list depends on it)
 };
 
 // ---- setup kernels (kernels_setup.hip) ----
@@ -102,14 +105,21 @@ hipError_t launch_spmv(const SellView* sell, const CsrView* csr, const Split& sp
 struct Vecs {
     double *x, *r, *rt, *p, *s, *st, *w, *u;
     const double* d;  // Jacobi reciprocal diagonal or nullptr
+    // pipe-PR-CG block vectors (two-pass kernels): zr[i] = (s~_i, r~_i) and
+    // uw[i] = (u_i, w_i), so that the pair of products [A s~, A r~] gathers
+    // one 16-byte entry per stored matrix entry (Section 6 reads A once for
+    // the block vector [s, r]).
+    double2* zr;
+    double2* uw;
 };
 
 struct Bufs {
     State* S[2];
     double* hist;
-    double* PS;  // [mu, sigma, gamma, nu, rr] partials
-    double* PU;  // [nu, rr] partials (HS)
-    double* PB;  // [bb] or [tt] partials
+    double* PS;   // [mu, sigma, gamma, nu, rr] partials
+    double* PU;   // [nu, rr] partials (HS)
+    double* PB;   // [bb] or [tt] partials
+    double* PS2;  // second copy of PS (fused kernels alternate between the two)
 };
 
 hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView* csr, const Split& sp,
@@ -126,7 +136,7 @@ struct LaunchEvents {
 };
 hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellView* sell,
                               const CsrView* csr, const Split& sp, const Vecs& v, const Bufs& B,
-                              hipStream_t st, const LaunchEvents* ev = nullptr);
+                              hipStream_t st, const LaunchEvents* ev = nullptr, int p_copy = 0);
 hipError_t launch_final(const SellView* sell, const CsrView* csr, const Split& sp, const Vecs& v,
                         const Bufs& B, int cur, const double* b, double* xout, hipStream_t st);
 

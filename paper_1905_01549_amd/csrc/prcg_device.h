@@ -88,41 +88,118 @@ __device__ __forceinline__ void chunk_of(int b, int G, int64_t ngroups, int64_t&
     g1 = (int64_t)(c + 1) * ngroups / G;
 }
 
-// Products of one SELL-64 row with NX vectors (entries summed in stored
-// column order; zero slots add nothing).
+// Products of one SELL-64 row (entries summed in stored column order; zero
+// slots add nothing).  The slots are consumed in fixed-size pieces: K
+// values, K columns and K gathered entries are loaded before the first of
+// the K multiply-adds, so a piece costs one memory round trip.  Full pieces
+// of kChunk slots come first, then one piece of the remaining 1..7 slots,
+// selected by a switch on the (wavefront-uniform) slot count, so that no
+// load sits behind a per-slot branch.
+constexpr int kChunk = 8;
+
+// Column of slot j: offset-aligned (off != nullptr, clamped into [0, n) so
+// zero slots of boundary rows read a valid entry) or packed (explicit).
+struct SlotCols {
+    const int32_t* off;
+    const int32_t* col;
+    int row, last;
+    __device__ __forceinline__ int operator()(int j) const
+    {
+        return off ? min(max(row + off[j], 0), last) : col[(int64_t)j * 64];
+    }
+};
+
+// K slots starting at j0; G(c) returns the gathered entry (double or
+// double2) at column c, F(acc, a, g) accumulates.
+template <int K, class T, class Gather, class Acc>
+__device__ __forceinline__ void slot_piece(const double* __restrict__ v, const SlotCols& cols, int j0, Gather&& gather,
+                                           Acc&& acc)
+{
+    int c[K];
+    double a[K];
+    T g[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) c[u] = cols(j0 + u);
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        a[u] = v[(int64_t)(j0 + u) * 64];
+        g[u] = gather(c[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) acc(a[u], g[u]);
+}
+
+template <class T, class Gather, class Acc>
+__device__ __forceinline__ void slot_loop(const double* __restrict__ v, const SlotCols& cols, int width,
+                                          Gather&& gather, Acc&& acc)
+{
+    int j0 = 0;
+    for (; j0 + kChunk <= width; j0 += kChunk) slot_piece<kChunk, T>(v, cols, j0, gather, acc);
+    switch (width - j0) {
+    case 1: slot_piece<1, T>(v, cols, j0, gather, acc); break;
+    case 2: slot_piece<2, T>(v, cols, j0, gather, acc); break;
+    case 3: slot_piece<3, T>(v, cols, j0, gather, acc); break;
+    case 4: slot_piece<4, T>(v, cols, j0, gather, acc); break;
+    case 5: slot_piece<5, T>(v, cols, j0, gather, acc); break;
+    case 6: slot_piece<6, T>(v, cols, j0, gather, acc); break;
+    case 7: slot_piece<7, T>(v, cols, j0, gather, acc); break;
+    default: break;
+    }
+}
+
+__device__ __forceinline__ SlotCols slot_cols(const SellView& A, int64_t slice, int lane, int64_t row64,
+                                              int64_t& base, int& width)
+{
+    base = A.slice_ptr[slice];
+    width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
+    const int meta = A.slice_meta[slice];
+    SlotCols c;
+    c.off = meta >= 0 ? A.soff + meta : nullptr;
+    c.col = A.col + base + lane;
+    c.row = (int)row64;
+    c.last = (int)A.n - 1;
+    return c;
+}
+
 template <int NX>
 __device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, int64_t row64,
                                          const double* __restrict__ x0, const double* __restrict__ x1, double& y0,
                                          double& y1)
 {
-    const int64_t base = A.slice_ptr[slice];
-    const int width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
-    const int meta = A.slice_meta[slice];
+    int64_t base;
+    int width;
+    const SlotCols cols = slot_cols(A, slice, lane, row64, base, width);
     const double* __restrict__ v = A.val + base + lane;
     double a0 = 0.0, a1 = 0.0;
-    if (meta >= 0) {
-        // offset-aligned: the column is row + offset, clamped into [0, n) so
-        // that zero slots of boundary rows read a valid entry
-        const int row = (int)row64;
-        const int last = (int)A.n - 1;
-        const int32_t* __restrict__ off = A.soff + meta;
-#pragma unroll 4
-        for (int j = 0; j < width; ++j) {
-            const int cj = min(max(row + off[j], 0), last);
-            const double vj = v[(int64_t)j * 64];
-            a0 = fma(vj, x0[cj], a0);
-            if (NX == 2) a1 = fma(vj, x1[cj], a1);
-        }
+    if (NX == 1) {
+        slot_loop<double>(v, cols, width, [&](int c) { return x0[c]; },
+                          [&](double a, double g) { a0 = fma(a, g, a0); });
     } else {
-        const int32_t* __restrict__ c = A.col + base + lane;
-#pragma unroll 4
-        for (int j = 0; j < width; ++j) {
-            const int cj = c[(int64_t)j * 64];
-            const double vj = v[(int64_t)j * 64];
-            a0 = fma(vj, x0[cj], a0);
-            if (NX == 2) a1 = fma(vj, x1[cj], a1);
-        }
+        slot_loop<double2>(v, cols, width, [&](int c) { return make_double2(x0[c], x1[c]); },
+                           [&](double a, double2 g) {
+                               a0 = fma(a, g.x, a0);
+                               a1 = fma(a, g.y, a1);
+                           });
     }
+    y0 = a0;
+    y1 = a1;
+}
+
+// Both products of one SELL-64 row with a block vector of pairs:
+// (y0, y1) = sum_j a_ij (xy_j.x, xy_j.y), entries in stored column order.
+__device__ __forceinline__ void sell_row_pair(const SellView& A, int64_t slice, int lane, int64_t row64,
+                                              const double2* __restrict__ xy, double& y0, double& y1)
+{
+    int64_t base;
+    int width;
+    const SlotCols cols = slot_cols(A, slice, lane, row64, base, width);
+    const double* __restrict__ v = A.val + base + lane;
+    double a0 = 0.0, a1 = 0.0;
+    slot_loop<double2>(v, cols, width, [&](int c) { return xy[c]; },
+                       [&](double a, double2 g) {
+                           a0 = fma(a, g.x, a0);
+                           a1 = fma(a, g.y, a1);
+                       });
     y0 = a0;
     y1 = a1;
 }
@@ -169,6 +246,51 @@ __device__ __forceinline__ void csr_group(const CsrView& A, int64_t g, const dou
             if (NX == 2) a1 += __shfl_xor(a1, off, 64);
         }
         if (sub == 0 && row < A.n) f(row, a0, a1);
+    }
+}
+
+// Vector-CSR product with a block vector of pairs.
+template <int L, class F>
+__device__ __forceinline__ void csr_group_pair(const CsrView& A, int64_t g, const double2* __restrict__ xy, F&& f)
+{
+    const int sub = threadIdx.x % L;
+    const int team = threadIdx.x / L;
+    for (int q = 0; q < L; ++q) {
+        const int64_t row = g * kGroupRows + (int64_t)q * (kBlock / L) + team;
+        double a0 = 0.0, a1 = 0.0;
+        if (row < A.n) {
+            const int32_t e1 = A.row_ptr[row + 1];
+            for (int32_t e = A.row_ptr[row] + sub; e < e1; e += L) {
+                const double ve = A.val[e];
+                const double2 xe = xy[A.col[e]];
+                a0 = fma(ve, xe.x, a0);
+                a1 = fma(ve, xe.y, a1);
+            }
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) {
+            a0 += __shfl_xor(a0, off, 64);
+            a1 += __shfl_xor(a1, off, 64);
+        }
+        if (sub == 0 && row < A.n) f(row, a0, a1);
+    }
+}
+
+template <int LANES, class F>
+__device__ __forceinline__ void rows_of_group_pair(const SellView& S, const CsrView& C, int64_t g,
+                                                   const double2* __restrict__ xy, F&& f)
+{
+    if constexpr (LANES == 1) {
+        const int w = uniform(threadIdx.x >> 6);
+        const int64_t slice = g * kWaves + w;
+        if (slice >= S.nslices) return;
+        const int lane = threadIdx.x & 63;
+        const int64_t row = slice * kSlice + lane;
+        double y0, y1;
+        sell_row_pair(S, slice, lane, row, xy, y0, y1);
+        if (row < S.n) f(row, y0, y1);
+    } else {
+        csr_group_pair<LANES>(C, g, xy, f);
     }
 }
 

@@ -24,7 +24,10 @@ VARIANTS = {"hs": PRCG_HS, "pr": PRCG_PR, "pipe_pr": PRCG_PIPE_PR, "m": PRCG_M, 
 PRECONDS = {"none": 0, "jacobi": 1}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem", -3: "edevice"}
 
-EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_stream", "prcg_spmv", "prcg_solve",
+KERNELS = {"fused": 0, "two_pass": 1, "two_pass_stage2": 2, "textbook": 3}
+OPT_KERNELS, OPT_GRID = 0, 1
+
+EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
             "prcg_time_kernels", "prcg_get_props", "prcg_create_batch", "prcg_solve_batched",
             "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config")
 
@@ -44,7 +47,7 @@ class prcg_matrix_props(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("stored_entries", ctypes.c_int64),
                 ("format", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
-                ("aligned_slices_frac", ctypes.c_double)]
+                ("aligned_slices_frac", ctypes.c_double), ("kernels", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -58,15 +61,22 @@ def load_library(path: str = LIB_PATH):
         return _LIB
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1905_01549_amd.build`")
+    # torch ships its own HIP runtime; load it first so that the library binds
+    # to the same one (device pointers from torch are then recognised)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "prcg_create_csr": (i32, [i64, i64, _VP, _VP, _VP, i32, _VP, ctypes.POINTER(_VP)]),
         "prcg_set_values": (i32, [_VP, _VP]),
         "prcg_set_stream": (i32, [_VP, _VP]),
+        "prcg_set_option": (i32, [_VP, i32, i32]),
         "prcg_spmv": (i32, [_VP, _VP, _VP]),
         "prcg_solve": (i32, [_VP, i32, _VP, _VP, dbl, i32, ctypes.POINTER(prcg_info), _VP]),
-        "prcg_time_kernels": (i32, [_VP, i32, i32, _VP, _VP, ctypes.POINTER(i32)]),
+        "prcg_time_kernels": (i32, [_VP, i32, i32, _VP, _VP, i32, ctypes.POINTER(i32)]),
         "prcg_get_props": (i32, [_VP, ctypes.POINTER(prcg_matrix_props)]),
         "prcg_create_batch": (i32, [_VP, i32, _VP, ctypes.POINTER(_VP)]),
         "prcg_solve_batched": (i32, [_VP, i32, _VP, _VP, dbl, i32, _VP, _VP]),
@@ -103,6 +113,10 @@ def prcg_set_values(A, values):
     _check(load_library().prcg_set_values(A, values))
 
 
+def prcg_set_option(A, option, value):
+    _check(load_library().prcg_set_option(A, option, value))
+
+
 def prcg_set_stream(A, hip_stream):
     _check(load_library().prcg_set_stream(A, hip_stream))
 
@@ -117,11 +131,11 @@ def prcg_solve(A, variant, b, x, tol, maxit, info=None, history=None) -> int:
                   allow_numeric=True)
 
 
-def prcg_time_kernels(A, variant, iters):
-    ms = (ctypes.c_double * 8)()
-    names = (ctypes.c_char * (8 * 48))()
+def prcg_time_kernels(A, variant, iters, capacity: int = 16):
+    ms = (ctypes.c_double * capacity)()
+    names = (ctypes.c_char * (capacity * 48))()
     nk = ctypes.c_int32(0)
-    _check(load_library().prcg_time_kernels(A, variant, iters, ms, names, ctypes.byref(nk)))
+    _check(load_library().prcg_time_kernels(A, variant, iters, ms, names, capacity, ctypes.byref(nk)))
     raw = bytes(names)
     return [(raw[48 * j:48 * (j + 1)].split(b"\0")[0].decode(), ms[j]) for j in range(nk.value)]
 
@@ -231,6 +245,14 @@ class Matrix:
     @property
     def props(self) -> prcg_matrix_props:
         return prcg_get_props(self.handle)
+
+    def set_kernels(self, mode: str):
+        """Kernel structure: "two_pass" (default), "fused", "two_pass_stage2" or
+        "textbook" (HS-CG one kernel per algorithm line)."""
+        prcg_set_option(self.handle, OPT_KERNELS, KERNELS[mode])
+
+    def set_grid(self, g: int):
+        prcg_set_option(self.handle, OPT_GRID, int(g))
 
     def set_values(self, values):
         v = _dev(values, _torch().float64)

@@ -19,22 +19,50 @@ KERNEL_WORDS = {
     ("pipe_pr", False): [("k_pipe_update", 6, 4, False), ("k_pipe_spmv", 2, 2, True)],
     ("pipe_pr", True): [("k_pipe_update", 9, 6, False), ("k_pipe_spmv", 2, 2, True)],
 }
+# fused structure (one kernel per PR / pipe-PR iteration, two per HS):
+# neighbour recomputation reads each double-buffered vector once
+KERNEL_WORDS_FUSED = {
+    ("hs", False): [("k_hs_xr", 4, 2, False), ("k_hs_fused", 2, 2, True)],
+    ("hs", True): [("k_hs_xr", 5, 2, False), ("k_hs_fused", 3, 2, True)],
+    ("pr", False): [("k_pr_fused", 4, 4, True)],
+    ("pr", True): [("k_pr_fused", 6, 5, True)],
+    ("pipe_pr", False): [("k_pipe_fused", 6, 6, True)],
+    ("pipe_pr", True): [("k_pipe_fused", 9, 8, True)],
+}
+# textbook HS-CG: one kernel per line of Alg. 1 (a dot of a vector with
+# itself reads it once)
+KERNEL_WORDS_TEXTBOOK = {
+    ("hs", False): [("k_tb_mu", 0, 0, False), ("k_tb_axpy_x", 2, 1, False), ("k_tb_axpy_r", 2, 1, False),
+                    ("k_tb_dot_nu", 1, 0, False), ("k_tb_nu", 0, 0, False), ("k_tb_xpay_p", 2, 1, False),
+                    ("k_tb_spmv", 1, 1, True), ("k_tb_dot_mu", 2, 0, False)],
+    ("hs", True): [("k_tb_mu", 0, 0, False), ("k_tb_axpy_x", 2, 1, False), ("k_tb_axpy_r", 2, 1, False),
+                   ("k_tb_prec", 2, 1, False), ("k_tb_dot_nu", 2, 0, False), ("k_tb_dot_rr", 1, 0, False),
+                   ("k_tb_nu", 0, 0, False), ("k_tb_xpay_p", 2, 1, False), ("k_tb_spmv", 1, 1, True),
+                   ("k_tb_dot_mu", 2, 0, False)],
+}
+for _tab in (KERNEL_WORDS_FUSED,):
+    for _j in (False, True):
+        _tab[("m", _j)] = _tab[("pr", _j)]
+        _tab[("pipe_m", _j)] = _tab[("pipe_pr", _j)]
 KERNEL_WORDS[("m", False)] = KERNEL_WORDS[("pr", False)]
 KERNEL_WORDS[("m", True)] = KERNEL_WORDS[("pr", True)]
 KERNEL_WORDS[("pipe_m", False)] = KERNEL_WORDS[("pipe_pr", False)]
 KERNEL_WORDS[("pipe_m", True)] = KERNEL_WORDS[("pipe_pr", True)]
 
 
-def kernel_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int) -> dict:
+def kernel_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int, fused: bool = False,
+                 textbook: bool = False) -> dict:
     """Algorithmic bytes per launch of each kernel of one iteration."""
     out = {}
-    for name, r, w, mat in KERNEL_WORDS[(variant, jacobi)]:
+    table = KERNEL_WORDS_TEXTBOOK if textbook else (KERNEL_WORDS_FUSED if fused else KERNEL_WORDS)
+    for name, r, w, mat in table[(variant, jacobi)]:
         out[name] = 8 * n * (r + w) + (matrix_bytes if mat else 0)
     return out
 
 
-def iteration_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int) -> int:
-    return sum(kernel_bytes(variant, jacobi, n, matrix_bytes).values())
+def iteration_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int, fused: bool = False,
+                    textbook: bool = False) -> int:
+    return sum(kernel_bytes(variant, jacobi, n, matrix_bytes, fused, textbook).values())
 
 
 def csr_matrix_bytes(n: int, nnz: int) -> int:

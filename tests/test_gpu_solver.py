@@ -43,8 +43,13 @@ def hist_close(h, ho, rtol=1e-8):
     return bool(np.all(np.abs(h - ho) <= rtol * ho + EPS))
 
 
-def gpu_matrix(prcg, A, precond="none"):
-    return prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
+STRUCTURES = ["fused", "two_pass", "two_pass_stage2", "textbook"]
+
+
+def gpu_matrix(prcg, A, precond="none", kernels="fused"):
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
+    M.set_kernels(kernels)
+    return M
 
 
 def oracle_solve(A, b, variant, precond, tol, maxit, x0=None):
@@ -52,8 +57,8 @@ def oracle_solve(A, b, variant, precond, tol, maxit, x0=None):
 
 
 def check_parity(prcg, A, b, variant, precond, tol, maxit, x0=None, hist_rtol=1e-8, x_rtol=1e-10,
-                 hist_len=200):
-    M = gpu_matrix(prcg, A, precond)
+                 hist_len=200, kernels="fused"):
+    M = gpu_matrix(prcg, A, precond, kernels)
     x, info = M.solve(b, variant, tol, maxit, x0=x0, history=True)
     x = x.cpu().numpy()
     ref_stop = oracle_solve(A, b, variant, precond, tol, maxit, x0=x0)
@@ -122,25 +127,41 @@ def test_spmv_every_layout(prcg, torch_cuda, fmt, monkeypatch):
 
 # ---------------------------------------------------------------- solver parity
 
+@pytest.mark.parametrize("kernels", STRUCTURES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_poisson2d_64_parity(prcg, torch_cuda, variant):
+def test_poisson2d_64_parity(prcg, torch_cuda, variant, kernels):
     pr = P.config1()
-    info = check_parity(prcg, pr.A, pr.b, variant, "none", 1e-10, 5000)
+    info = check_parity(prcg, pr.A, pr.b, variant, "none", 1e-10, 5000, kernels=kernels)
     assert info.status == "ok"
 
 
+@pytest.mark.parametrize("kernels", STRUCTURES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_jacobi_parity_ragged(prcg, torch_cuda, variant):
+def test_jacobi_parity_ragged(prcg, torch_cuda, variant, kernels):
     A = P.random_spd(7777, 6.0, 8)
     b = P.uniform_vector(A.n, 9)
-    check_parity(prcg, A, b, variant, "jacobi", 1e-10, 3000)
+    check_parity(prcg, A, b, variant, "jacobi", 1e-10, 3000, kernels=kernels)
 
 
+@pytest.mark.parametrize("kernels", STRUCTURES)
 @pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
-def test_poisson3d_jacobi_parity(prcg, torch_cuda, variant):
+def test_poisson3d_jacobi_parity(prcg, torch_cuda, variant, kernels):
     A = P.poisson3d(40, 37, 33)  # n = 48,840: several tiles and a ragged tail
     b = P.uniform_vector(A.n, 2)
-    check_parity(prcg, A, b, variant, "jacobi", 1e-10, 3000)
+    check_parity(prcg, A, b, variant, "jacobi", 1e-10, 3000, kernels=kernels)
+
+
+@pytest.mark.parametrize("grid", [8, 24, 1024])
+@pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
+def test_grid_sizes(prcg, torch_cuda, variant, grid):
+    A = P.poisson3d(30, 29, 31)
+    b = P.uniform_vector(A.n, 3)
+    M = gpu_matrix(prcg, A, "jacobi")
+    M.set_grid(grid)
+    x, info = M.solve(b, variant, 1e-10, 3000, history=True)
+    ref = oracle_solve(A, b, variant, "jacobi", 0.0, info.iters)
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+    assert hist_close(info.history[:201], ref["history"][:201])
 
 
 @pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
@@ -233,10 +254,11 @@ def test_maxit_zero(prcg, torch_cuda):
         assert np.all(x.cpu().numpy() == 0.0)
 
 
-def test_fixed_iterations_with_zero_tolerance(prcg, torch_cuda):
+@pytest.mark.parametrize("kernels", STRUCTURES)
+def test_fixed_iterations_with_zero_tolerance(prcg, torch_cuda, kernels):
     A = P.poisson2d(32)
     b = P.uniform_vector(A.n, 4)
-    M = gpu_matrix(prcg, A)
+    M = gpu_matrix(prcg, A, "none", kernels)
     for v in VARIANTS:
         for maxit in (1, 15, 16, 17, 33):
             _, info = M.solve(b, v, 0.0, maxit)
@@ -290,10 +312,11 @@ def test_invalid_csr_is_rejected(prcg, torch_cuda):
         M.solve(np.ones(A.n), "pr", -1.0, 10)
 
 
-def test_bitwise_repeatable(prcg, torch_cuda):
+@pytest.mark.parametrize("kernels", STRUCTURES)
+def test_bitwise_repeatable(prcg, torch_cuda, kernels):
     A = P.poisson3d(30)
     b = P.uniform_vector(A.n, 5)
-    M = gpu_matrix(prcg, A, "jacobi")
+    M = gpu_matrix(prcg, A, "jacobi", kernels)
     for v in VARIANTS:
         x1, i1 = M.solve(b, v, 1e-10, 2000, history=True)
         x2, i2 = M.solve(b, v, 1e-10, 2000, history=True)
@@ -316,11 +339,12 @@ def test_set_values_changes_the_operator(prcg, torch_cuda):
 
 # ---------------------------------------------------------------- full-size workload
 
-def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda):
-    """The 128^3 Jacobi workload at full size, in the launch configuration the
-    benchmark times: the first 200 residual norms against the oracle."""
+@pytest.mark.parametrize("kernels", ["fused", "two_pass"])
+def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
+    """The 128^3 Jacobi workload at full size, in the launch configurations the
+    benchmark times: the first 200 residual norms and x_200 against the oracle."""
     pr = P.config2()
-    M = gpu_matrix(prcg, pr.A, "jacobi")
+    M = gpu_matrix(prcg, pr.A, "jacobi", kernels)
     for v in ["hs", "pr", "pipe_pr"]:
         x, info = M.solve(pr.b, v, 0.0, 200, history=True)
         ref = oracle_solve(pr.A, pr.b, v, "jacobi", 0.0, 200)
@@ -328,3 +352,12 @@ def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda):
         assert hist_close(info.history, ref["history"])
         xg = x.cpu().numpy()
         assert np.linalg.norm(xg - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+
+
+def test_time_kernels_capacity_is_checked(prcg, torch_cuda):
+    A = P.poisson2d(16)
+    M = gpu_matrix(prcg, A, "jacobi", "textbook")
+    with pytest.raises(prcg.PrcgError):
+        prcg.prcg_time_kernels(M.handle, prcg.PRCG_HS, 3, capacity=4)
+    names = [k for k, _ in prcg.prcg_time_kernels(M.handle, prcg.PRCG_HS, 3, capacity=10)]
+    assert len(names) == 10 and names[0] == "k_tb_mu"
