@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# kernel structures compared (the default "two_pass" places stage 2 by size)
+STRUCTURES = ("two_pass", "two_pass_redundant", "two_pass_stage2", "two_pass_last", "fused", "textbook")
 TOL = 1e-10
 MAXIT = 1000
 
@@ -38,10 +40,14 @@ def parse():
     ap.add_argument("--grid", type=int, default=0, help="override the workgroup count (tuning)")
     ap.add_argument("--kernels", default="two_pass", help="kernel structure of the flagship run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--m", type=int, default=128, help="grid edge (128 = the benchmark workload)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the flagship variant's kernels (the launches the roofline uses)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--suite", action="store_true",
+                    help="per-iteration times of every variant on every workload (one JSON line each)")
     return ap.parse_args()
 
 
@@ -66,6 +72,157 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def batched_section(torch, prcg, problems, traffic):
+    """512 anisotropic systems in one persistent launch vs one prcg_solve per system."""
+    A, offs, b, xs, eps = problems.config4()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    bt = torch.as_tensor(b, device="cuda")
+    x, iters, status = B.solve(bt, "pr", 1e-10, 20000)  # includes the autotuner's trial runs
+    assert all(st == "ok" for st in status)
+    reps = 3
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        x, iters, status = B.solve(bt, "pr", 1e-10, 20000)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t) / reps
+    nt, grid = B.config("pr")
+    sizes = np.diff(offs)
+    # algorithmic bytes: per system-iteration 10 vectors (PR two-pass, no preconditioner) + its matrix
+    per_row_matrix = 8.0 * 5  # offset-aligned slices: 8 bytes per stored entry, 5 entries per row
+    moved = float(np.sum(iters * sizes * (80.0 + per_row_matrix)))
+    # sequential: one handle and one solve per system (handles created before timing)
+    mats = [problems.batch_system(s_)[0] for s_ in range(len(sizes))]
+    handles = [prcg.Matrix(m.row_ptr, m.col_idx, m.values, "none") for m in mats]
+    bs = [bt[offs[s_]:offs[s_ + 1]].contiguous() for s_ in range(len(sizes))]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    seq_iters = 0
+    for h, bb in zip(handles, bs):
+        _, info = h.solve(bb, "pr", 1e-10, 20000)
+        seq_iters += info.iters
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    for h in handles:
+        h.close()
+    B.close()
+    M.close()
+    return {"workload": "aniso2d_batch_512", "systems": int(len(sizes)), "n_total": int(A.n),
+            "nnz_total": int(A.nnz), "batched_solves_per_s": len(sizes) / t_batch, "batched_ms": t_batch * 1e3,
+            "sequential_solves_per_s": len(sizes) / t_seq, "sequential_ms": t_seq * 1e3,
+            "speedup": t_seq / t_batch, "iterations_total": int(iters.sum()), "sequential_iterations": seq_iters,
+            "algorithmic_GBps": moved / t_batch / 1e9, "threads_per_workgroup": nt, "workgroups": grid}
+
+
+def unrolled_pr_cg(torch, rows, cols, vals, b, iters):
+    """PR-CG (Alg. 2, no preconditioner) written with differentiable torch ops
+    for a fixed number of iterations: the autograd-unrolling comparator."""
+    n = b.shape[0]
+
+    def spmv(v):
+        return torch.zeros(n, dtype=v.dtype, device=v.device).index_add(0, rows, vals * v[cols])
+
+    x = torch.zeros_like(b)
+    r = b - spmv(x)
+    p = r
+    s = spmv(p)
+    nu, mu, sigma, gamma = r @ r, p @ s, r @ s, s @ s
+    for _ in range(iters):
+        alpha = nu / mu
+        x = x + alpha * p
+        r = r - alpha * s
+        nup = nu - 2.0 * alpha * sigma + alpha * alpha * gamma
+        beta = nup / nu
+        p = r + beta * p
+        s = spmv(p)
+        mu, sigma, gamma, nu = p @ s, r @ s, s @ s, r @ r
+    return x
+
+
+def adjoint_section(torch, prcg, problems):
+    """Gradient of w^T x, x = A^{-1} b, w.r.t. b and the CSR values on the
+    96^3 variable-coefficient problem: adjoint solve vs unrolled autograd."""
+    from paper_1905_01549_amd.autograd import solve as dsolve
+    pr = problems.config5()
+    A = pr.A
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    w = torch.as_tensor(pr.extra["w"], device="cuda")
+    vals0 = torch.as_tensor(A.values, device="cuda")
+    b0 = torch.as_tensor(pr.b, device="cuda")
+
+    def adjoint_grad():
+        vals = vals0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        x = dsolve(vals, b, M, "pr", 1e-10, 20000)
+        (w * x).sum().backward()
+        return vals.grad, b.grad
+
+    gv, gb = adjoint_grad()
+    reps = 3
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        gv, gb = adjoint_grad()
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - t) / reps
+    _, info = M.solve(b0, "pr", 1e-10, 20000)
+    iters = info.iters
+    rows = torch.as_tensor(np.repeat(np.arange(A.n), np.diff(A.row_ptr)), device="cuda")
+    cols = torch.as_tensor(A.col_idx.astype(np.int64), device="cuda")
+
+    def unrolled_grad():
+        vals = vals0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        x = unrolled_pr_cg(torch, rows, cols, vals, b, iters)
+        (w * x).sum().backward()
+        return vals.grad, b.grad
+
+    uv, ub = unrolled_grad()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    uv, ub = unrolled_grad()
+    torch.cuda.synchronize()
+    t_unr = time.perf_counter() - t
+    dv = float((uv - gv).abs().max() / gv.abs().max())
+    db = float((ub - gb).abs().max() / gb.abs().max())
+    M.close()
+    return {"workload": "varcoef7_96", "n": int(A.n), "nnz": int(A.nnz), "forward_iterations": iters,
+            "adjoint_gradients_per_s": 1.0 / t_adj, "adjoint_ms": t_adj * 1e3,
+            "unrolled_autograd_gradients_per_s": 1.0 / t_unr, "unrolled_ms": t_unr * 1e3,
+            "speedup": t_unr / t_adj, "max_rel_diff_values_grad": dv, "max_rel_diff_b_grad": db}
+
+
+def suite(torch, prcg, problems):
+    """Per-iteration time of every variant on every workload (printed, one
+    JSON line per workload and kernel structure)."""
+    work = [("poisson2d_64", problems.config1, "none", 1e-10, 5000),
+            ("poisson3d_128_jacobi", problems.config2, "jacobi", 1e-10, 1000),
+            ("model_diag_1e6", problems.config3a, "none", 1e-10, 20000),
+            ("varcoef27_160", problems.config3b, "none", 1e-10, 20000),
+            ("varcoef7_96", problems.config5, "none", 1e-10, 20000)]
+    for name, fn, pre, tol, maxit in work:
+        pr = fn()
+        M = prcg.Matrix(pr.A.row_ptr, pr.A.col_idx, pr.A.values, pre)
+        b = torch.as_tensor(pr.b, device="cuda")
+        for kern in STRUCTURES:
+            M.set_kernels(kern)
+            out = {"workload": name, "n": pr.A.n, "nnz": pr.A.nnz, "kernels": kern}
+            for v in (("hs",) if kern == "textbook" else ("hs", "pr", "pipe_pr")):
+                x, info = M.solve(b, v, tol, maxit)
+                best = float("inf")
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    x, info = M.solve(b, v, tol, maxit)
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t)
+                out[v] = {"iters": info.iters, "status": info.status, "relres_true": info.relres_true,
+                          "us_per_iter": best / max(info.iters, 1) * 1e6, "solve_ms": best * 1e3}
+            print(json.dumps(out), flush=True)
+        M.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -76,6 +233,9 @@ def main():
     from paper_1905_01549_amd import prcg, problems, traffic
 
     torch.cuda.set_device(0)
+    if args.suite:
+        suite(torch, prcg, problems)
+        return
     pr = problems.config2(m=args.m)
     A = pr.A
     workload = f"poisson3d_{args.m}_jacobi"
@@ -126,9 +286,9 @@ def main():
     iters_per_s = total_iters / elapsed
     flagship = info
 
-    # every variant under both kernel structures, same workload (best of 2 solves)
+    # every variant under every kernel structure, same workload (best of 2 solves)
     variants = {}
-    for kern in ("two_pass", "fused", "textbook"):
+    for kern in STRUCTURES:
         M.set_kernels(kern)
         for v in (("hs",) if kern == "textbook" else ("hs", "pr", "pipe_pr")):
             vi = solve(v)
@@ -167,14 +327,23 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the oracle as it stands: complete PR-CG solves of the same workload
+        # to 1e-10, repeated until about 10 s of CPU time have been spent
         import oracle
+        done_iters, solves = 0, 0
         t = time.perf_counter()
-        oracle.solve(A.row_ptr, A.col_idx, A.values, pr.b, args.variant, "jacobi", 0.0, args.cpu_iters)
+        while solves == 0 or time.perf_counter() - t < args.cpu_seconds:
+            ref = oracle.solve(A.row_ptr, A.col_idx, A.values, pr.b, args.variant, "jacobi", TOL, MAXIT)
+            done_iters += ref["iters"]
+            solves += 1
         dt = time.perf_counter() - t
-        cpu = {"value": args.cpu_iters / dt, "unit": "CG iterations/s", "cores": oracle.max_threads(),
+        cpu = {"value": done_iters / dt, "unit": "CG iterations/s", "cores": oracle.max_threads(),
                "kind": "oracle",
-               "sample": f"{args.cpu_iters} PR-CG iterations (with initialisation) of the same "
-                         f"{workload} workload, FP64 C oracle"}
+               "sample": f"{solves} complete {args.variant} solves to 1e-10 ({done_iters} iterations, {dt:.1f} s) "
+                         f"of the same {workload} workload by the FP64 C oracle"}
+
+    batched = None if args.no_batched else batched_section(torch, prcg, problems, traffic)
+    adjoint = None if args.no_adjoint else adjoint_section(torch, prcg, problems)
 
     out = {
         "metric": "CG iterations/sec (FP64 PR-CG solve to 1e-10 relative residual)",
@@ -198,6 +367,8 @@ def main():
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out))
 

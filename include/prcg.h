@@ -98,7 +98,9 @@ typedef struct {
                                    which store one column offset per slot and slice
                                    instead of a column index per entry              */
     int32_t kernels;          /* kernel structure in use (PRCG_KERNELS_*)           */
-    int32_t pad;
+    int32_t stage2;           /* two-pass stage-2 reductions in one-workgroup
+                                 kernels of their own: bit 0 HS-CG, bit 1 PR-CG
+                                 and M-CG                                         */
 } prcg_matrix_props;
 
 /* Options (prcg_set_option).
@@ -109,16 +111,28 @@ typedef struct {
  *       the owner's exact operations.  Needs the SELL-64 layout; matrices
  *       stored as vector CSR use the two-pass structure.
  *     PRCG_KERNELS_TWO_PASS (default): an update kernel and a product kernel
- *       per reduction (PR: 2, pipe-PR: 2, HS: 3 kernels per iteration).  On
- *       MI355X this moves more bytes than FUSED but runs faster: the fused
- *       product's neighbour recomputation gathers three to five vectors per
- *       stored entry.
- *     PRCG_KERNELS_TWO_PASS_STAGE2: as TWO_PASS, with PR's stage-2
- *       reduction in a one-workgroup kernel of its own.
+ *       per reduction (PR: 2, pipe-PR: 2, HS: 3 kernels per iteration), with
+ *       stage 2 of each reduction (the sum of the per-workgroup partials)
+ *       placed by size: HS-CG and PR-CG as STAGE2 from 64 workgroups up,
+ *       else as REDUNDANT; pipe-PR-CG always as REDUNDANT.
+ *     PRCG_KERNELS_TWO_PASS_REDUNDANT: stage 2 runs redundantly in every
+ *       workgroup of the kernel that consumes the totals (pipe-PR-CG: in
+ *       workgroup 0 of the product kernel, before its share of the
+ *       product, so that the reduction overlaps the others' products).
+ *     PRCG_KERNELS_TWO_PASS_STAGE2: every stage-2 reduction in a
+ *       one-workgroup kernel of its own (PR and pipe-PR: 3, HS: 5 kernels per
+ *       iteration).
+ *     PRCG_KERNELS_TWO_PASS_LAST: stage 2 run by the last workgroup of the
+ *       kernel that writes the partials (an atomic ticket counter picks it;
+ *       no workgroup waits for another).  Slower on MI355X: the fence that
+ *       publishes each workgroup's partials to the other XCDs writes back
+ *       its L2.
  *     PRCG_KERNELS_TEXTBOOK: HS-CG as one kernel per line of Alg. 1 (AXPYs,
  *       preconditioner, each inner product, a one-workgroup reduction
  *       kernel per synchronisation, the product): the unfused baseline.
  *       Other variants run TWO_PASS under this setting.
+ *   All two-pass placements add the partials in the same fixed order:
+ *   results are bitwise identical across them.
  *   PRCG_OPT_GRID  largest number of workgroups of the row-parallel kernels
  *     (8..1024, default 1024; the actual count is a multiple of 8). */
 typedef enum { PRCG_OPT_KERNELS = 0, PRCG_OPT_GRID = 1 } prcg_option;
@@ -126,7 +140,9 @@ typedef enum {
     PRCG_KERNELS_FUSED = 0,
     PRCG_KERNELS_TWO_PASS = 1,
     PRCG_KERNELS_TWO_PASS_STAGE2 = 2,
-    PRCG_KERNELS_TEXTBOOK = 3
+    PRCG_KERNELS_TEXTBOOK = 3,
+    PRCG_KERNELS_TWO_PASS_LAST = 4,
+    PRCG_KERNELS_TWO_PASS_REDUNDANT = 5
 } prcg_kernels;
 
 /*

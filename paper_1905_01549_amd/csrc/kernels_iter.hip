@@ -18,9 +18,16 @@
 //            on data of the row, so they share one pass; workgroup 0 of the
 //            SpMV kernel runs stage 2 while the other workgroups compute
 //            u = A s~ and w = A r~ (one pass over A): the overlap of the
-//            reduction with the products of Section 2.2.1.
+//            reduction with the products of Section 2.2.1.  This placement
+//            costs nothing and is the default for pipe-PR.
 //   HS-CG:   [stage 2 of mu + x, r updates + nu] [stage 2 of nu + p update]
 //            [SpMV + mu]: two reductions per iteration, as Alg. 1 needs.
+//
+// Where stage 2 runs is a choice (Split): redundantly in every workgroup of
+// the consuming kernel (above), in a one-workgroup kernel of its own
+// (stage2), or in the last workgroup of the producing kernel to finish its
+// partials (lastwg; take_last_ticket).  The sums are the same in all three:
+// the partials are added in the same fixed order.
 //
 // Jacobi (M^{-1} = diag(d)): the vectors the algorithms define explicitly
 // as M^{-1} v (HS r~, PR s~, pipe u~ and w~) are recomputed as d*v where
@@ -128,7 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
 // One workgroup: ||b||, the b = 0 case, and the first scalar step where the
 // variant's first iteration kernel does not perform it.
 // step0: 1 when this kernel performs the scalar step of k = 0 (pipe-PR
-// two-pass and HS); otherwise the first iteration kernel does.
+// two-pass and HS; PR when the iteration's own step runs at the end of the
+// product kernel); otherwise the first iteration kernel does.  HS with
+// step0 = 2 also forms alpha_0 from mu_0.
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
                                                         const double* __restrict__ PS, State* __restrict__ out,
@@ -153,10 +162,11 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, 
         st.zero_x = 1;
         st.rr = 0.0;
         if (w) hist[0] = 0.0;
-    } else if (step0 && (variant == kPipePR || variant == kPipeM)) {
-        step_one_reduction(st, t, PRE, variant == kPipeM, hist, w);
     } else if (variant == kHS) {
         step_hs_nu(st, t[3], PRE ? t[4] : t[3], hist, w);
+        if (step0 == 2 && !st.done) step_hs_mu(st, t[0]);
+    } else if (step0) {
+        step_one_reduction(st, t, PRE, variant == kM || variant == kPipeM, hist, w);
     }
     // otherwise the first iteration kernel performs the step for k = 0
     if (w) *out = st;
@@ -173,7 +183,7 @@ __device__ __forceinline__ void row_range(const Split& sp, int64_t g0, int64_t g
 // Stage 2 of iteration k + scalar step, then the vector updates of
 // iteration k+1 (Alg. 2): x += alpha p; r -= alpha s; r~ -= alpha s~;
 // p = r~ + beta p.
-// REDUCE = false: the state was already advanced by k_pr_finish and `in`
+// REDUCE = false: the state was already advanced by k_finish_one and `in`
 // is the current state (`out` unused).
 template <bool PRE, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
@@ -235,10 +245,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
     }
 }
 
-// One workgroup: stage 2 of iteration k and the scalar step (used when
-// the update kernel should not reduce the partials itself).
+// One workgroup: stage 2 of iteration k and the scalar step of a
+// one-reduction variant (PR, M, pipe-PR, pipe-M), when neither the consuming
+// kernel nor the producing kernel reduces the partials itself.
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_pr_finish(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, int meurant)
 {
@@ -252,14 +263,49 @@ __global__ __launch_bounds__(kBlock) void k_pr_finish(Split sp, const State* __r
     if (threadIdx.x == 0) *out = st;
 }
 
+// One workgroup: stage 2 of HS-CG's mu_k (alpha_k) or nu_k (tests, beta_k).
+__global__ __launch_bounds__(kBlock) void k_hs_finish_mu(Split sp, const State* __restrict__ in,
+                                                         State* __restrict__ out, const double* __restrict__ PS)
+{
+    __shared__ double lds[kWaves];
+    State st = *in;
+    if (!st.done) {
+        double t[1];
+        reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
+        step_hs_mu(st, t[0]);
+    }
+    if (threadIdx.x == 0) *out = st;
+}
+
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* __restrict__ in,
+                                                         State* __restrict__ out, double* __restrict__ hist,
+                                                         const double* __restrict__ PU)
+{
+    __shared__ double lds[kWaves * 2];
+    State st = *in;
+    if (!st.done) {
+        double t[2];
+        reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+        step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
+    }
+    if (threadIdx.x == 0) *out = st;
+}
+
 // s_k = A p_k, s~_k = M^{-1} s_k, and the inner products of Alg. 2
 // mu = <p, s>, sigma = <r~, s>, gamma = <s~, s>, nu = <r~, r> (+ <r, r>).
-template <int LANES, bool PRE>
-__global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
-                                                    double* __restrict__ PS, Vecs v)
+// LAST: the last workgroup also runs stage 2 and the scalar step, advancing
+// the state from `in` to `out`.
+template <int LANES, bool PRE, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+                                                    State* __restrict__ out, double* __restrict__ hist,
+                                                    double* __restrict__ PS, int meurant, int* ticket, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
-    if (cur->done) return;
+    if (in->done) {
+        if (LAST && writer_thread()) *out = *in;
+        return;
+    }
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -277,6 +323,13 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
         });
     }
     write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+    if (LAST && take_last_ticket(ticket, sp.G)) {
+        State st = *in;
+        double t[5];
+        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+        if (threadIdx.x == 0) *out = st;
+    }
 }
 
 // ------------------------------------------------------------------ pipe-PR-CG
@@ -287,13 +340,19 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
 //   w~' = w~ - alpha u~; p = r~ + beta p; s = w' + beta s; s~ = w~' + beta s~.
 // w' and w~' live only in registers (Section 2.2.1: w and w' need not be
 // stored separately; w is recomputed by the next kernel).
-template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* __restrict__ cur,
-                                                        double* __restrict__ PS, Vecs v)
+// LAST: the last workgroup also runs stage 2 and the scalar step of
+// iteration k (`in` -> `out`); the product kernel then only multiplies.
+template <bool PRE, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* __restrict__ in,
+                                                        State* __restrict__ out, double* __restrict__ hist,
+                                                        double* __restrict__ PS, int meurant, int* ticket, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
-    const State st = *cur;
-    if (st.done) return;
+    const State st = *in;
+    if (st.done) {
+        if (LAST && writer_thread()) *out = st;
+        return;
+    }
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
@@ -335,38 +394,48 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
         if (PRE) acc[4] = fma(rn, rn, acc[4]);
     }
     write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+    if (LAST && take_last_ticket(ticket, sp.G)) {
+        State nx = st;
+        double t[5];
+        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        step_one_reduction(nx, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+        if (threadIdx.x == 0) *out = nx;
+    }
 }
 
 // u_k = A s~_k and w_k = A r~_k (the recompute) in one pass over A with the
-// block vector (s~, r~).  Workgroup 0 also reduces the inner products of
-// iteration k and performs the scalar step once its share of the product is
-// issued (Section 2.2.1: the products and the reduction proceed at the same
-// time); the grid stays at G workgroups so every compute unit gets the same
-// share of the product.
-template <int LANES, bool PRE>
+// block vector (s~, r~).  REDUCE: workgroup 0 first reduces the inner
+// products of iteration k and performs the scalar step, then takes its
+// share of the product, while the other workgroups multiply (Section 2.2.1:
+// the reduction proceeds during the products).  Reducing first keeps the
+// reduction off the kernel's tail: done after the product, it lengthened
+// the kernel by 9-12 us on MI355X.
+// REDUCE = false: the update kernel or a one-workgroup kernel advances the
+// state instead.
+template <int LANES, bool PRE, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, int meurant, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
-    State st = *in;
-    if (!st.done) {
-        int64_t g0, g1;
-        chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
-        double2* __restrict__ uw = v.uw;
-        for (int64_t g = g0; g < g1; ++g) {
-            rows_of_group_pair<LANES>(S, C, g, v.zr, [&](int64_t i, double ui, double wi) {
-                uw[i] = make_double2(ui, wi);
-            });
-        }
-    }
-    if (blockIdx.x == 0) {
+    const State st = *in;
+    if (REDUCE && blockIdx.x == 0) {
+        State nx = st;
         if (!st.done) {
             double t[5];
             reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
-            step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+            step_one_reduction(nx, t, PRE, meurant != 0, hist, threadIdx.x == 0);
         }
-        if (threadIdx.x == 0) *out = st;
+        if (threadIdx.x == 0) *out = nx;
+    }
+    if (st.done) return;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double2* __restrict__ uw = v.uw;
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group_pair<LANES>(S, C, g, v.zr, [&](int64_t i, double ui, double wi) {
+            uw[i] = make_double2(ui, wi);
+        });
     }
 }
 
@@ -374,21 +443,31 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
 
 // Stage 2 of mu_{k-1} (alpha_{k-1}), then x += alpha p, r -= alpha s and the
 // partials of nu_k = <r~_k, r_k> (+ <r_k, r_k>), r~_k = M^{-1} r_k.
-template <bool PRE>
+// REDUCE = false: a one-workgroup kernel or the product kernel has already
+// done the step and `in` is the current state.
+// LAST: the last workgroup reduces nu_k and runs its step (`in` -> `out`).
+template <bool PRE, bool REDUCE, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restrict__ in, State* __restrict__ out,
-                                                  const double* __restrict__ PS, double* __restrict__ PU, Vecs v)
+                                                  double* __restrict__ hist, const double* __restrict__ PS,
+                                                  double* __restrict__ PU, int* ticket, Vecs v)
 {
+    static_assert(!(REDUCE && LAST), "one state transition per kernel");
     __shared__ double lds[kWaves * 2];
     State st = *in;
-    if (st.done) {
+    if (REDUCE) {
+        if (st.done) {
+            if (writer_thread()) *out = st;
+            return;
+        }
+        double t[1];
+        reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
+        step_hs_mu(st, t[0]);
         if (writer_thread()) *out = st;
+    }
+    if (st.done) {
+        if (LAST && writer_thread()) *out = st;
         return;
     }
-    double t[1];
-    reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
-    step_hs_mu(st, t[0]);
-    if (writer_thread()) *out = st;
-    if (st.done) return;
     const double alpha = st.alpha;
     int64_t g0, g1, i0, i1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
@@ -410,23 +489,31 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
         if (PRE) acc[1] = fma(rn, rn, acc[1]);
     }
     write_partials<2>(acc, PU, sp.Gs, blockIdx.x, lds);
+    if (LAST && take_last_ticket(ticket, sp.G)) {
+        double t[2];
+        reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+        step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
+        if (threadIdx.x == 0) *out = st;
+    }
 }
 
 // Stage 2 of nu_k (convergence test, beta_k), then p_k = r~_k + beta_k p_{k-1}.
-template <bool PRE>
+template <bool PRE, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                  double* __restrict__ hist, const double* __restrict__ PU, Vecs v)
 {
     __shared__ double lds[kWaves * 2];
     State st = *in;
-    if (st.done) {
+    if (REDUCE) {
+        if (st.done) {
+            if (writer_thread()) *out = st;
+            return;
+        }
+        double t[2];
+        reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+        step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, writer_thread());
         if (writer_thread()) *out = st;
-        return;
     }
-    double t[2];
-    reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
-    step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, writer_thread());
-    if (writer_thread()) *out = st;
     if (st.done) return;
     const double beta = st.beta;
     int64_t g0, g1, i0, i1;
@@ -447,13 +534,18 @@ __global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restri
     }
 }
 
-// s_k = A p_k and the partials of mu_k = <p_k, s_k>.
-template <int LANES>
-__global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
-                                                    double* __restrict__ PS, Vecs v)
+// s_k = A p_k and the partials of mu_k = <p_k, s_k>.  LAST: the last
+// workgroup also reduces mu_k and forms alpha_k (`in` -> `out`).
+template <int LANES, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+                                                    State* __restrict__ out, double* __restrict__ PS, int* ticket,
+                                                    Vecs v)
 {
     __shared__ double lds[kWaves * 1];
-    if (cur->done) return;
+    if (in->done) {
+        if (LAST && writer_thread()) *out = *in;
+        return;
+    }
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     double acc[1] = {0.0};
@@ -464,6 +556,13 @@ __global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split
         });
     }
     write_partials<1>(acc, PS, sp.Gs, blockIdx.x, lds);
+    if (LAST && take_last_ticket(ticket, sp.G)) {
+        State st = *in;
+        double t[1];
+        reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
+        step_hs_mu(st, t[0]);
+        if (threadIdx.x == 0) *out = st;
+    }
 }
 
 // ------------------------------------------------------------------ exit
@@ -564,7 +663,8 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     });
     if (e != hipSuccess) return e;
     return with_pre(pre, [&](auto P) {
-        const int step0 = variant == kHS || ((variant == kPipePR || variant == kPipeM) && !sp.fused);
+        const bool pipe2 = (variant == kPipePR || variant == kPipeM) && !sp.fused;
+        const int step0 = variant == kHS ? (sp.lastwg ? 2 : 1) : (pipe2 || sp.lastwg ? 1 : 0);
         hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
                            B.PB, B.PS, B.S[0], B.hist, tol, (int)maxit);
         return hipGetLastError();
@@ -575,8 +675,8 @@ int iter_kernel_count(int variant, const Split& sp)
 {
     if (sp.textbook && variant == kHS) return textbook_kernel_count(sp.textbook_pre);
     if (sp.fused) return variant == kHS ? 2 : 1;
-    if (variant == kHS) return 3;
-    if ((variant == kPR || variant == kM) && sp.stage2) return 3;
+    if (variant == kHS) return stage2_of(sp, kHS) ? 5 : 3;
+    if (variant != kHS && stage2_of(sp, variant)) return 3;
     return 2;
 }
 
@@ -587,13 +687,19 @@ const char* iter_kernel_name(int variant, const Split& sp, int j)
         if (variant == kHS) return j == 0 ? "k_hs_xr" : "k_hs_fused";
         return (variant == kPR || variant == kM) ? "k_pr_fused" : "k_pipe_fused";
     }
+    if (variant == kHS && stage2_of(sp, kHS)) {
+        static const char* n5[] = {"k_hs_finish_mu", "k_hs_xr", "k_hs_finish_nu", "k_hs_p", "k_hs_spmv"};
+        return n5[j];
+    }
     switch (variant) {
     case kHS: return j == 0 ? "k_hs_xr" : (j == 1 ? "k_hs_p" : "k_hs_spmv");
     case kPR:
     case kM:
-        if (sp.stage2) return j == 0 ? "k_pr_finish" : (j == 1 ? "k_pr_update" : "k_pr_spmv");
+        if (stage2_of(sp, kPR)) return j == 0 ? "k_finish_one" : (j == 1 ? "k_pr_update" : "k_pr_spmv");
         return j == 0 ? "k_pr_update" : "k_pr_spmv";
-    default: return j == 0 ? "k_pipe_update" : "k_pipe_spmv";
+    default:
+        if (stage2_of(sp, variant)) return j == 0 ? "k_pipe_update" : (j == 1 ? "k_pipe_spmv" : "k_finish_one");
+        return j == 0 ? "k_pipe_update" : "k_pipe_spmv";
     }
 }
 
@@ -610,14 +716,25 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
         return with_pre(pre, [&](auto P) {
             constexpr int LL = decltype(L)::value;
             constexpr bool PP = decltype(P)::value;
+            int* tk = B.ticket;
+            const bool s2 = stage2_of(sp, variant);
             switch (variant) {
             case kPR:
             case kM:
-                if (sp.stage2 && j == 0) {
-                    launch(k_pr_finish<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                if (sp.lastwg) {
+                    if (j == 0) {
+                        launch(k_pr_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                               B.hist, (const double*)B.PS, meurant, v);
+                    } else {
+                        launch(k_pr_spmv<LL, PP, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                               B.S[nxt], B.hist, B.PS, meurant, tk, v);
+                        cur = nxt;
+                    }
+                } else if (s2 && j == 0) {
+                    launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PS, meurant);
                     cur = nxt;
-                } else if (sp.stage2 && j == 1) {
+                } else if (s2 && j == 1) {
                     launch(k_pr_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            B.hist, (const double*)B.PS, meurant, v);
                 } else if (j == 0) {
@@ -625,30 +742,76 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                            B.hist, (const double*)B.PS, meurant, v);
                     cur = nxt;
                 } else {
-                    launch(k_pr_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
+                    launch(k_pr_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                           B.S[nxt], B.hist, B.PS, meurant, tk, v);
                 }
                 break;
             case kPipePR:
             case kPipeM:
-                if (j == 0) {
-                    launch(k_pipe_update<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.PS, v);
+                if (sp.lastwg) {
+                    if (j == 0) {
+                        launch(k_pipe_update<PP, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                               B.hist, B.PS, meurant, tk, v);
+                        cur = nxt;
+                    } else {
+                        launch(k_pipe_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                               B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
+                    }
+                } else if (j == 0) {
+                    launch(k_pipe_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, B.PS, meurant, tk, v);
+                } else if (s2 && j == 1) {
+                    launch(k_pipe_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                           B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
+                } else if (s2) {
+                    launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                           (const double*)B.PS, meurant);
+                    cur = nxt;
                 } else {
-                    launch(k_pipe_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                    launch(k_pipe_spmv<LL, PP, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
                            B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
                     cur = nxt;
                 }
                 break;
             default:  // HS
-                if (j == 0) {
-                    launch(k_hs_xr<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           (const double*)B.PS, B.PU, v);
+                if (sp.lastwg) {
+                    if (j == 0) {
+                        launch(k_hs_xr<PP, false, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                               B.hist, (const double*)B.PS, B.PU, tk, v);
+                        cur = nxt;
+                    } else if (j == 1) {
+                        launch(k_hs_p<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                               B.hist, (const double*)B.PU, v);
+                    } else {
+                        launch(k_hs_spmv<LL, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.S[nxt],
+                               B.PS, tk, v);
+                        cur = nxt;
+                    }
+                } else if (s2 && j == 0) {
+                    launch(k_hs_finish_mu, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           (const double*)B.PS);
+                    cur = nxt;
+                } else if (s2 && j == 1) {
+                    launch(k_hs_xr<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, B.PU, tk, v);
+                } else if (s2 && j == 2) {
+                    launch(k_hs_finish_nu<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PU);
+                    cur = nxt;
+                } else if (s2 && j == 3) {
+                    launch(k_hs_p<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                           (const double*)B.PU, v);
+                } else if (j == 0) {
+                    launch(k_hs_xr<PP, true, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, B.PU, tk, v);
                     cur = nxt;
                 } else if (j == 1) {
-                    launch(k_hs_p<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                    launch(k_hs_p<PP, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PU, v);
                     cur = nxt;
                 } else {
-                    launch(k_hs_spmv<LL>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
+                    launch(k_hs_spmv<LL, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.PS, tk, v);
                 }
                 break;
             }

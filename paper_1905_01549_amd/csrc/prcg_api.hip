@@ -90,7 +90,7 @@ struct prcg_matrix_s {
     double* hist = nullptr;
     int64_t hist_cap = 0;
     double* partials = nullptr;  // PS | PU | PB
-    int32_t* dflags = nullptr;
+    int32_t* dflags = nullptr;   // [0..3] setup flags, [4] reduction ticket
     State* hstate = nullptr;     // pinned, two slots
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -145,6 +145,7 @@ struct prcg_matrix_s {
         B.PU = partials + (size_t)kMaxDots * kMaxGrid;
         B.PB = partials + (size_t)(kMaxDots + 2) * kMaxGrid;
         B.PS2 = partials + (size_t)(kMaxDots + 3) * kMaxGrid;
+        B.ticket = dflags + 4;
         return B;
     }
 };
@@ -248,6 +249,15 @@ void invalidate_graphs(prcg_matrix A)
 
 // Choose the work split: G workgroups (multiple of 8 when G >= 8, so every
 // XCD gets the same number), at most gmax_opt (PRCG_OPT_GRID, default 1024).
+//
+// Stage-2 placement of the default two-pass structure.  The redundant form
+// costs every workgroup of the consuming kernel a read of all partials
+// (G^2 reads of the same few cache lines per reduction: 5-15 us on MI355X
+// from 64 workgroups up); a one-workgroup kernel costs one launch (about
+// 4 us).  HS-CG and PR-CG therefore take the separate kernel from 64
+// workgroups up.  pipe-PR-CG reduces in one workgroup of its product kernel
+// before that workgroup's share of the product, which hides the reduction.
+constexpr int kStage2MinGrid = 64;
 Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
 {
     Split sp{};
@@ -260,7 +270,12 @@ Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
     sp.G = (int)std::max<int64_t>(G, 1);
     sp.Gs = (sp.G + 63) / 64 * 64;
     sp.fused = (kernels_mode == PRCG_KERNELS_FUSED && lanes == 1) ? 1 : 0;
-    sp.stage2 = kernels_mode == PRCG_KERNELS_TWO_PASS_STAGE2 ? 1 : 0;
+    if (kernels_mode == PRCG_KERNELS_TWO_PASS_STAGE2) {
+        sp.stage2 = 7;
+    } else if (kernels_mode == PRCG_KERNELS_TWO_PASS || kernels_mode == PRCG_KERNELS_TEXTBOOK) {
+        sp.stage2 = sp.G >= kStage2MinGrid ? 3 : 0;
+    }
+    sp.lastwg = kernels_mode == PRCG_KERNELS_TWO_PASS_LAST ? 1 : 0;
     sp.textbook = kernels_mode == PRCG_KERNELS_TEXTBOOK ? 1 : 0;
     return sp;
 }
@@ -427,7 +442,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     HTRY(hipMalloc(&A->row_ptr, sizeof(int32_t) * (n + 1)));
     HTRY(hipMalloc(&A->col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
     HTRY(hipMalloc(&A->val, sizeof(double) * std::max<int64_t>(nnz, 1)));
-    HTRY(hipMalloc(&A->dflags, sizeof(int32_t) * 4));
+    HTRY(hipMalloc(&A->dflags, sizeof(int32_t) * 8));
     HTRY(hipHostMalloc(&A->hstate, sizeof(State) * 2, hipHostMallocDefault));
     HTRY(hipEventCreateWithFlags(&A->ev[0], hipEventDisableTiming));
     HTRY(hipEventCreateWithFlags(&A->ev[1], hipEventDisableTiming));
@@ -438,7 +453,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     }
 
     // validate the structure (flags[0]) and find the longest row (flags[1])
-    HTRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t) * 4, A->stream));
+    HTRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t) * 8, A->stream));
     HTRY(launch_validate(n, nnz, A->row_ptr, A->col, A->dflags, A->dflags + 1, A->stream));
     int32_t hf[4];
     TRY(read_flags(A, hf, 4));
@@ -537,7 +552,7 @@ prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value)
 {
     if (!A) return fail(PRCG_EINVAL, "null handle");
     if (option == PRCG_OPT_KERNELS) {
-        if (value < PRCG_KERNELS_FUSED || value > PRCG_KERNELS_TEXTBOOK)
+        if (value < PRCG_KERNELS_FUSED || value > PRCG_KERNELS_TWO_PASS_REDUNDANT)
             return fail(PRCG_EINVAL, "unknown kernel structure");
         A->kernels_mode = value;
     } else if (option == PRCG_OPT_GRID) {
@@ -624,6 +639,7 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
     props->stored_entries = A->sp.lanes == 1 ? A->stored : A->nnz;
     props->grid = A->sp.G;
     props->kernels = A->sp.fused ? PRCG_KERNELS_FUSED : A->kernels_mode;
+    props->stage2 = A->sp.stage2;
     props->block = kBlock;
     // bytes one product reads: values, the column indices of packed slices,
     // the offsets of aligned slices and the per-slice metadata

@@ -73,12 +73,23 @@ struct Split {
     int Gs;         // stride between reduction values in a partials buffer
     int64_t ngroups;
     int lanes;      // 1 = SELL-64, else lanes per row of vector CSR
-    int stage2;     // PR/M two-pass: 0 = every update workgroup reduces the
-                    // partials, 1 = a one-workgroup kernel reduces them first
+    int stage2;     // two-pass, per variant (bit 0: HS, 1: PR/M, 2: pipe): a
+                    // one-workgroup kernel reduces the partials before the
+                    // kernel that needs the totals
+    int lastwg;     // two-pass: the last workgroup of the kernel that writes
+                    // the partials reduces them (ticket counter)
+                    // (neither: every workgroup of the consuming kernel
+                    // reduces them redundantly)
     int fused;      // 1 = fused kernels (SELL-64 only), 0 = two-pass kernels
     int textbook;   // 1 = HS-CG as one kernel per algorithm line
     int textbook_pre;  // preconditioned (the textbook kernel list depends on it)
 };
+
+inline bool stage2_of(const Split& sp, int variant)
+{
+    const int bit = variant == kHS ? 1 : ((variant == kPR || variant == kM) ? 2 : 4);
+    return (sp.stage2 & bit) != 0;
+}
 
 // ---- setup kernels (kernels_setup.hip) ----
 hipError_t launch_validate(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
@@ -120,6 +131,7 @@ struct Bufs {
     double* PU;   // [nu, rr] partials (HS)
     double* PB;   // [bb] or [tt] partials
     double* PS2;  // second copy of PS (fused kernels alternate between the two)
+    int* ticket;  // workgroup counter of the last-workgroup reduction (0 between kernels)
 };
 
 hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView* csr, const Split& sp,

@@ -78,6 +78,33 @@ __device__ __forceinline__ void write_partials(double (&acc)[NV], double* __rest
     }
 }
 
+// Stage 2 by the last workgroup.  After thread 0 has written the
+// workgroup's partials (write_partials), it takes a ticket; the workgroup
+// that draws the last one (G - 1) returns true and reduces all partials.
+// Thread 0's agent-scope fence before its ticket releases its partials to
+// every XCD; the fence after the last ticket (and in every thread of that
+// workgroup after the barrier) acquires everyone else's.  No workgroup
+// waits for another, so the scheme cannot hang.  The last workgroup resets
+// the counter, which is therefore 0 whenever no kernel is running.
+__device__ __forceinline__ bool take_last_ticket(int* ticket, int G)
+{
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int t = atomicAdd(ticket, 1);
+        const int last = t == G - 1;
+        if (last) {
+            __threadfence();
+            atomicExch(ticket, 0);
+        }
+        is_last = last;
+    }
+    __syncthreads();
+    const bool last = is_last != 0;
+    if (last) __threadfence();
+    return last;
+}
+
 // Workgroup b of G owns the 256-row groups [g0, g1).  The hardware hands
 // workgroups to the 8 XCDs round-robin (b mod 8), so consecutive runs are
 // given to workgroups of the same XCD: neighbouring rows then share an L2.

@@ -24,7 +24,8 @@ VARIANTS = {"hs": PRCG_HS, "pr": PRCG_PR, "pipe_pr": PRCG_PIPE_PR, "m": PRCG_M, 
 PRECONDS = {"none": 0, "jacobi": 1}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem", -3: "edevice"}
 
-KERNELS = {"fused": 0, "two_pass": 1, "two_pass_stage2": 2, "textbook": 3}
+KERNELS = {"fused": 0, "two_pass": 1, "two_pass_stage2": 2, "textbook": 3, "two_pass_last": 4,
+           "two_pass_redundant": 5}
 OPT_KERNELS, OPT_GRID = 0, 1
 
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
@@ -47,7 +48,7 @@ class prcg_matrix_props(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("stored_entries", ctypes.c_int64),
                 ("format", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
-                ("aligned_slices_frac", ctypes.c_double), ("kernels", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("aligned_slices_frac", ctypes.c_double), ("kernels", ctypes.c_int32), ("stage2", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -247,7 +248,8 @@ class Matrix:
         return prcg_get_props(self.handle)
 
     def set_kernels(self, mode: str):
-        """Kernel structure: "two_pass" (default), "fused", "two_pass_stage2" or
+        """Kernel structure: "two_pass" (default; stage-2 placement by size),
+        "two_pass_redundant", "two_pass_stage2", "two_pass_last", "fused" or
         "textbook" (HS-CG one kernel per algorithm line)."""
         prcg_set_option(self.handle, OPT_KERNELS, KERNELS[mode])
 

@@ -43,7 +43,7 @@ def hist_close(h, ho, rtol=1e-8):
     return bool(np.all(np.abs(h - ho) <= rtol * ho + EPS))
 
 
-STRUCTURES = ["fused", "two_pass", "two_pass_stage2", "textbook"]
+STRUCTURES = ["fused", "two_pass", "two_pass_redundant", "two_pass_stage2", "two_pass_last", "textbook"]
 
 
 def gpu_matrix(prcg, A, precond="none", kernels="fused"):
@@ -151,12 +151,13 @@ def test_poisson3d_jacobi_parity(prcg, torch_cuda, variant, kernels):
     check_parity(prcg, A, b, variant, "jacobi", 1e-10, 3000, kernels=kernels)
 
 
+@pytest.mark.parametrize("kernels", ["two_pass", "two_pass_redundant", "two_pass_last"])
 @pytest.mark.parametrize("grid", [8, 24, 1024])
 @pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
-def test_grid_sizes(prcg, torch_cuda, variant, grid):
+def test_grid_sizes(prcg, torch_cuda, variant, grid, kernels):
     A = P.poisson3d(30, 29, 31)
     b = P.uniform_vector(A.n, 3)
-    M = gpu_matrix(prcg, A, "jacobi")
+    M = gpu_matrix(prcg, A, "jacobi", kernels)
     M.set_grid(grid)
     x, info = M.solve(b, variant, 1e-10, 3000, history=True)
     ref = oracle_solve(A, b, variant, "jacobi", 0.0, info.iters)
@@ -325,6 +326,39 @@ def test_bitwise_repeatable(prcg, torch_cuda, kernels):
         assert np.array_equal(i1.history, i2.history)
 
 
+def test_reduction_placements_agree_bitwise(prcg, torch_cuda):
+    """Stage 2 in every consuming workgroup, in a kernel of its own or in the
+    producing kernel's last workgroup adds the same partials in the same
+    order: iterates and histories are identical bit for bit."""
+    A = P.poisson3d(29, 31, 30)
+    b = P.uniform_vector(A.n, 6)
+    for pre in ("none", "jacobi"):
+        for v in VARIANTS:
+            out = []
+            for kernels in ("two_pass_redundant", "two_pass_stage2", "two_pass_last"):
+                M = gpu_matrix(prcg, A, pre, kernels)
+                x, info = M.solve(b, v, 1e-10, 2000, history=True)
+                out.append((x.cpu().numpy(), info.iters, info.history))
+                M.close()
+            for x, k, h in out[1:]:
+                assert k == out[0][1], (v, pre)
+                assert np.array_equal(x, out[0][0]) and np.array_equal(h, out[0][2]), (v, pre)
+
+
+def test_last_workgroup_ticket_survives_grid_changes(prcg, torch_cuda):
+    """The ticket counter of the last-workgroup reduction returns to 0 after
+    every kernel, so solves with different grids on one handle stay exact."""
+    A = P.poisson3d(30, 29, 31)
+    b = P.uniform_vector(A.n, 7)
+    M = gpu_matrix(prcg, A, "jacobi", "two_pass_last")
+    for grid, v in ((1024, "pr"), (24, "hs"), (8, "pipe_pr"), (96, "pr"), (1024, "hs")):
+        M.set_grid(grid)
+        x, info = M.solve(b, v, 1e-10, 3000)
+        ref = oracle_solve(A, b, v, "jacobi", 0.0, info.iters)
+        assert info.status == "ok"
+        assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"]), (grid, v)
+
+
 def test_set_values_changes_the_operator(prcg, torch_cuda):
     A = P.poisson2d(24)
     b = P.uniform_vector(A.n, 3)
@@ -339,7 +373,7 @@ def test_set_values_changes_the_operator(prcg, torch_cuda):
 
 # ---------------------------------------------------------------- full-size workload
 
-@pytest.mark.parametrize("kernels", ["fused", "two_pass"])
+@pytest.mark.parametrize("kernels", ["fused", "two_pass", "two_pass_last"])
 def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
     """The 128^3 Jacobi workload at full size, in the launch configurations the
     benchmark times: the first 200 residual norms and x_200 against the oracle."""
