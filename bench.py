@@ -72,6 +72,13 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def nu_split(M) -> bool:
+    """Whether PR's update kernel forms <r~, r> and <r, r> (Jacobi): stage 2
+    outside the update kernel, i.e. in its own kernel or a last workgroup."""
+    p = M.props
+    return bool(p.stage2 & 2) or p.kernels == 4
+
+
 def batched_section(torch, prcg, problems, traffic):
     """512 anisotropic systems in one persistent launch vs one prcg_solve per system."""
     A, offs, b, xs, eps = problems.config4()
@@ -256,7 +263,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         kt = M.time_kernels(args.variant, 200)
-        kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused)
+        kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
         print(json.dumps({"workload": workload, "variant": args.variant, "launches": 200,
                           "kernels": {k: {"us": ms * 1e3, "bytes": kb.get(k, 0),
                                           "GBps": kb.get(k, 0) / (ms * 1e-3) / 1e9} for k, ms in kt}}))
@@ -300,9 +307,9 @@ def main():
                 torch.cuda.synchronize()
                 best = min(best, time.perf_counter() - t)
             fz = kern == "fused"
-            it_bytes = traffic.iteration_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook")
+            it_bytes = traffic.iteration_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook", nu_split(M))
             kt = M.time_kernels(v, 50)
-            kb = traffic.kernel_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook")
+            kb = traffic.kernel_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook", nu_split(M))
             variants[f"{v}/{kern}"] = {
                 "iters": vi.iters,
                 "relres_true": vi.relres_true,
@@ -317,7 +324,7 @@ def main():
 
     # dominant kernel of the flagship variant: the SpMV + inner-product kernel
     kt = dict(M.time_kernels(args.variant, 200))
-    kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused)
+    kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
     dom = max((k for k in kt if k in kb), key=lambda k: kt[k])
     achieved = kb[dom] / (kt[dom] * 1e-3) / 1e9
     tb = load_traffic(dom, workload)

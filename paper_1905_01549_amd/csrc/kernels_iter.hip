@@ -85,10 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_init_r(SellView S, CsrView C, Split 
 }
 
 // s0 = A p0 (s~0 = M^{-1} s0 stored when it evolves by recurrence);
-// partials of mu0, sigma0, gamma0, nu0, <r0, r0>.
+// partials of mu0, sigma0, gamma0 (to PS) and nu0, <r0, r0> (to PN).
 template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split sp, Vecs v, int store_st,
-                                                   double* __restrict__ PS)
+                                                   double* __restrict__ PS, double* __restrict__ PN)
 {
     __shared__ double lds[kWaves * 5];
     int64_t g0, g1;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split 
             acc[4] = fma(ri, ri, acc[4]);      // <r0, r0>
         });
     }
-    write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+    write_partials_at<5, 3>(acc, PS, PN, sp.Gs, blockIdx.x, lds);
 }
 
 // pipe-PR-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0; the block
@@ -140,14 +140,15 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
 // step0 = 2 also forms alpha_0 from mu_0.
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
-                                                        const double* __restrict__ PS, State* __restrict__ out,
-                                                        double* __restrict__ hist, double tol, int maxit)
+                                                        const double* __restrict__ PS, const double* __restrict__ PN,
+                                                        State* __restrict__ out, double* __restrict__ hist, double tol,
+                                                        int maxit)
 {
     __shared__ double lds[kWaves * 5];
     double bb[1];
     reduce_partials<1>(PB, sp.G, sp.Gs, bb, lds);
     double t[5];
-    reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+    reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
     State st = {};
     st.bnorm = sqrt(bb[0]);
     st.tol = tol;
@@ -182,14 +183,21 @@ __device__ __forceinline__ void row_range(const Split& sp, int64_t g0, int64_t g
 
 // Stage 2 of iteration k + scalar step, then the vector updates of
 // iteration k+1 (Alg. 2): x += alpha p; r -= alpha s; r~ -= alpha s~;
-// p = r~ + beta p.
-// REDUCE = false: the state was already advanced by k_finish_one and `in`
-// is the current state (`out` unused).
-template <bool PRE, bool REDUCE>
+// p = r~ + beta p.  The partials of iteration k are read from PS (mu, sigma,
+// gamma) and PN (nu, <r, r>).
+// REDUCE = false: the state was already advanced (k_finish_one, or the last
+// workgroup of the product kernel) and `in` is the current state.
+// NUDOT (Jacobi, REDUCE = false): this kernel also writes the partials of
+// nu_{k+1} = <r~, r> and <r, r> of the rows it has just updated to PN, so
+// the product kernel need not read r again.
+template <bool PRE, bool REDUCE, bool NUDOT>
 __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
-                                                      const double* __restrict__ PS, int meurant, Vecs v)
+                                                      const double* __restrict__ PS, double* __restrict__ PN,
+                                                      int meurant, Vecs v)
 {
+    static_assert(!(REDUCE && NUDOT), "PN is read by every workgroup when REDUCE");
+    static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
     __shared__ double lds[kWaves * 5];
     State st = *in;
     if (REDUCE) {
@@ -198,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
             return;
         }
         double t[5];
-        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, meurant != 0, hist, writer_thread());
         if (writer_thread()) *out = st;
     }
@@ -213,6 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
     double* __restrict__ p = v.p;
     const double* __restrict__ s = v.s;
     const double* __restrict__ d = v.d;
+    double acc[2] = {0.0, 0.0};
     // two rows per step, every load issued before the first store
     for (int64_t i = i0; i < i1; i += 2 * kBlock) {
         const int64_t j = i + kBlock;
@@ -236,13 +245,22 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
         r[i] = rn0;
         if (PRE) rt[i] = rtn0;
         p[i] = fma(beta, p0, rtn0);
+        if (NUDOT) {
+            acc[0] = fma(rtn0, rn0, acc[0]);
+            acc[1] = fma(rn0, rn0, acc[1]);
+        }
         if (two) {
             x[j] = fma(alpha, p1, x1);
             r[j] = rn1;
             if (PRE) rt[j] = rtn1;
             p[j] = fma(beta, p1, rtn1);
+            if (NUDOT) {
+                acc[0] = fma(rtn1, rn1, acc[0]);
+                acc[1] = fma(rn1, rn1, acc[1]);
+            }
         }
     }
+    if (NUDOT) write_partials<2>(acc, PN, sp.Gs, blockIdx.x, lds);
 }
 
 // One workgroup: stage 2 of iteration k and the scalar step of a
@@ -251,13 +269,14 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
-                                                      const double* __restrict__ PS, int meurant)
+                                                      const double* __restrict__ PS, const double* __restrict__ PN,
+                                                      int meurant)
 {
     __shared__ double lds[kWaves * 5];
     State st = *in;
     if (!st.done) {
         double t[5];
-        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
@@ -293,14 +312,18 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* 
 }
 
 // s_k = A p_k, s~_k = M^{-1} s_k, and the inner products of Alg. 2
-// mu = <p, s>, sigma = <r~, s>, gamma = <s~, s>, nu = <r~, r> (+ <r, r>).
+// mu = <p, s>, sigma = <r~, s>, gamma = <s~, s> (to PS) and, with NUDOT,
+// nu = <r~, r> (+ <r, r>) (to PN; otherwise the update kernel wrote them).
 // LAST: the last workgroup also runs stage 2 and the scalar step, advancing
 // the state from `in` to `out`.
-template <int LANES, bool PRE, bool LAST>
+template <int LANES, bool PRE, bool LAST, bool NUDOT>
 __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ hist,
-                                                    double* __restrict__ PS, int meurant, int* ticket, Vecs v)
+                                                    double* __restrict__ PS, double* __restrict__ PN, int meurant,
+                                                    int* ticket, Vecs v)
 {
+    static_assert(PRE || NUDOT, "without a preconditioner nu = <r, r> is formed here");
+    constexpr int NV = NUDOT ? 5 : 3;
     __shared__ double lds[kWaves * 5];
     if (in->done) {
         if (LAST && writer_thread()) *out = *in;
@@ -308,25 +331,29 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
     }
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
     for (int64_t g = g0; g < g1; ++g) {
         rows_of_group<LANES, 1>(S, C, g, v.p, nullptr, [&](int64_t i, double si, double) {
             v.s[i] = si;
-            const double ri = v.r[i];
-            const double rti = PRE ? v.rt[i] : ri;
+            const double rti = PRE ? v.rt[i] : v.r[i];
             const double sti = PRE ? v.d[i] * si : si;
             acc[0] = fma(v.p[i], si, acc[0]);
             acc[1] = fma(rti, si, acc[1]);
             acc[2] = fma(sti, si, acc[2]);
-            acc[3] = fma(rti, ri, acc[3]);
-            if (PRE) acc[4] = fma(ri, ri, acc[4]);
+            if constexpr (NUDOT) {
+                const double ri = PRE ? v.r[i] : rti;
+                acc[3] = fma(rti, ri, acc[3]);
+                if (PRE) acc[4] = fma(ri, ri, acc[4]);
+            }
         });
     }
-    write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+    write_partials_at<NV, 3>(acc, PS, PN, sp.Gs, blockIdx.x, lds);
     if (LAST && take_last_ticket(ticket, sp.G)) {
         State st = *in;
         double t[5];
-        reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
         if (threadIdx.x == 0) *out = st;
     }
@@ -638,6 +665,19 @@ SellView sell_or_empty(const SellView* s)
 }
 CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullptr, nullptr, 0}; }
 
+// With a preconditioner and stage 2 outside the update kernel, PR's update
+// kernel forms nu and <r, r> (in PN); otherwise the product kernel forms all
+// five inner products, and PN is the tail of PS.
+bool nu_in_update(int variant, int pre, const Split& sp)
+{
+    return pre && (variant == kPR || variant == kM) && !sp.fused && (stage2_of(sp, kPR) || sp.lastwg);
+}
+
+double* pn_of(int variant, int pre, const Split& sp, const Bufs& B)
+{
+    return nu_in_update(variant, pre, sp) ? B.PN : B.PS + 3 * (int64_t)sp.Gs;
+}
+
 }  // namespace
 
 hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView* csr, const Split& sp,
@@ -654,7 +694,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
             hipLaunchKernelGGL((k_init_r<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
                                S, C, sp, b, x0, v, store_rt, B.PB);
             hipLaunchKernelGGL((k_init_s<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
-                               S, C, sp, v, store_st, B.PS);
+                               S, C, sp, v, store_st, B.PS, pn_of(variant, pre, sp, B));
             if (pipe)
                 hipLaunchKernelGGL((k_init_u<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0,
                                    st, S, C, sp, v);
@@ -666,7 +706,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
         const bool pipe2 = (variant == kPipePR || variant == kPipeM) && !sp.fused;
         const int step0 = variant == kHS ? (sp.lastwg ? 2 : 1) : (pipe2 || sp.lastwg ? 1 : 0);
         hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
-                           B.PB, B.PS, B.S[0], B.hist, tol, (int)maxit);
+                           B.PB, B.PS, pn_of(variant, pre, sp, B), B.S[0], B.hist, tol, (int)maxit);
         return hipGetLastError();
     });
 }
@@ -720,32 +760,56 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
             const bool s2 = stage2_of(sp, variant);
             switch (variant) {
             case kPR:
-            case kM:
+            case kM: {
+                double* PN = pn_of(variant, pre, sp, B);
+                const bool nu_up = nu_in_update(variant, pre, sp);
+                // the update kernel without a reduction, forming nu when nu_up
+                auto update = [&]() {
+                    if constexpr (PP) {
+                        if (nu_up) {
+                            launch(k_pr_update<PP, false, true>, grid, block, st, ev, sp, (const State*)B.S[cur],
+                                   B.S[nxt], B.hist, (const double*)B.PS, PN, meurant, v);
+                            return;
+                        }
+                    }
+                    launch(k_pr_update<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, PN, meurant, v);
+                };
+                // the product kernel (LAST: with the reduction in its last workgroup)
+                auto product = [&](auto last) {
+                    constexpr bool LA = decltype(last)::value;
+                    if constexpr (PP) {
+                        if (nu_up) {
+                            launch(k_pr_spmv<LL, PP, LA, false>, grid, block, st, ev, S, C, sp,
+                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, meurant, tk, v);
+                            return;
+                        }
+                    }
+                    launch(k_pr_spmv<LL, PP, LA, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                           B.S[nxt], B.hist, B.PS, PN, meurant, tk, v);
+                };
                 if (sp.lastwg) {
                     if (j == 0) {
-                        launch(k_pr_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                               B.hist, (const double*)B.PS, meurant, v);
+                        update();
                     } else {
-                        launch(k_pr_spmv<LL, PP, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                               B.S[nxt], B.hist, B.PS, meurant, tk, v);
+                        product(std::true_type{});
                         cur = nxt;
                     }
                 } else if (s2 && j == 0) {
                     launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
-                           (const double*)B.PS, meurant);
+                           (const double*)B.PS, (const double*)PN, meurant);
                     cur = nxt;
                 } else if (s2 && j == 1) {
-                    launch(k_pr_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, meurant, v);
+                    update();
                 } else if (j == 0) {
-                    launch(k_pr_update<PP, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, meurant, v);
+                    launch(k_pr_update<PP, true, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, PN, meurant, v);
                     cur = nxt;
                 } else {
-                    launch(k_pr_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, B.PS, meurant, tk, v);
+                    product(std::false_type{});
                 }
                 break;
+            }
             case kPipePR:
             case kPipeM:
                 if (sp.lastwg) {
@@ -765,7 +829,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                            B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
                 } else if (s2) {
                     launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
-                           (const double*)B.PS, meurant);
+                           (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), meurant);
                     cur = nxt;
                 } else {
                     launch(k_pipe_spmv<LL, PP, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],

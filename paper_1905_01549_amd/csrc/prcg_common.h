@@ -128,6 +128,7 @@ struct Bufs {
     State* S[2];
     double* hist;
     double* PS;   // [mu, sigma, gamma, nu, rr] partials
+    double* PN;   // [nu, rr] partials when PR's update kernel produces them
     double* PU;   // [nu, rr] partials (HS)
     double* PB;   // [bb] or [tt] partials
     double* PS2;  // second copy of PS (fused kernels alternate between the two)

@@ -41,12 +41,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * N
 }
 
 // Stage 2 of a reduction: the G per-workgroup partials of each of NV values
-// (value i at P[i * Gs + g], G <= kMaxGrid) are summed in a fixed order.
-// Every thread of the calling workgroup receives the totals.  All loads are
-// issued before the first addition so the cost is one memory latency.
-template <int NV>
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
-                                                double* lds)
+// are summed in a fixed order (G <= kMaxGrid).  Value i < N1 is read from
+// P1[i * Gs + g], value i >= N1 from P2[(i - N1) * Gs + g] (two kernels may
+// produce the partials of one reduction).  Every thread of the calling
+// workgroup receives the totals.  All loads are issued before the first
+// addition so the cost is one memory latency.
+template <int NV, int N1>
+__device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1, const double* __restrict__ P2, int G,
+                                                   int Gs, double (&tot)[NV], double* lds)
 {
     constexpr int kPer = kMaxGrid / kBlock;
     double buf[NV][kPer];
@@ -54,7 +56,10 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, in
     for (int j = 0; j < kPer; ++j) {
         const int g = threadIdx.x + j * kBlock;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) buf[i][j] = g < G ? P[i * Gs + g] : 0.0;
+        for (int i = 0; i < NV; ++i) {
+            const double* P = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+            buf[i][j] = g < G ? P[g] : 0.0;
+        }
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -66,16 +71,34 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, in
     block_sum<NV>(tot, lds);
 }
 
-// Stage 1: per-thread sums -> one partial per workgroup and value.
 template <int NV>
-__device__ __forceinline__ void write_partials(double (&acc)[NV], double* __restrict__ P, int Gs, int slot,
-                                               double* lds)
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
+                                                double* lds)
+{
+    reduce_partials_at<NV, NV>(P, nullptr, G, Gs, tot, lds);
+}
+
+// Stage 1: per-thread sums -> one partial per workgroup and value (value
+// i < N1 to P1, the others to P2, with the layout of reduce_partials_at).
+template <int NV, int N1>
+__device__ __forceinline__ void write_partials_at(double (&acc)[NV], double* __restrict__ P1, double* __restrict__ P2,
+                                                  int Gs, int slot, double* lds)
 {
     block_sum<NV>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) P[i * Gs + slot] = acc[i];
+        for (int i = 0; i < NV; ++i) {
+            double* P = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+            P[slot] = acc[i];
+        }
     }
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&acc)[NV], double* __restrict__ P, int Gs, int slot,
+                                               double* lds)
+{
+    write_partials_at<NV, NV>(acc, P, nullptr, Gs, slot, lds);
 }
 
 // Stage 2 by the last workgroup.  After thread 0 has written the

@@ -51,18 +51,23 @@ KERNEL_WORDS[("pipe_m", True)] = KERNEL_WORDS[("pipe_pr", True)]
 
 
 def kernel_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int, fused: bool = False,
-                 textbook: bool = False) -> dict:
-    """Algorithmic bytes per launch of each kernel of one iteration."""
+                 textbook: bool = False, nu_in_update: bool = False) -> dict:
+    """Algorithmic bytes per launch of each kernel of one iteration.
+
+    nu_in_update: PR/M with Jacobi, where the update kernel forms <r~, r> and
+    <r, r> from the rows it writes, so the product kernel does not read r."""
     out = {}
     table = KERNEL_WORDS_TEXTBOOK if textbook else (KERNEL_WORDS_FUSED if fused else KERNEL_WORDS)
     for name, r, w, mat in table[(variant, jacobi)]:
+        if nu_in_update and jacobi and not fused and name == "k_pr_spmv":
+            r -= 1
         out[name] = 8 * n * (r + w) + (matrix_bytes if mat else 0)
     return out
 
 
 def iteration_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int, fused: bool = False,
-                    textbook: bool = False) -> int:
-    return sum(kernel_bytes(variant, jacobi, n, matrix_bytes, fused, textbook).values())
+                    textbook: bool = False, nu_in_update: bool = False) -> int:
+    return sum(kernel_bytes(variant, jacobi, n, matrix_bytes, fused, textbook, nu_in_update).values())
 
 
 def csr_matrix_bytes(n: int, nnz: int) -> int:
