@@ -209,8 +209,9 @@ prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x
  * Per-kernel device time of `iters` iterations of variant v on A, from
  * x0 = 0 with b = (1, ..., 1) and tol = 0 (so every iteration does its full
  * work; PRCG_EDEVICE if the run ends early).  Each launch carries dispatch
- * start/stop timestamps (hipExtLaunchKernelGGL events), so the times are
- * kernel execution times.  Overwrites the solver state of A.
+ * start/stop timestamps (hipExtLaunchKernelGGL events) and runs on the
+ * handle's own non-blocking stream after A's stream has drained, so the
+ * times are kernel execution times.  Overwrites the solver state of A.
  *   ms_per_launch  host float64[capacity]: average milliseconds per launch
  *                  of each kernel of one iteration, in launch order.
  *   names          host, nullable, char[capacity][48]: kernel names.

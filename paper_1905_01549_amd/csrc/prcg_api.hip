@@ -666,13 +666,18 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
     if (s != PRCG_OK) return s;
     const Vecs vv = A->vecs_view();
     const Bufs B = A->bufs();
+    // The timed launches go to the handle's own non-blocking stream (after
+    // the caller's stream has drained): dispatch timestamps on a
+    // non-blocking stream measure the kernel alone.
+    HIP_TRY(hipStreamSynchronize(A->stream));
+    hipStream_t ts = A->capture;
     // right-hand side: the spare vector filled with ones; x0 = 0 (vector x)
     const int nk = iter_kernel_count(v, A->sp);
     std::vector<double> ones((size_t)A->n, 1.0);
     double* bvec = A->spare();
-    HIP_TRY(hipMemcpyAsync(bvec, ones.data(), sizeof(double) * A->n, hipMemcpyHostToDevice, A->stream));
-    HIP_TRY(hipMemsetAsync(vv.x, 0, sizeof(double) * A->n, A->stream));
-    HIP_TRY(launch_init(v, A->precond, A->sellp(), A->csrp(), A->sp, vv, B, bvec, vv.x, 0.0, iters + 1, A->stream));
+    HIP_TRY(hipMemcpyAsync(bvec, ones.data(), sizeof(double) * A->n, hipMemcpyHostToDevice, ts));
+    HIP_TRY(hipMemsetAsync(vv.x, 0, sizeof(double) * A->n, ts));
+    HIP_TRY(launch_init(v, A->precond, A->sellp(), A->csrp(), A->sp, vv, B, bvec, vv.x, 0.0, iters + 1, ts));
     std::vector<hipEvent_t> ev((size_t)2 * nk * iters, nullptr);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     int cur = 0;
@@ -681,9 +686,9 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
         for (int j = 0; j < nk && err == hipSuccess; ++j) {
             const size_t q = (size_t)2 * (it * nk + j);
             const LaunchEvents le{ev[q], ev[q + 1]};
-            err = launch_iteration(A, v, j, it, cur, A->stream, &le);
+            err = launch_iteration(A, v, j, it, cur, ts, &le);
         }
-    if (err == hipSuccess) err = hipStreamSynchronize(A->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(ts);
     std::vector<double> tot((size_t)nk, 0.0);
     for (int it = 0; it < iters && err == hipSuccess; ++it)
         for (int j = 0; j < nk && err == hipSuccess; ++j) {
