@@ -72,6 +72,13 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def variants_of(kern: str):
+    """Variants timed under a kernel structure (GV-CG has one structure)."""
+    if kern == "textbook":
+        return ("hs",)
+    return ("hs", "pr", "pipe_pr", "gv") if kern == "two_pass" else ("hs", "pr", "pipe_pr")
+
+
 def nu_split(M) -> bool:
     """Whether PR's update kernel forms <r~, r> and <r, r> (Jacobi): stage 2
     outside the update kernel, i.e. in its own kernel or a last workgroup."""
@@ -178,33 +185,46 @@ def adjoint_section(torch, prcg, problems):
     rows = torch.as_tensor(np.repeat(np.arange(A.n), np.diff(A.row_ptr)), device="cuda")
     cols = torch.as_tensor(A.col_idx.astype(np.int64), device="cuda")
 
-    def unrolled_grad():
+    def unrolled_grad(k):
         vals = vals0.clone().requires_grad_(True)
         b = b0.clone().requires_grad_(True)
-        x = unrolled_pr_cg(torch, rows, cols, vals, b, iters)
+        x = unrolled_pr_cg(torch, rows, cols, vals, b, k)
         (w * x).sum().backward()
         return vals.grad, b.grad
 
-    uv, ub = unrolled_grad()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    uv, ub = unrolled_grad()
-    torch.cuda.synchronize()
-    t_unr = time.perf_counter() - t
-    dv = float((uv - gv).abs().max() / gv.abs().max())
-    db = float((ub - gb).abs().max() / gb.abs().max())
+    # the unrolled values-gradient converges about twice as slowly as the
+    # iterate: time it at the forward iteration count and at twice that
+    unrolled = {}
+    unrolled_grad(iters)  # warm-up (allocator, kernels)
+    for k in (iters, 2 * iters):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        uv, ub = unrolled_grad(k)
+        torch.cuda.synchronize()
+        unrolled[k] = {"iterations": k, "ms": (time.perf_counter() - t) * 1e3,
+                       "max_rel_diff_values_grad": float((uv - gv).abs().max() / gv.abs().max()),
+                       "max_rel_diff_b_grad": float((ub - gb).abs().max() / gb.abs().max())}
     M.close()
+    same, twice = unrolled[iters], unrolled[2 * iters]
     return {"workload": "varcoef7_96", "n": int(A.n), "nnz": int(A.nnz), "forward_iterations": iters,
             "adjoint_gradients_per_s": 1.0 / t_adj, "adjoint_ms": t_adj * 1e3,
-            "unrolled_autograd_gradients_per_s": 1.0 / t_unr, "unrolled_ms": t_unr * 1e3,
-            "speedup": t_unr / t_adj, "max_rel_diff_values_grad": dv, "max_rel_diff_b_grad": db}
+            "unrolled_autograd_gradients_per_s": 1e3 / twice["ms"], "speedup": twice["ms"] * 1e-3 / t_adj,
+            "unrolled_same_iterations": same, "unrolled_twice_iterations": twice,
+            "speedup_vs_same_iterations": same["ms"] * 1e-3 / t_adj}
 
 
 def suite(torch, prcg, problems):
     """Per-iteration time of every variant on every workload (printed, one
     JSON line per workload and kernel structure)."""
+    def shard():
+        # one GPU's rows of the 128^3 problem split into 8 z-slabs (no halo)
+        A = problems.poisson3d(128, 128, 16)
+        return problems.Problem(name="poisson3d_128x128x16_jacobi", A=A, b=problems.uniform_vector(A.n, 2),
+                                precond="jacobi")
+
     work = [("poisson2d_64", problems.config1, "none", 1e-10, 5000),
             ("poisson3d_128_jacobi", problems.config2, "jacobi", 1e-10, 1000),
+            ("poisson3d_128x128x16_jacobi", shard, "jacobi", 1e-10, 2000),
             ("model_diag_1e6", problems.config3a, "none", 1e-10, 20000),
             ("varcoef27_160", problems.config3b, "none", 1e-10, 20000),
             ("varcoef7_96", problems.config5, "none", 1e-10, 20000)]
@@ -215,7 +235,7 @@ def suite(torch, prcg, problems):
         for kern in STRUCTURES:
             M.set_kernels(kern)
             out = {"workload": name, "n": pr.A.n, "nnz": pr.A.nnz, "kernels": kern}
-            for v in (("hs",) if kern == "textbook" else ("hs", "pr", "pipe_pr")):
+            for v in variants_of(kern):
                 x, info = M.solve(b, v, tol, maxit)
                 best = float("inf")
                 for _ in range(2):
@@ -297,7 +317,7 @@ def main():
     variants = {}
     for kern in STRUCTURES:
         M.set_kernels(kern)
-        for v in (("hs",) if kern == "textbook" else ("hs", "pr", "pipe_pr")):
+        for v in variants_of(kern):
             vi = solve(v)
             best = float("inf")
             for _ in range(2):

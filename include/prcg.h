@@ -53,13 +53,23 @@ typedef struct prcg_batch_s* prcg_batch;
  *                s, s~, w', w~'; the products u = A s~ and w = A r~ (the
  *                recompute of w') read A once and overlap the reduction.
  *   PRCG_M       M-CG (Appendix D): PR-CG with nu'_k = -nu_{k-1} + alpha^2 gamma.
- *   PRCG_PIPE_M  pipe-PR-M-CG (Appendix D): pipe-PR-CG with the M-CG nu'.   */
+ *   PRCG_PIPE_M  pipe-PR-M-CG (Appendix D): pipe-PR-CG with the M-CG nu'.
+ *   PRCG_GV      GV-CG (Appendix D), the Ghysels-Vanroose pipelined CG the
+ *                paper compares against: recurrences for w, s, u and
+ *                mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k; one product
+ *                t = A w~ per iteration overlaps the reduction.
+ *   PRCG_PR_NORECOMPUTE  the ablation of Section 2: PR-CG that keeps the
+ *                predicted nu'_k as nu_k (eq. nuk_norecomp) instead of
+ *                recomputing it; it loses accuracy and is for study only.
+ * The batched solver runs the first five. */
 typedef enum {
     PRCG_HS = 0,
     PRCG_PR = 1,
     PRCG_PIPE_PR = 2,
     PRCG_M = 3,
-    PRCG_PIPE_M = 4
+    PRCG_PIPE_M = 4,
+    PRCG_GV = 5,
+    PRCG_PR_NORECOMPUTE = 6
 } prcg_variant;
 
 /* Preconditioners: none (M = I) or Jacobi (M^{-1} = diag(A)^{-1}). */

@@ -37,7 +37,7 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
 
 template <int NT, bool PRE, int KIND>
 __device__ void solve_system(const BatchView& B, const Vecs& v, const double* __restrict__ b, double tol,
-                             int maxit, int meurant, int sys, int32_t* __restrict__ iters_out,
+                             int maxit, int form, int sys, int32_t* __restrict__ iters_out,
                              int32_t* __restrict__ status_out, double* lds)
 {
     constexpr int NW = NT / 64;
@@ -103,7 +103,7 @@ __device__ void solve_system(const BatchView& B, const Vecs& v, const double* __
             sys_spmv<NT, 1>(B, sl0, sl1, PRE ? stv : s, nullptr, [&](int64_t i, double ui, double) { u[i] = ui; });
             __syncthreads();
         }
-        step_one_reduction(st, t5, PRE, meurant != 0, nullptr, false);
+        step_one_reduction(st, t5, PRE, form, nullptr, false);
     }
 
     while (!st.done) {
@@ -133,7 +133,7 @@ __device__ void solve_system(const BatchView& B, const Vecs& v, const double* __
                 if (PRE) q[4] = fma(ri, ri, q[4]);
             });
             block_sum<5, NW>(q, lds);
-            step_one_reduction(st, q, PRE, meurant != 0, nullptr, false);
+            step_one_reduction(st, q, PRE, form, nullptr, false);
         } else if (KIND == 2) {
             // Alg. 3: all vector updates and the inner products in one pass
             double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -162,7 +162,7 @@ __device__ void solve_system(const BatchView& B, const Vecs& v, const double* __
                 if (PRE) q[4] = fma(rn, rn, q[4]);
             }
             block_sum<5, NW>(q, lds);  // its barriers also publish the updated vectors
-            step_one_reduction(st, q, PRE, meurant != 0, nullptr, false);
+            step_one_reduction(st, q, PRE, form, nullptr, false);
             if (st.done) break;
             // u = A s~, w = A r~ (one pass over the system's matrix)
             sys_spmv<NT, 2>(B, sl0, sl1, PRE ? stv : s, PRE ? rt : r, [&](int64_t i, double ui, double wi) {
@@ -208,7 +208,7 @@ __device__ void solve_system(const BatchView& B, const Vecs& v, const double* __
 
 template <int NT, bool PRE, int KIND>
 __global__ __launch_bounds__(NT) void k_batch(BatchView B, Vecs v, const double* __restrict__ b, double tol,
-                                              int maxit, int meurant, int32_t* __restrict__ queue,
+                                              int maxit, int form, int32_t* __restrict__ queue,
                                               int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out)
 {
     __shared__ double lds[(NT / 64) * 6];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchView B, Vecs v, const double*
         const int q = s_next;
         __syncthreads();
         if (q >= B.nsys) return;  // the queue only grows: every workgroup reaches this
-        solve_system<NT, PRE, KIND>(B, v, b, tol, maxit, meurant, B.order[q], iters_out, status_out, lds);
+        solve_system<NT, PRE, KIND>(B, v, b, tol, maxit, form, B.order[q], iters_out, status_out, lds);
     }
 }
 
@@ -244,12 +244,12 @@ hipError_t launch_batch(const BatchView& B, const Vecs& v, const double* b, doub
                         int pre, int nt, int grid, int32_t* queue, int32_t* iters, int32_t* status, hipStream_t st)
 {
     const int kind = variant == kHS ? 0 : (variant == kPR || variant == kM) ? 1 : 2;
-    const int meurant = variant == kM || variant == kPipeM;
+    const int form = nu_form(variant);
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, queue);
     auto body = [&](auto NTc, auto P, auto Kc) -> hipError_t {
         constexpr int T = decltype(NTc)::value;
         hipLaunchKernelGGL((k_batch<T, decltype(P)::value, decltype(Kc)::value>), dim3(grid), dim3(T), 0, st, B, v, b,
-                           tol, maxit, meurant, queue, iters, status);
+                           tol, maxit, form, queue, iters, status);
         return hipGetLastError();
     };
     switch (nt) {

@@ -29,7 +29,7 @@ __device__ __forceinline__ bool writer() { return blockIdx.x == 0 && threadIdx.x
 template <bool PRE>
 __device__ __forceinline__ bool enter_one_reduction(const Split& sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ hist,
-                                                    const double* __restrict__ Pin, int meurant, State& st,
+                                                    const double* __restrict__ Pin, int form, State& st,
                                                     double* lds)
 {
     st = *in;
@@ -39,7 +39,7 @@ __device__ __forceinline__ bool enter_one_reduction(const Split& sp, const State
     }
     double t[5];
     reduce_partials<5>(Pin, sp.G, sp.Gs, t, lds);
-    step_one_reduction(st, t, PRE, meurant != 0, hist, writer());
+    step_one_reduction(st, t, PRE, form, hist, writer());
     if (writer()) *out = st;
     return !st.done;
 }
@@ -80,11 +80,11 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const State* __restrict__ in,
                                                      State* __restrict__ out, double* __restrict__ hist,
                                                      const double* __restrict__ Pin, double* __restrict__ Pout,
-                                                     int meurant, FusedVecs f, int q)
+                                                     int form, FusedVecs f, int q)
 {
     __shared__ double lds[kWaves * 5];
     State st;
-    if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, meurant, st, lds)) return;
+    if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, form, st, lds)) return;
     const double alpha = st.alpha, beta = st.beta;
     const double* __restrict__ p_o = f.p[q];
     double* __restrict__ p_n = f.p[1 - q];
@@ -159,11 +159,11 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, const State* __restrict__ in,
                                                        State* __restrict__ out, double* __restrict__ hist,
                                                        const double* __restrict__ Pin, double* __restrict__ Pout,
-                                                       int meurant, FusedVecs f, int q)
+                                                       int form, FusedVecs f, int q)
 {
     __shared__ double lds[kWaves * 5];
     State st;
-    if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, meurant, st, lds)) return;
+    if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, form, st, lds)) return;
     const double alpha = st.alpha, beta = st.beta;
     const double* __restrict__ t_o = PRE ? f.rt[q] : f.r[q];
     double* __restrict__ t_n = PRE ? f.rt[1 - q] : f.r[1 - q];
@@ -311,7 +311,7 @@ hipError_t launch_fused_kernel(int variant, int pre, int j, int it, int& cur, co
     const dim3 grid(sp.G), block(kBlock);
     const int q = it & 1;
     const int nxt = 1 - cur;
-    const int meurant = variant == kM || variant == kPipeM;
+    const int form = nu_form(variant);
     double* Pq[2] = {B.PS, PS2};
     auto go = [&](auto kernel, auto... args) {
         if (ev && ev->start)
@@ -321,17 +321,17 @@ hipError_t launch_fused_kernel(int variant, int pre, int j, int it, int& cur, co
         return hipGetLastError();
     };
     hipError_t e = hipSuccess;
-    if (variant == kPR || variant == kM) {
+    if (variant == kPR || variant == kM || variant == kPRNoRecompute) {
         e = pre ? go(k_pr_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], meurant, f, q)
+                     Pq[1 - q], form, f, q)
                 : go(k_pr_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], meurant, f, q);
+                     Pq[1 - q], form, f, q);
         cur = nxt;
     } else if (variant == kPipePR || variant == kPipeM) {
         e = pre ? go(k_pipe_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], meurant, f, q)
+                     Pq[1 - q], form, f, q)
                 : go(k_pipe_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], meurant, f, q);
+                     Pq[1 - q], form, f, q);
         cur = nxt;
     } else {
         // HS: the first kernel is the two-pass k_hs_xr on the current buffers

@@ -112,10 +112,12 @@ __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split 
     write_partials_at<5, 3>(acc, PS, PN, sp.Gs, blockIdx.x, lds);
 }
 
-// pipe-PR-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0; the block
-// vectors (s~0, r~0) and (u0, w0) are filled as well.
+// pipe-PR-CG and GV-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0; the
+// block vectors (s~0, r~0) and (u0, w0) are filled as well.  GV also keeps
+// t := u0 and w~0 = M^{-1} w0 = s~0, so that its first direction update
+// (beta = 0) reproduces p0, s0, s~0 and u0.
 template <int LANES, bool PRE>
-__global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split sp, Vecs v)
+__global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split sp, Vecs v, int gv)
 {
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
@@ -128,6 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
             v.w[i] = si;
             v.uw[i] = make_double2(ui, si);
             v.zr[i] = make_double2(st[i], rt[i]);
+            if (gv) {
+                v.t[i] = ui;
+                if (PRE) v.wt[i] = st[i];
+            }
         });
     }
 }
@@ -166,8 +172,10 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, 
     } else if (variant == kHS) {
         step_hs_nu(st, t[3], PRE ? t[4] : t[3], hist, w);
         if (step0 == 2 && !st.done) step_hs_mu(st, t[0]);
+    } else if (variant == kGV) {
+        step_gv_first(st, t, PRE, hist, w);
     } else if (step0) {
-        step_one_reduction(st, t, PRE, variant == kM || variant == kPipeM, hist, w);
+        step_one_reduction(st, t, PRE, nu_form(variant), hist, w);
     }
     // otherwise the first iteration kernel performs the step for k = 0
     if (w) *out = st;
@@ -194,7 +202,7 @@ template <bool PRE, bool REDUCE, bool NUDOT>
 __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, double* __restrict__ PN,
-                                                      int meurant, Vecs v)
+                                                      int form, Vecs v)
 {
     static_assert(!(REDUCE && NUDOT), "PN is read by every workgroup when REDUCE");
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
         }
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
-        step_one_reduction(st, t, PRE, meurant != 0, hist, writer_thread());
+        step_one_reduction(st, t, PRE, form, hist, writer_thread());
         if (writer_thread()) *out = st;
     }
     if (st.done) return;
@@ -270,14 +278,14 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, const double* __restrict__ PN,
-                                                      int meurant)
+                                                      int form)
 {
     __shared__ double lds[kWaves * 5];
     State st = *in;
     if (!st.done) {
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
-        step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+        step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
 }
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* 
 template <int LANES, bool PRE, bool LAST, bool NUDOT>
 __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ hist,
-                                                    double* __restrict__ PS, double* __restrict__ PN, int meurant,
+                                                    double* __restrict__ PS, double* __restrict__ PN, int form,
                                                     int* ticket, Vecs v)
 {
     static_assert(PRE || NUDOT, "without a preconditioner nu = <r, r> is formed here");
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
         State st = *in;
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
-        step_one_reduction(st, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+        step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
         if (threadIdx.x == 0) *out = st;
     }
 }
@@ -372,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
 template <bool PRE, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* __restrict__ in,
                                                         State* __restrict__ out, double* __restrict__ hist,
-                                                        double* __restrict__ PS, int meurant, int* ticket, Vecs v)
+                                                        double* __restrict__ PS, int form, int* ticket, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
     const State st = *in;
@@ -425,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
         State nx = st;
         double t[5];
         reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
-        step_one_reduction(nx, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+        step_one_reduction(nx, t, PRE, form, hist, threadIdx.x == 0);
         if (threadIdx.x == 0) *out = nx;
     }
 }
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
 template <int LANES, bool PRE, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
-                                                      const double* __restrict__ PS, int meurant, Vecs v)
+                                                      const double* __restrict__ PS, int form, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
     const State st = *in;
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
         if (!st.done) {
             double t[5];
             reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
-            step_one_reduction(nx, t, PRE, meurant != 0, hist, threadIdx.x == 0);
+            step_one_reduction(nx, t, PRE, form, hist, threadIdx.x == 0);
         }
         if (threadIdx.x == 0) *out = nx;
     }
@@ -464,6 +472,99 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
             uw[i] = make_double2(ui, wi);
         });
     }
+}
+
+// ------------------------------------------------------------------ GV-CG
+
+// GV-CG (Appendix D) in two kernels per iteration.  This one first finishes
+// iteration k-1's direction updates with beta_{k-1} (they wait for the
+// reduction of iteration k-1) and then takes iteration k's updates with
+// alpha_{k-1}; every operation is row-local:
+//   p = r~ + beta p; s = w + beta s; s~ = w~ + beta s~; u = t + beta u;
+//   x += alpha p; r -= alpha s; r~ -= alpha s~; w -= alpha u; w~ = M^{-1} w;
+// then the partials of nu_k = <r~, r>, eta_k = <r~, w> (+ <r, r>).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_gv_update(Split sp, const State* __restrict__ cur,
+                                                      double* __restrict__ PS, Vecs v)
+{
+    __shared__ double lds[kWaves * 3];
+    const State st = *cur;
+    if (st.done) return;
+    const double alpha = st.alpha, beta = st.beta;
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    double* __restrict__ rt = v.rt;
+    double* __restrict__ p = v.p;
+    double* __restrict__ s = v.s;
+    double* __restrict__ stl = v.st;
+    double* __restrict__ w = v.w;
+    double* __restrict__ u = v.u;
+    double* __restrict__ wt = v.wt;
+    const double* __restrict__ t = v.t;
+    const double* __restrict__ d = v.d;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < i1; i += kBlock) {
+        const double pi = p[i], si = s[i], ui = u[i], ti = t[i], wi = w[i], xi = x[i], ri = r[i];
+        double rti = ri, sti = si, di = 1.0;
+        if (PRE) {
+            rti = rt[i];
+            sti = stl[i];
+            di = d[i];
+        }
+        const double pn = fma(beta, pi, rti);                     // p_{k-1}
+        const double sn = fma(beta, si, wi);                      // s_{k-1}
+        const double stn = PRE ? fma(beta, sti, di * wi) : sn;    // s~_{k-1} = w~_{k-1} + beta s~_{k-2}
+        const double un = fma(beta, ui, ti);                      // u_{k-1}
+        const double rn = fma(-alpha, sn, ri);                    // r_k
+        const double rtn = PRE ? fma(-alpha, stn, rti) : rn;      // r~_k
+        const double wn = fma(-alpha, un, wi);                    // w_k
+        x[i] = fma(alpha, pn, xi);                                // x_k
+        r[i] = rn;
+        p[i] = pn;
+        s[i] = sn;
+        u[i] = un;
+        w[i] = wn;
+        if (PRE) {
+            rt[i] = rtn;
+            stl[i] = stn;
+            wt[i] = di * wn;                                      // w~_k = M^{-1} w_k
+        }
+        acc[0] = fma(rtn, rn, acc[0]);                            // nu_k  = <r~_k, r_k>
+        acc[1] = fma(rtn, wn, acc[1]);                            // eta_k = <r~_k, w_k>
+        if (PRE) acc[2] = fma(rn, rn, acc[2]);
+    }
+    write_partials<3>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+// t_k = A w~_k.  Workgroup 0 first reduces nu_k, eta_k (+ <r_k, r_k>) and
+// performs the scalar step (beta_k, mu_k, tests, alpha_k), then takes its
+// share of the product: the reduction overlaps the product, as GV-CG is
+// designed for.
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_gv_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+                                                    State* __restrict__ out, double* __restrict__ hist,
+                                                    const double* __restrict__ PS, Vecs v)
+{
+    __shared__ double lds[kWaves * 3];
+    const State st = *in;
+    if (blockIdx.x == 0) {
+        State nx = st;
+        if (!st.done) {
+            double t[3];
+            reduce_partials<3>(PS, sp.G, sp.Gs, t, lds);
+            step_gv(nx, t, PRE, hist, threadIdx.x == 0);
+        }
+        if (threadIdx.x == 0) *out = nx;
+    }
+    if (st.done) return;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    double* __restrict__ t = v.t;
+    for (int64_t g = g0; g < g1; ++g)
+        rows_of_group<LANES, 1>(S, C, g, PRE ? v.wt : v.w, nullptr, [&](int64_t i, double ti, double) { t[i] = ti; });
 }
 
 // ------------------------------------------------------------------ HS-CG
@@ -670,7 +771,8 @@ CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullpt
 // five inner products, and PN is the tail of PS.
 bool nu_in_update(int variant, int pre, const Split& sp)
 {
-    return pre && (variant == kPR || variant == kM) && !sp.fused && (stage2_of(sp, kPR) || sp.lastwg);
+    const bool pr = variant == kPR || variant == kM || variant == kPRNoRecompute;
+    return pre && pr && !sp.fused && (stage2_of(sp, kPR) || sp.lastwg);
 }
 
 double* pn_of(int variant, int pre, const Split& sp, const Bufs& B)
@@ -688,16 +790,17 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     const CsrView C = csr_or_empty(csr);
     const bool pipe = variant == kPipePR || variant == kPipeM;
     const int store_rt = variant != kHS;  // r~ evolves by recurrence in PR and pipe-PR
-    const int store_st = pipe;            // s~ evolves by recurrence in pipe-PR
+    const int gv = variant == kGV;
+    const int store_st = pipe || gv;      // s~ evolves by recurrence in pipe-PR and GV
     hipError_t e = with_lanes(sp.lanes, [&](auto L) {
         return with_pre(pre, [&](auto P) {
             hipLaunchKernelGGL((k_init_r<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
                                S, C, sp, b, x0, v, store_rt, B.PB);
             hipLaunchKernelGGL((k_init_s<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
                                S, C, sp, v, store_st, B.PS, pn_of(variant, pre, sp, B));
-            if (pipe)
+            if (pipe || gv)
                 hipLaunchKernelGGL((k_init_u<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0,
-                                   st, S, C, sp, v);
+                                   st, S, C, sp, v, gv);
             return hipGetLastError();
         });
     });
@@ -713,6 +816,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
 
 int iter_kernel_count(int variant, const Split& sp)
 {
+    if (variant == kGV) return 2;  // one structure for GV-CG
     if (sp.textbook && variant == kHS) return textbook_kernel_count(sp.textbook_pre);
     if (sp.fused) return variant == kHS ? 2 : 1;
     if (variant == kHS) return stage2_of(sp, kHS) ? 5 : 3;
@@ -722,10 +826,11 @@ int iter_kernel_count(int variant, const Split& sp)
 
 const char* iter_kernel_name(int variant, const Split& sp, int j)
 {
+    if (variant == kGV) return j == 0 ? "k_gv_update" : "k_gv_spmv";
     if (sp.textbook && variant == kHS) return textbook_kernel_name(sp.textbook_pre, j);
     if (sp.fused) {
         if (variant == kHS) return j == 0 ? "k_hs_xr" : "k_hs_fused";
-        return (variant == kPR || variant == kM) ? "k_pr_fused" : "k_pipe_fused";
+        return (variant == kPipePR || variant == kPipeM) ? "k_pipe_fused" : "k_pr_fused";
     }
     if (variant == kHS && stage2_of(sp, kHS)) {
         static const char* n5[] = {"k_hs_finish_mu", "k_hs_xr", "k_hs_finish_nu", "k_hs_p", "k_hs_spmv"};
@@ -735,6 +840,7 @@ const char* iter_kernel_name(int variant, const Split& sp, int j)
     case kHS: return j == 0 ? "k_hs_xr" : (j == 1 ? "k_hs_p" : "k_hs_spmv");
     case kPR:
     case kM:
+    case kPRNoRecompute:
         if (stage2_of(sp, kPR)) return j == 0 ? "k_finish_one" : (j == 1 ? "k_pr_update" : "k_pr_spmv");
         return j == 0 ? "k_pr_update" : "k_pr_spmv";
     default:
@@ -751,7 +857,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
     const CsrView C = csr_or_empty(csr);
     const dim3 grid(sp.G), block(kBlock);
     const int nxt = 1 - cur;
-    const int meurant = variant == kM || variant == kPipeM;
+    const int form = nu_form(variant);
     hipError_t e = with_lanes(sp.lanes, [&](auto L) {
         return with_pre(pre, [&](auto P) {
             constexpr int LL = decltype(L)::value;
@@ -759,8 +865,18 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
             int* tk = B.ticket;
             const bool s2 = stage2_of(sp, variant);
             switch (variant) {
+            case kGV:
+                if (j == 0) {
+                    launch(k_gv_update<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.PS, v);
+                } else {
+                    launch(k_gv_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, v);
+                    cur = nxt;
+                }
+                break;
             case kPR:
-            case kM: {
+            case kM:
+            case kPRNoRecompute: {
                 double* PN = pn_of(variant, pre, sp, B);
                 const bool nu_up = nu_in_update(variant, pre, sp);
                 // the update kernel without a reduction, forming nu when nu_up
@@ -768,12 +884,12 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                     if constexpr (PP) {
                         if (nu_up) {
                             launch(k_pr_update<PP, false, true>, grid, block, st, ev, sp, (const State*)B.S[cur],
-                                   B.S[nxt], B.hist, (const double*)B.PS, PN, meurant, v);
+                                   B.S[nxt], B.hist, (const double*)B.PS, PN, form, v);
                             return;
                         }
                     }
                     launch(k_pr_update<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, PN, meurant, v);
+                           B.hist, (const double*)B.PS, PN, form, v);
                 };
                 // the product kernel (LAST: with the reduction in its last workgroup)
                 auto product = [&](auto last) {
@@ -781,12 +897,12 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                     if constexpr (PP) {
                         if (nu_up) {
                             launch(k_pr_spmv<LL, PP, LA, false>, grid, block, st, ev, S, C, sp,
-                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, meurant, tk, v);
+                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, form, tk, v);
                             return;
                         }
                     }
                     launch(k_pr_spmv<LL, PP, LA, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, B.PS, PN, meurant, tk, v);
+                           B.S[nxt], B.hist, B.PS, PN, form, tk, v);
                 };
                 if (sp.lastwg) {
                     if (j == 0) {
@@ -797,13 +913,13 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                     }
                 } else if (s2 && j == 0) {
                     launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
-                           (const double*)B.PS, (const double*)PN, meurant);
+                           (const double*)B.PS, (const double*)PN, form);
                     cur = nxt;
                 } else if (s2 && j == 1) {
                     update();
                 } else if (j == 0) {
                     launch(k_pr_update<PP, true, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, PN, meurant, v);
+                           B.hist, (const double*)B.PS, PN, form, v);
                     cur = nxt;
                 } else {
                     product(std::false_type{});
@@ -815,25 +931,25 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 if (sp.lastwg) {
                     if (j == 0) {
                         launch(k_pipe_update<PP, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                               B.hist, B.PS, meurant, tk, v);
+                               B.hist, B.PS, form, tk, v);
                         cur = nxt;
                     } else {
                         launch(k_pipe_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                               B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
+                               B.S[nxt], B.hist, (const double*)B.PS, form, v);
                     }
                 } else if (j == 0) {
                     launch(k_pipe_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, B.PS, meurant, tk, v);
+                           B.hist, B.PS, form, tk, v);
                 } else if (s2 && j == 1) {
                     launch(k_pipe_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
+                           B.S[nxt], B.hist, (const double*)B.PS, form, v);
                 } else if (s2) {
                     launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
-                           (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), meurant);
+                           (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), form);
                     cur = nxt;
                 } else {
                     launch(k_pipe_spmv<LL, PP, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, (const double*)B.PS, meurant, v);
+                           B.S[nxt], B.hist, (const double*)B.PS, form, v);
                     cur = nxt;
                 }
                 break;

@@ -93,7 +93,7 @@ struct prcg_matrix_s {
     int32_t* dflags = nullptr;   // [0..3] setup flags, [4] reduction ticket
     State* hstate = nullptr;     // pinned, two slots
     hipEvent_t ev[2] = {nullptr, nullptr};
-    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t graph[kNumVariants] = {};
 
     SellView sell() const { return SellView{slice_ptr, slice_meta, soff, scol, sval, n, nslices}; }
     CsrView csr() const { return CsrView{row_ptr, col, val, n}; }
@@ -117,6 +117,9 @@ struct prcg_matrix_s {
         v.d = d;
         v.zr = pairs;
         v.uw = pairs + n8;
+        // GV-CG uses two of the fused structure's second copies
+        v.t = vecs + 9 * n8;
+        v.wt = vecs + 10 * n8;
         return v;
     }
     double* spare() const { return vecs + 8 * (size_t)n; }
@@ -173,9 +176,9 @@ struct prcg_batch_s {
     int32_t* status = nullptr;
     int tuned_nt[3] = {0, 0, 0};
     int tuned_grid[3] = {0, 0, 0};
-    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    double graph_tol[5] = {0, 0, 0, 0, 0};
-    int32_t graph_maxit[5] = {0, 0, 0, 0, 0};
+    hipGraphExec_t graph[kNumVariants] = {};
+    double graph_tol[kNumVariants] = {};
+    int32_t graph_maxit[kNumVariants] = {};
 
     Vecs vecs_view() const
     {
@@ -192,6 +195,8 @@ struct prcg_batch_s {
         v.d = A->d;
         v.zr = nullptr;
         v.uw = nullptr;
+        v.t = nullptr;
+        v.wt = nullptr;
         return v;
     }
     BatchView view() const
@@ -309,7 +314,7 @@ hipError_t launch_iteration(prcg_matrix A, int variant, int j, int it, int& cur,
     const Bufs B = A->bufs();
     if (A->sp.textbook && variant == kHS)
         return launch_textbook_kernel(A->precond, j, cur, A->sellp(), A->csrp(), A->sp, A->vecs_view(), B, st, ev);
-    if (A->sp.fused) {
+    if (A->sp.fused && variant != kGV) {  // GV-CG has the two-pass structure only
         const FusedVecs f = A->fused_view();
         if (variant == kHS && j == 0) {
             Vecs v = A->vecs_view();
@@ -386,7 +391,15 @@ prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double*
 
 prcg_status check_variant(int v)
 {
-    if (v < PRCG_HS || v > PRCG_PIPE_M) return fail(PRCG_EINVAL, "unknown variant");
+    if (v < PRCG_HS || v > PRCG_PR_NORECOMPUTE) return fail(PRCG_EINVAL, "unknown variant");
+    return PRCG_OK;
+}
+
+// The batched solver runs HS, PR, pipe-PR and their Meurant forms.
+prcg_status check_batch_variant(int v)
+{
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (v > PRCG_PIPE_M) return fail(PRCG_EINVAL, "the batched solver runs HS, PR, pipe-PR, M and pipe-M only");
     return PRCG_OK;
 }
 
@@ -871,7 +884,7 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
                                int32_t* iters, int32_t* status)
 {
     if (!B) return fail(PRCG_EINVAL, "null batch");
-    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (check_batch_variant(v) != PRCG_OK) return PRCG_EINVAL;
     if (!(tol >= 0.0) || maxit < 0) return fail(PRCG_EINVAL, "tol must be >= 0 and maxit >= 0");
     if (!is_device_pointer(b) || !is_device_pointer(x)) return fail(PRCG_EINVAL, "b and x must be device pointers");
     prcg_matrix A = B->A;
@@ -954,7 +967,7 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
 prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, int32_t* grid)
 {
     if (!B || !threads || !grid) return fail(PRCG_EINVAL, "null argument");
-    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (check_batch_variant(v) != PRCG_OK) return PRCG_EINVAL;
     const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
     *threads = B->tuned_nt[kind];
     *grid = B->tuned_grid[kind];

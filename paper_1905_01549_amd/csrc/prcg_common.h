@@ -14,7 +14,18 @@ constexpr int kGroupRows = kBlock;  // rows handled by one workgroup step (4 sli
 constexpr int kMaxDots = 5;
 constexpr int kMaxGrid = 1024;  // largest workgroup count of the row-parallel kernels
 
-enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4 };
+enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4, kGV = 5, kPRNoRecompute = 6 };
+constexpr int kNumVariants = 7;
+
+// How a one-reduction variant forms nu and nu' (step_one_reduction):
+// 0 PR (eq. nuk_simplified), 1 Meurant (nu' = -nu + alpha^2 gamma),
+// 2 PR without the recompute (nu_k := nu'_k, eq. nuk_norecomp).
+enum NuForm { kFormPR = 0, kFormMeurant = 1, kFormNoRecompute = 2 };
+__host__ __device__ inline int nu_form(int variant)
+{
+    if (variant == kM || variant == kPipeM) return kFormMeurant;
+    return variant == kPRNoRecompute ? kFormNoRecompute : kFormPR;
+}
 enum Status { kOK = 0, kNotConverged = 1, kBreakdown = 2 };
 
 // Scalar state of a solve, resident in device memory.  Two copies are kept
@@ -87,7 +98,7 @@ struct Split {
 
 inline bool stage2_of(const Split& sp, int variant)
 {
-    const int bit = variant == kHS ? 1 : ((variant == kPR || variant == kM) ? 2 : 4);
+    const int bit = variant == kHS ? 1 : ((variant == kPipePR || variant == kPipeM) ? 4 : 2);
     return (sp.stage2 & bit) != 0;
 }
 
@@ -122,6 +133,8 @@ struct Vecs {
     // the block vector [s, r]).
     double2* zr;
     double2* uw;
+    // GV-CG: t = A w~ and the stored w~ = M^{-1} w (the product's input)
+    double *t, *wt;
 };
 
 struct Bufs {

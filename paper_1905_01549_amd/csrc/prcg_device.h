@@ -360,12 +360,16 @@ __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v);
 // The scalar step after the reduction of iteration k of a one-reduction
 // variant (PR, M, pipe-PR, pipe-M): record ||r_k||, test convergence and
 // breakdown, then form alpha_k, nu'_{k+1} and beta_{k+1} (Alg. 2 / Alg. 3,
-// eq. nuk_simplified; Meurant: nu' = -nu + alpha^2 gamma).
-__device__ inline void step_one_reduction(State& st, const double (&t)[5], bool pre, bool meurant, double* hist,
-                                   bool writer)
+// eq. nuk_simplified; Meurant: nu' = -nu + alpha^2 gamma).  form =
+// kFormNoRecompute is the ablation of Section 2 that keeps the predicted
+// nu'_k as nu_k (eq. nuk_norecomp; nu'_0 := nu_0), so the recomputed inner
+// product serves only as ||r_k||^2 when M = I.
+__device__ inline void step_one_reduction(State& st, const double (&t)[5], bool pre, int form, double* hist,
+                                          bool writer)
 {
-    const double mu = t[0], sigma = t[1], gamma = t[2], nu = t[3];
-    const double rr = pre ? t[4] : nu;
+    const double mu = t[0], sigma = t[1], gamma = t[2];
+    const double nu = (form == kFormNoRecompute && st.k >= 0) ? st.nup : t[3];
+    const double rr = pre ? t[4] : t[3];
     const int k = st.k + 1;
     const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
     if (writer) hist[k] = rnorm / st.bnorm;
@@ -391,7 +395,8 @@ __device__ inline void step_one_reduction(State& st, const double (&t)[5], bool 
         return;
     }
     const double alpha = nu / mu;
-    const double nup = meurant ? -nu + alpha * alpha * gamma : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
+    const double nup = form == kFormMeurant ? -nu + alpha * alpha * gamma
+                                            : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
     st.alpha = alpha;
     st.nup = nup;
     if (!finite(nup) || !(nup > 0.0)) {
@@ -400,6 +405,75 @@ __device__ inline void step_one_reduction(State& st, const double (&t)[5], bool 
     } else {
         st.beta = nup / nu;
     }
+}
+
+// GV-CG (Appendix D) after the reduction of iteration k >= 1 (nu_k, eta_k
+// and, with a preconditioner, <r_k, r_k>): beta_k = nu_k / nu_{k-1},
+// mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k, then the tests and
+// alpha_k = nu_k / mu_k.
+__device__ inline void step_gv(State& st, const double (&t)[3], bool pre, double* hist, bool writer)
+{
+    const double nu = t[0], eta = t[1];
+    const double rr = pre ? t[2] : nu;
+    const int k = st.k + 1;
+    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
+    if (writer) hist[k] = rnorm / st.bnorm;
+    const double beta = nu / st.nu;
+    const double mu = eta - (beta / st.alpha) * nu;
+    st.k = k;
+    st.rr = rr;
+    st.beta = beta;
+    st.nu = nu;
+    st.mu = mu;
+    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
+        st.done = 1;
+        st.status = kOK;
+        return;
+    }
+    if (!finite(nu) || !finite(mu) || !finite(rr) || !(nu > 0.0) || !(mu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        return;
+    }
+    if (k == st.maxit) {
+        st.done = 1;
+        st.status = kNotConverged;
+        return;
+    }
+    st.alpha = nu / mu;
+}
+
+// GV-CG at k = 0 (initialize of Appendix D: nu_0, mu_0 and <r_0, r_0> in
+// the one-reduction layout t[3], t[0], t[4]): the tests, alpha_0, and
+// beta := 0 so that the first direction update leaves p_0, s_0, s~_0, u_0
+// as initialised.
+__device__ inline void step_gv_first(State& st, const double (&t)[5], bool pre, double* hist, bool writer)
+{
+    const double mu = t[0], nu = t[3];
+    const double rr = pre ? t[4] : nu;
+    const double rnorm = sqrt(rr > 0.0 ? rr : 0.0);
+    if (writer) hist[0] = rnorm / st.bnorm;
+    st.k = 0;
+    st.rr = rr;
+    st.nu = nu;
+    st.mu = mu;
+    st.beta = 0.0;
+    if (finite(rr) && rnorm <= st.tol * st.bnorm) {
+        st.done = 1;
+        st.status = kOK;
+        return;
+    }
+    if (!finite(nu) || !finite(mu) || !finite(rr) || !(nu > 0.0) || !(mu > 0.0)) {
+        st.done = 1;
+        st.status = kBreakdown;
+        return;
+    }
+    if (st.maxit == 0) {
+        st.done = 1;
+        st.status = kNotConverged;
+        return;
+    }
+    st.alpha = nu / mu;
 }
 
 // HS-CG after the reduction of nu_k (Alg. 1): record ||r_k||, test, beta_k.

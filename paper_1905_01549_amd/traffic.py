@@ -18,6 +18,9 @@ KERNEL_WORDS = {
     ("pr", True): [("k_pr_update", 6, 4, False), ("k_pr_spmv", 4, 1, True)],
     ("pipe_pr", False): [("k_pipe_update", 6, 4, False), ("k_pipe_spmv", 2, 2, True)],
     ("pipe_pr", True): [("k_pipe_update", 9, 6, False), ("k_pipe_spmv", 2, 2, True)],
+    # GV-CG: the direction updates of k-1 and the updates of k in one pass
+    ("gv", False): [("k_gv_update", 7, 6, False), ("k_gv_spmv", 1, 1, True)],
+    ("gv", True): [("k_gv_update", 10, 9, False), ("k_gv_spmv", 1, 1, True)],
 }
 # fused structure (one kernel per PR / pipe-PR iteration, two per HS):
 # neighbour recomputation reads each double-buffered vector once
@@ -44,6 +47,8 @@ for _tab in (KERNEL_WORDS_FUSED,):
     for _j in (False, True):
         _tab[("m", _j)] = _tab[("pr", _j)]
         _tab[("pipe_m", _j)] = _tab[("pipe_pr", _j)]
+KERNEL_WORDS[("pr_norecompute", False)] = KERNEL_WORDS[("pr", False)]
+KERNEL_WORDS[("pr_norecompute", True)] = KERNEL_WORDS[("pr", True)]
 KERNEL_WORDS[("m", False)] = KERNEL_WORDS[("pr", False)]
 KERNEL_WORDS[("m", True)] = KERNEL_WORDS[("pr", True)]
 KERNEL_WORDS[("pipe_m", False)] = KERNEL_WORDS[("pipe_pr", False)]
