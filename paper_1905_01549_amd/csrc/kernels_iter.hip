@@ -152,9 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, 
 {
     __shared__ double lds[kWaves * 5];
     double bb[1];
-    reduce_partials<1>(PB, sp.G, sp.Gs, bb, lds);
+    reduce_partials<1, kWholeGrid>(PB, sp.G, sp.Gs, bb, lds);
     double t[5];
-    reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
+    reduce_partials_at<5, 3, kWholeGrid>(PS, PN, sp.G, sp.Gs, t, lds);
     State st = {};
     st.bnorm = sqrt(bb[0]);
     st.tol = tol;
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __
     State st = *in;
     if (!st.done) {
         double t[5];
-        reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
+        reduce_partials_at<5, 3, kWholeGrid>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_mu(Split sp, const State* 
     State st = *in;
     if (!st.done) {
         double t[1];
-        reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials<1, kWholeGrid>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
     }
     if (threadIdx.x == 0) *out = st;
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* 
     State st = *in;
     if (!st.done) {
         double t[2];
-        reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+        reduce_partials<2, kWholeGrid>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(kBlock) void k_final_reduce(Split sp, const double*
 {
     __shared__ double lds[kWaves * 1];
     double t[1];
-    reduce_partials<1>(PB, sp.G, sp.Gs, t, lds);
+    reduce_partials<1, kWholeGrid>(PB, sp.G, sp.Gs, t, lds);
     if (threadIdx.x == 0) {
         const double bn = st->bnorm;
         st->relres_true = bn > 0.0 ? sqrt(t[0]) / bn : 0.0;

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_tb_nu(Split sp, const State* __restr
     State st = *in;
     if (!st.done) {
         double t[2];
-        reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
+        reduce_partials<2, kWholeGrid>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_tb_mu(Split sp, const State* __restr
     State st = *in;
     if (!st.done) {
         double t[1];
-        reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials<1, kWholeGrid>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
     }
     if (threadIdx.x == 0) *out = st;

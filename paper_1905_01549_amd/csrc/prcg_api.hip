@@ -85,7 +85,7 @@ struct prcg_matrix_s {
     double* vecs = nullptr;  // x r rt p s st w u spare | second copies r rt p s st w u
     int kernels_mode = 0;    // PRCG_KERNELS_*
     double2* pairs = nullptr;  // pipe-PR block vectors: (s~, r~) then (u, w)
-    int grid_opt = 1024;     // largest workgroup count
+    int grid_opt = 0;        // largest workgroup count (0: chosen by size)
     State* S = nullptr;      // two copies
     double* hist = nullptr;
     int64_t hist_cap = 0;
@@ -254,7 +254,13 @@ void invalidate_graphs(prcg_matrix A)
 }
 
 // Choose the work split: G workgroups (multiple of 8 when G >= 8, so every
-// XCD gets the same number), at most gmax_opt (PRCG_OPT_GRID, default 1024).
+// XCD gets the same number), at most gmax_opt (PRCG_OPT_GRID), or by size
+// when gmax_opt is 0 (the default): from kBigGroups 256-row groups up, two
+// groups per workgroup (at most kMaxGrid), below that at most 1024
+// workgroups.  Measured on MI355X: 4096 workgroups run the 128^3 iteration
+// 3-10% faster than 1024 (more waves in flight per SIMD), while problems of
+// 1-4k groups run best at 1024.
+constexpr int64_t kBigGroups = 8192;
 //
 // Stage-2 placement of the default two-pass structure.  The redundant form
 // costs every workgroup of the consuming kernel a read of all partials
@@ -270,7 +276,8 @@ Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
     sp.n = n;
     sp.lanes = lanes;
     sp.ngroups = (n + kGroupRows - 1) / kGroupRows;
-    int gmax = std::min(kMaxGrid, std::max(8, gmax_opt));
+    int64_t gmax = gmax_opt > 0 ? std::min(kMaxGrid, std::max(8, gmax_opt))
+                                : (sp.ngroups >= kBigGroups ? std::min<int64_t>(kMaxGrid, sp.ngroups / 2) : 1024);
     int64_t G = std::min<int64_t>(sp.ngroups, gmax);
     if (G >= 8) G -= G % 8;
     sp.G = (int)std::max<int64_t>(G, 1);
@@ -541,7 +548,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
     }
     A->kernels_mode = PRCG_KERNELS_TWO_PASS;
-    A->grid_opt = 1024;
+    A->grid_opt = 0;
     A->sp = make_split(n, lanes, A->grid_opt, A->kernels_mode);
     A->sp.textbook_pre = precond;
     A->sell_storage = A->sell();
@@ -570,7 +577,8 @@ prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value)
             return fail(PRCG_EINVAL, "unknown kernel structure");
         A->kernels_mode = value;
     } else if (option == PRCG_OPT_GRID) {
-        if (value < 8 || value > kMaxGrid) return fail(PRCG_EINVAL, "grid must be in [8, 1024]");
+        if (value != 0 && (value < 8 || value > kMaxGrid))
+            return fail(PRCG_EINVAL, "grid must be 0 (by size) or in [8, 4096]");
         A->grid_opt = value;
     } else {
         return fail(PRCG_EINVAL, "unknown option");

@@ -44,39 +44,47 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * N
 // are summed in a fixed order (G <= kMaxGrid).  Value i < N1 is read from
 // P1[i * Gs + g], value i >= N1 from P2[(i - N1) * Gs + g] (two kernels may
 // produce the partials of one reduction).  Every thread of the calling
-// workgroup receives the totals.  All loads are issued before the first
-// addition so the cost is one memory latency.
-template <int NV, int N1>
+// workgroup receives the totals.  Thread t adds the partials t, t + 256,
+// t + 512, ... in that order; they are loaded PIECE at a time, all loads of
+// a piece before its first addition.  Kernels that do nothing else use
+// PIECE = kMaxGrid / kBlock (one memory latency for any G); kernels that
+// reduce beside other work use 4, to keep their register count down.  The
+// order of additions is the same for every PIECE.
+template <int NV, int N1, int PIECE = 4>
 __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1, const double* __restrict__ P2, int G,
                                                    int Gs, double (&tot)[NV], double* lds)
 {
-    constexpr int kPer = kMaxGrid / kBlock;
-    double buf[NV][kPer];
+    constexpr int kPiece = PIECE;
+    const double* P[NV];
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int g = threadIdx.x + j * kBlock;
+    for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tot[i] = 0.0;
+    for (int g0 = 0; g0 < G; g0 += kPiece * kBlock) {
+        double buf[NV][kPiece];
+#pragma unroll
+        for (int j = 0; j < kPiece; ++j) {
+            const int g = g0 + (int)threadIdx.x + j * kBlock;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) buf[i][j] = g < G ? P[i][g] : 0.0;
+        }
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const double* P = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
-            buf[i][j] = g < G ? P[g] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kPiece; ++j) tot[i] += buf[i][j];
         }
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double t = buf[i][0];
-#pragma unroll
-        for (int j = 1; j < kPer; ++j) t += buf[i][j];
-        tot[i] = t;
     }
     block_sum<NV>(tot, lds);
 }
 
-template <int NV>
+template <int NV, int PIECE = 4>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
                                                 double* lds)
 {
-    reduce_partials_at<NV, NV>(P, nullptr, G, Gs, tot, lds);
+    reduce_partials_at<NV, NV, PIECE>(P, nullptr, G, Gs, tot, lds);
 }
+
+constexpr int kWholeGrid = kMaxGrid / kBlock;  // PIECE of the one-workgroup stage-2 kernels
 
 // Stage 1: per-thread sums -> one partial per workgroup and value (value
 // i < N1 to P1, the others to P2, with the layout of reduce_partials_at).
