@@ -61,6 +61,9 @@ typedef struct prcg_batch_s* prcg_batch;
  *   PRCG_PR_NORECOMPUTE  the ablation of Section 2: PR-CG that keeps the
  *                predicted nu'_k as nu_k (eq. nuk_norecomp) instead of
  *                recomputing it; it loses accuracy and is for study only.
+ *   PRCG_PIPE_PR_NOWRECOMPUTE  the second ablation of Section 2: pipe-PR-CG
+ *                that keeps w'_k (and w~'_k) as w_k instead of recomputing
+ *                w_k = A r~_k; the product computes u = A s~ only.
  * The batched solver runs the first five. */
 typedef enum {
     PRCG_HS = 0,
@@ -69,7 +72,8 @@ typedef enum {
     PRCG_M = 3,
     PRCG_PIPE_M = 4,
     PRCG_GV = 5,
-    PRCG_PR_NORECOMPUTE = 6
+    PRCG_PR_NORECOMPUTE = 6,
+    PRCG_PIPE_PR_NOWRECOMPUTE = 7
 } prcg_variant;
 
 /* Preconditioners: none (M = I) or Jacobi (M^{-1} = diag(A)^{-1}). */
@@ -107,7 +111,8 @@ typedef struct {
     double aligned_slices_frac; /* SELL-64: share of slots in offset-aligned slices,
                                    which store one column offset per slot and slice
                                    instead of a column index per entry              */
-    int32_t kernels;          /* kernel structure in use (PRCG_KERNELS_*)           */
+    int32_t kernels;          /* kernel structure in use (PRCG_KERNELS_*; AUTO is
+                                 reported as the structure it chose)              */
     int32_t stage2;           /* two-pass stage-2 reductions in one-workgroup
                                  kernels of their own: bit 0 HS-CG, bit 1 PR-CG
                                  and M-CG                                         */
@@ -115,12 +120,16 @@ typedef struct {
 
 /* Options (prcg_set_option).
  *   PRCG_OPT_KERNELS  kernel structure of an iteration:
+ *     PRCG_KERNELS_AUTO (default): FUSED when A is stored as SELL-64 and the
+ *       row-parallel kernels have fewer than 64 workgroups (16k rows: the
+ *       iteration is latency-bound and one kernel per iteration wins),
+ *       TWO_PASS otherwise.  prcg_get_props reports the structure chosen.
  *     PRCG_KERNELS_FUSED: PR-CG and pipe-PR-CG run one kernel per
  *       iteration, HS-CG two; the sparse product recomputes the new
  *       direction at neighbouring rows from double-buffered vectors, with
  *       the owner's exact operations.  Needs the SELL-64 layout; matrices
  *       stored as vector CSR use the two-pass structure.
- *     PRCG_KERNELS_TWO_PASS (default): an update kernel and a product kernel
+ *     PRCG_KERNELS_TWO_PASS: an update kernel and a product kernel
  *       per reduction (PR: 2, pipe-PR: 2, HS: 3 kernels per iteration), with
  *       stage 2 of each reduction (the sum of the per-workgroup partials)
  *       placed by size: HS-CG and PR-CG as STAGE2 from 64 workgroups up,
@@ -154,7 +163,8 @@ typedef enum {
     PRCG_KERNELS_TWO_PASS_STAGE2 = 2,
     PRCG_KERNELS_TEXTBOOK = 3,
     PRCG_KERNELS_TWO_PASS_LAST = 4,
-    PRCG_KERNELS_TWO_PASS_REDUNDANT = 5
+    PRCG_KERNELS_TWO_PASS_REDUNDANT = 5,
+    PRCG_KERNELS_AUTO = 6
 } prcg_kernels;
 
 /*

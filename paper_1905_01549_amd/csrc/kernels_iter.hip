@@ -113,9 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split 
 }
 
 // pipe-PR-CG and GV-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0; the
-// block vectors (s~0, r~0) and (u0, w0) are filled as well.  GV also keeps
-// t := u0 and w~0 = M^{-1} w0 = s~0, so that its first direction update
-// (beta = 0) reproduces p0, s0, s~0 and u0.
+// block vectors (s~0, r~0) and (u0, w0) are filled as well.  gv = 1 (GV-CG)
+// also keeps t := u0 and w~0 = M^{-1} w0 = s~0, so that its first direction
+// update (beta = 0) reproduces p0, s0, s~0 and u0; gv = 2 (pipe-PR-CG
+// without the recompute of w) keeps w~0 only.
 template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split sp, Vecs v, int gv)
 {
@@ -130,10 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
             v.w[i] = si;
             v.uw[i] = make_double2(ui, si);
             v.zr[i] = make_double2(st[i], rt[i]);
-            if (gv) {
-                v.t[i] = ui;
-                if (PRE) v.wt[i] = st[i];
-            }
+            if (gv & 1) v.t[i] = ui;
+            if (gv && PRE) v.wt[i] = st[i];  // w~0 = M^{-1} w0 = s~0
         });
     }
 }
@@ -377,7 +376,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
 // stored separately; w is recomputed by the next kernel).
 // LAST: the last workgroup also runs stage 2 and the scalar step of
 // iteration k (`in` -> `out`); the product kernel then only multiplies.
-template <bool PRE, bool LAST>
+// NOW: the ablation of Section 2 that never recomputes w: w'_k (and, with
+// a preconditioner, w~'_k = w~_{k-1} - alpha u~) is stored and is the next
+// iteration's w (w~), instead of A r~ (M^{-1} A r~).
+template <bool PRE, bool LAST, bool NOW = false>
 __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* __restrict__ in,
                                                         State* __restrict__ out, double* __restrict__ hist,
                                                         double* __restrict__ PS, int form, int* ticket, Vecs v)
@@ -398,7 +400,8 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
     double* __restrict__ p = v.p;
     double* __restrict__ s = v.s;
     double2* __restrict__ zr = v.zr;
-    const double2* __restrict__ uw = v.uw;
+    double2* __restrict__ uw = v.uw;
+    double* __restrict__ wt = v.wt;
     const double* __restrict__ d = v.d;
     for (int64_t i = i0; i < i1; i += kBlock) {
         const double pi = p[i], xi = x[i];
@@ -407,13 +410,18 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
         const double si = PRE ? s[i] : zri.x;
         const double ri = PRE ? r[i] : zri.y;
         const double rn = fma(-alpha, si, ri);                 // r_k
-        const double snew = fma(beta, si, fma(-alpha, ui, wi));  // s_k = w'_k + beta s_{k-1}
+        const double wn = fma(-alpha, ui, wi);                 // w'_k
+        const double snew = fma(beta, si, wn);                 // s_k = w'_k + beta s_{k-1}
         double rti = rn, sti = snew;
         if (PRE) {
             const double di = d[i];
             rti = fma(-alpha, zri.x, zri.y);                   // r~_k = r~_{k-1} - alpha s~_{k-1}
-            sti = fma(beta, zri.x, fma(-alpha, di * ui, di * wi));  // s~_k = w~'_k + beta s~_{k-1}
+            // w~'_k = w~_{k-1} - alpha u~ (w~ = M^{-1} w when w is recomputed)
+            const double wtn = fma(-alpha, di * ui, NOW ? wt[i] : di * wi);
+            sti = fma(beta, zri.x, wtn);                       // s~_k = w~'_k + beta s~_{k-1}
+            if (NOW) wt[i] = wtn;
         }
+        if (NOW) uw[i].y = wn;
         const double pnew = fma(beta, pi, rti);                // p_k
         x[i] = fma(alpha, pi, xi);
         p[i] = pnew;
@@ -446,8 +454,9 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
 // reduction off the kernel's tail: done after the product, it lengthened
 // the kernel by 9-12 us on MI355X.
 // REDUCE = false: the update kernel or a one-workgroup kernel advances the
-// state instead.
-template <int LANES, bool PRE, bool REDUCE>
+// state instead.  NOW (no recompute of w): only u = A s~ is stored; w keeps
+// the update kernel's w'.
+template <int LANES, bool PRE, bool REDUCE, bool NOW = false>
 __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, int form, Vecs v)
@@ -469,7 +478,10 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
     double2* __restrict__ uw = v.uw;
     for (int64_t g = g0; g < g1; ++g) {
         rows_of_group_pair<LANES>(S, C, g, v.zr, [&](int64_t i, double ui, double wi) {
-            uw[i] = make_double2(ui, wi);
+            if (NOW)
+                uw[i].x = ui;
+            else
+                uw[i] = make_double2(ui, wi);
         });
     }
 }
@@ -772,7 +784,7 @@ CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullpt
 bool nu_in_update(int variant, int pre, const Split& sp)
 {
     const bool pr = variant == kPR || variant == kM || variant == kPRNoRecompute;
-    return pre && pr && !sp.fused && (stage2_of(sp, kPR) || sp.lastwg);
+    return pre && pr && !uses_fused(variant, sp) && (stage2_of(sp, kPR) || sp.lastwg);
 }
 
 double* pn_of(int variant, int pre, const Split& sp, const Bufs& B)
@@ -788,9 +800,9 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
 {
     const SellView S = sell_or_empty(sell);
     const CsrView C = csr_or_empty(csr);
-    const bool pipe = variant == kPipePR || variant == kPipeM;
+    const bool pipe = is_pipe(variant);
     const int store_rt = variant != kHS;  // r~ evolves by recurrence in PR and pipe-PR
-    const int gv = variant == kGV;
+    const int gv = variant == kGV ? 1 : (variant == kPipeNoWRecompute ? 2 : 0);
     const int store_st = pipe || gv;      // s~ evolves by recurrence in pipe-PR and GV
     hipError_t e = with_lanes(sp.lanes, [&](auto L) {
         return with_pre(pre, [&](auto P) {
@@ -806,7 +818,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     });
     if (e != hipSuccess) return e;
     return with_pre(pre, [&](auto P) {
-        const bool pipe2 = (variant == kPipePR || variant == kPipeM) && !sp.fused;
+        const bool pipe2 = is_pipe(variant) && !uses_fused(variant, sp);
         const int step0 = variant == kHS ? (sp.lastwg ? 2 : 1) : (pipe2 || sp.lastwg ? 1 : 0);
         hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
                            B.PB, B.PS, pn_of(variant, pre, sp, B), B.S[0], B.hist, tol, (int)maxit);
@@ -818,7 +830,7 @@ int iter_kernel_count(int variant, const Split& sp)
 {
     if (variant == kGV) return 2;  // one structure for GV-CG
     if (sp.textbook && variant == kHS) return textbook_kernel_count(sp.textbook_pre);
-    if (sp.fused) return variant == kHS ? 2 : 1;
+    if (uses_fused(variant, sp)) return variant == kHS ? 2 : 1;
     if (variant == kHS) return stage2_of(sp, kHS) ? 5 : 3;
     if (variant != kHS && stage2_of(sp, variant)) return 3;
     return 2;
@@ -828,7 +840,7 @@ const char* iter_kernel_name(int variant, const Split& sp, int j)
 {
     if (variant == kGV) return j == 0 ? "k_gv_update" : "k_gv_spmv";
     if (sp.textbook && variant == kHS) return textbook_kernel_name(sp.textbook_pre, j);
-    if (sp.fused) {
+    if (uses_fused(variant, sp)) {
         if (variant == kHS) return j == 0 ? "k_hs_xr" : "k_hs_fused";
         return (variant == kPipePR || variant == kPipeM) ? "k_pipe_fused" : "k_pr_fused";
     }
@@ -928,31 +940,40 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
             }
             case kPipePR:
             case kPipeM:
-                if (sp.lastwg) {
-                    if (j == 0) {
-                        launch(k_pipe_update<PP, true>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                               B.hist, B.PS, form, tk, v);
+            case kPipeNoWRecompute: {
+                auto pipe = [&](auto now) {
+                    constexpr bool NW = decltype(now)::value;
+                    if (sp.lastwg) {
+                        if (j == 0) {
+                            launch(k_pipe_update<PP, true, NW>, grid, block, st, ev, sp, (const State*)B.S[cur],
+                                   B.S[nxt], B.hist, B.PS, form, tk, v);
+                            cur = nxt;
+                        } else {
+                            launch(k_pipe_spmv<LL, PP, false, NW>, grid, block, st, ev, S, C, sp,
+                                   (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)B.PS, form, v);
+                        }
+                    } else if (j == 0) {
+                        launch(k_pipe_update<PP, false, NW>, grid, block, st, ev, sp, (const State*)B.S[cur],
+                               B.S[nxt], B.hist, B.PS, form, tk, v);
+                    } else if (s2 && j == 1) {
+                        launch(k_pipe_spmv<LL, PP, false, NW>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                               B.S[nxt], B.hist, (const double*)B.PS, form, v);
+                    } else if (s2) {
+                        launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                               B.hist, (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), form);
                         cur = nxt;
                     } else {
-                        launch(k_pipe_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
+                        launch(k_pipe_spmv<LL, PP, true, NW>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
                                B.S[nxt], B.hist, (const double*)B.PS, form, v);
+                        cur = nxt;
                     }
-                } else if (j == 0) {
-                    launch(k_pipe_update<PP, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, B.PS, form, tk, v);
-                } else if (s2 && j == 1) {
-                    launch(k_pipe_spmv<LL, PP, false>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, (const double*)B.PS, form, v);
-                } else if (s2) {
-                    launch(k_finish_one<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
-                           (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), form);
-                    cur = nxt;
-                } else {
-                    launch(k_pipe_spmv<LL, PP, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, (const double*)B.PS, form, v);
-                    cur = nxt;
-                }
+                };
+                if (variant == kPipeNoWRecompute)
+                    pipe(std::true_type{});
+                else
+                    pipe(std::false_type{});
                 break;
+            }
             default:  // HS
                 if (sp.lastwg) {
                     if (j == 0) {

@@ -282,10 +282,14 @@ Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
     if (G >= 8) G -= G % 8;
     sp.G = (int)std::max<int64_t>(G, 1);
     sp.Gs = (sp.G + 63) / 64 * 64;
-    sp.fused = (kernels_mode == PRCG_KERNELS_FUSED && lanes == 1) ? 1 : 0;
+    // AUTO: the fused structure for problems of fewer than kStage2MinGrid
+    // workgroups (latency-bound; one kernel per iteration wins), two-pass above
+    const bool small = sp.G < kStage2MinGrid;
+    sp.fused = lanes == 1 && (kernels_mode == PRCG_KERNELS_FUSED || (kernels_mode == PRCG_KERNELS_AUTO && small)) ? 1 : 0;
     if (kernels_mode == PRCG_KERNELS_TWO_PASS_STAGE2) {
         sp.stage2 = 7;
-    } else if (kernels_mode == PRCG_KERNELS_TWO_PASS || kernels_mode == PRCG_KERNELS_TEXTBOOK) {
+    } else if (kernels_mode == PRCG_KERNELS_TWO_PASS || kernels_mode == PRCG_KERNELS_TEXTBOOK ||
+               kernels_mode == PRCG_KERNELS_AUTO) {
         sp.stage2 = sp.G >= kStage2MinGrid ? 3 : 0;
     }
     sp.lastwg = kernels_mode == PRCG_KERNELS_TWO_PASS_LAST ? 1 : 0;
@@ -321,7 +325,7 @@ hipError_t launch_iteration(prcg_matrix A, int variant, int j, int it, int& cur,
     const Bufs B = A->bufs();
     if (A->sp.textbook && variant == kHS)
         return launch_textbook_kernel(A->precond, j, cur, A->sellp(), A->csrp(), A->sp, A->vecs_view(), B, st, ev);
-    if (A->sp.fused && variant != kGV) {  // GV-CG has the two-pass structure only
+    if (uses_fused(variant, A->sp)) {
         const FusedVecs f = A->fused_view();
         if (variant == kHS && j == 0) {
             Vecs v = A->vecs_view();
@@ -398,7 +402,7 @@ prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double*
 
 prcg_status check_variant(int v)
 {
-    if (v < PRCG_HS || v > PRCG_PR_NORECOMPUTE) return fail(PRCG_EINVAL, "unknown variant");
+    if (v < PRCG_HS || v > PRCG_PIPE_PR_NOWRECOMPUTE) return fail(PRCG_EINVAL, "unknown variant");
     return PRCG_OK;
 }
 
@@ -547,7 +551,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
                               A->slice_meta, A->soff, A->scol, A->sval, 1, A->stream));
         HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
     }
-    A->kernels_mode = PRCG_KERNELS_TWO_PASS;
+    A->kernels_mode = PRCG_KERNELS_AUTO;
     A->grid_opt = 0;
     A->sp = make_split(n, lanes, A->grid_opt, A->kernels_mode);
     A->sp.textbook_pre = precond;
@@ -573,7 +577,7 @@ prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value)
 {
     if (!A) return fail(PRCG_EINVAL, "null handle");
     if (option == PRCG_OPT_KERNELS) {
-        if (value < PRCG_KERNELS_FUSED || value > PRCG_KERNELS_TWO_PASS_REDUNDANT)
+        if (value < PRCG_KERNELS_FUSED || value > PRCG_KERNELS_AUTO)
             return fail(PRCG_EINVAL, "unknown kernel structure");
         A->kernels_mode = value;
     } else if (option == PRCG_OPT_GRID) {
@@ -660,7 +664,8 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
     props->lanes_per_row = A->sp.lanes;
     props->stored_entries = A->sp.lanes == 1 ? A->stored : A->nnz;
     props->grid = A->sp.G;
-    props->kernels = A->sp.fused ? PRCG_KERNELS_FUSED : A->kernels_mode;
+    props->kernels = A->sp.fused ? PRCG_KERNELS_FUSED
+                                 : (A->kernels_mode == PRCG_KERNELS_AUTO ? PRCG_KERNELS_TWO_PASS : A->kernels_mode);
     props->stage2 = A->sp.stage2;
     props->block = kBlock;
     // bytes one product reads: values, the column indices of packed slices,

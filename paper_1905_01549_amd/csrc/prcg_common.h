@@ -14,8 +14,13 @@ constexpr int kGroupRows = kBlock;  // rows handled by one workgroup step (4 sli
 constexpr int kMaxDots = 5;
 constexpr int kMaxGrid = 4096;  // largest workgroup count of the row-parallel kernels
 
-enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4, kGV = 5, kPRNoRecompute = 6 };
-constexpr int kNumVariants = 7;
+enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4, kGV = 5, kPRNoRecompute = 6, kPipeNoWRecompute = 7 };
+constexpr int kNumVariants = 8;
+
+__host__ __device__ inline bool is_pipe(int variant)
+{
+    return variant == kPipePR || variant == kPipeM || variant == kPipeNoWRecompute;
+}
 
 // How a one-reduction variant forms nu and nu' (step_one_reduction):
 // 0 PR (eq. nuk_simplified), 1 Meurant (nu' = -nu + alpha^2 gamma),
@@ -98,8 +103,15 @@ struct Split {
 
 inline bool stage2_of(const Split& sp, int variant)
 {
-    const int bit = variant == kHS ? 1 : ((variant == kPipePR || variant == kPipeM) ? 4 : 2);
+    const int bit = variant == kHS ? 1 : (is_pipe(variant) ? 4 : 2);
     return (sp.stage2 & bit) != 0;
+}
+
+// The fused structure covers HS, PR, pipe-PR and their forms; GV-CG and the
+// no-w-recompute ablation always run two-pass.
+inline bool uses_fused(int variant, const Split& sp)
+{
+    return sp.fused && variant != kGV && variant != kPipeNoWRecompute;
 }
 
 // ---- setup kernels (kernels_setup.hip) ----
@@ -133,7 +145,8 @@ struct Vecs {
     // the block vector [s, r]).
     double2* zr;
     double2* uw;
-    // GV-CG: t = A w~ and the stored w~ = M^{-1} w (the product's input)
+    // GV-CG: t = A w~ and the stored w~ = M^{-1} w (the product's input);
+    // pipe-PR-CG without the recompute of w keeps its recurrence w~' in wt
     double *t, *wt;
 };
 

@@ -19,14 +19,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprcg.so")
 
-PRCG_HS, PRCG_PR, PRCG_PIPE_PR, PRCG_M, PRCG_PIPE_M, PRCG_GV, PRCG_PR_NORECOMPUTE = 0, 1, 2, 3, 4, 5, 6
+PRCG_HS, PRCG_PR, PRCG_PIPE_PR, PRCG_M, PRCG_PIPE_M, PRCG_GV = 0, 1, 2, 3, 4, 5
+PRCG_PR_NORECOMPUTE, PRCG_PIPE_PR_NOWRECOMPUTE = 6, 7
 VARIANTS = {"hs": PRCG_HS, "pr": PRCG_PR, "pipe_pr": PRCG_PIPE_PR, "m": PRCG_M, "pipe_m": PRCG_PIPE_M,
-            "gv": PRCG_GV, "pr_norecompute": PRCG_PR_NORECOMPUTE}
+            "gv": PRCG_GV, "pr_norecompute": PRCG_PR_NORECOMPUTE, "pipe_pr_nowrecompute": PRCG_PIPE_PR_NOWRECOMPUTE}
 PRECONDS = {"none": 0, "jacobi": 1}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem", -3: "edevice"}
 
 KERNELS = {"fused": 0, "two_pass": 1, "two_pass_stage2": 2, "textbook": 3, "two_pass_last": 4,
-           "two_pass_redundant": 5}
+           "two_pass_redundant": 5, "auto": 6}
 OPT_KERNELS, OPT_GRID = 0, 1
 
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
@@ -249,7 +250,8 @@ class Matrix:
         return prcg_get_props(self.handle)
 
     def set_kernels(self, mode: str):
-        """Kernel structure: "two_pass" (default; stage-2 placement by size),
+        """Kernel structure: "auto" (default: "fused" below 64 workgroups,
+        else "two_pass"), "two_pass" (stage-2 placement by size),
         "two_pass_redundant", "two_pass_stage2", "two_pass_last", "fused" or
         "textbook" (HS-CG one kernel per algorithm line)."""
         prcg_set_option(self.handle, OPT_KERNELS, KERNELS[mode])

@@ -47,6 +47,10 @@ for _tab in (KERNEL_WORDS_FUSED,):
     for _j in (False, True):
         _tab[("m", _j)] = _tab[("pr", _j)]
         _tab[("pipe_m", _j)] = _tab[("pipe_pr", _j)]
+# pipe-PR-CG without the recompute of w: the update also writes w' (and
+# reads/writes w~' with Jacobi); the product reads only s~ of the pair
+KERNEL_WORDS[("pipe_pr_nowrecompute", False)] = [("k_pipe_update", 6, 5, False), ("k_pipe_spmv", 2, 1, True)]
+KERNEL_WORDS[("pipe_pr_nowrecompute", True)] = [("k_pipe_update", 10, 8, False), ("k_pipe_spmv", 2, 1, True)]
 KERNEL_WORDS[("pr_norecompute", False)] = KERNEL_WORDS[("pr", False)]
 KERNEL_WORDS[("pr_norecompute", True)] = KERNEL_WORDS[("pr", True)]
 KERNEL_WORDS[("m", False)] = KERNEL_WORDS[("pr", False)]

@@ -43,7 +43,7 @@ def hist_close(h, ho, rtol=1e-8):
     return bool(np.all(np.abs(h - ho) <= rtol * ho + EPS))
 
 
-STRUCTURES = ["fused", "two_pass", "two_pass_redundant", "two_pass_stage2", "two_pass_last", "textbook"]
+STRUCTURES = ["auto", "fused", "two_pass", "two_pass_redundant", "two_pass_stage2", "two_pass_last", "textbook"]
 
 
 def gpu_matrix(prcg, A, precond="none", kernels="fused"):
@@ -373,7 +373,7 @@ def test_set_values_changes_the_operator(prcg, torch_cuda):
 
 # ---------------------------------------------------------------- full-size workload
 
-@pytest.mark.parametrize("kernels", ["fused", "two_pass", "two_pass_last"])
+@pytest.mark.parametrize("kernels", ["auto", "fused", "two_pass_last"])
 def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
     """The 128^3 Jacobi workload at full size, in the launch configurations the
     benchmark times: the first 200 residual norms and x_200 against the oracle."""
@@ -386,6 +386,17 @@ def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
         assert hist_close(info.history, ref["history"])
         xg = x.cpu().numpy()
         assert np.linalg.norm(xg - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+
+
+def test_auto_structure_by_size(prcg, torch_cuda):
+    """The default structure is fused on small SELL-64 problems and two-pass
+    (with stage 2 in its own kernel) on large ones; props report the choice."""
+    small = gpu_matrix(prcg, P.poisson2d(64), "none", "auto")
+    assert small.props.kernels == prcg.KERNELS["fused"] and small.props.grid < 64
+    big = gpu_matrix(prcg, P.poisson3d(40), "jacobi", "auto")
+    assert big.props.kernels == prcg.KERNELS["two_pass"] and big.props.stage2 == 3
+    csr = prcg.Matrix(*(lambda A: (A.row_ptr, A.col_idx, A.values))(P.arrowhead(5000, 2)), "none")
+    assert csr.props.kernels == prcg.KERNELS["two_pass"]  # vector CSR: no fused structure
 
 
 def test_time_kernels_capacity_is_checked(prcg, torch_cuda):
