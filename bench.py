@@ -73,6 +73,17 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def variants_of(kern: str):
     """Variants timed under a kernel structure (GV-CG has one structure)."""
     if kern == "textbook":
@@ -354,6 +365,7 @@ def main():
                 "traffic": tb}
 
     cpu = None
+    cpu_host = None
     if not args.no_cpu_baseline:
         # the oracle as it stands: complete PR-CG solves of the same workload
         # to 1e-10, repeated until about 10 s of CPU time have been spent
@@ -365,10 +377,21 @@ def main():
             done_iters += ref["iters"]
             solves += 1
         dt = time.perf_counter() - t
-        cpu = {"value": done_iters / dt, "unit": "CG iterations/s", "cores": oracle.max_threads(),
+        threads = oracle.max_threads()
+        cpu = {"value": done_iters / dt, "unit": "CG iterations/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{solves} complete {args.variant} solves to 1e-10 ({done_iters} iterations, {dt:.1f} s) "
                          f"of the same {workload} workload by the FP64 C oracle"}
+        # the same oracle on one core: 40 iterations (a bounded sample of the solve)
+        oracle.set_threads(1)
+        t = time.perf_counter()
+        one = oracle.solve(A.row_ptr, A.col_idx, A.values, pr.b, args.variant, "jacobi", 0.0, 40)
+        dt1 = time.perf_counter() - t
+        oracle.set_threads(threads)
+        cpu_host = {"model": cpu_model(), "nproc": os.cpu_count(), "threads": threads,
+                    "iters_per_s_all_threads": done_iters / dt,
+                    "iters_per_s_one_thread": one["iters"] / dt1,
+                    "one_thread_sample": f"{one['iters']} iterations from x0 = 0 ({dt1:.1f} s, incl. setup)"}
 
     batched = None if args.no_batched else batched_section(torch, prcg, problems, traffic)
     adjoint = None if args.no_adjoint else adjoint_section(torch, prcg, problems)
@@ -395,6 +418,7 @@ def main():
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_host": cpu_host,
         "batched": batched,
         "adjoint": adjoint,
     }

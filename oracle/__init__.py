@@ -78,6 +78,8 @@ def load_library(path: str):
     lib.orc_outer_csr.argtypes = [ctypes.c_int64, _I32, _I32, _DBL, _DBL, _DBL]
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     return lib
 
 
@@ -140,6 +142,11 @@ def outer_csr(row_ptr, col_idx, lam, x) -> np.ndarray:
 
 def max_threads() -> int:
     return int(_lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP thread count of later calls (results do not depend on it)."""
+    _lib().orc_set_threads(int(n))
 
 
 _DIAG_KEYS = ("nu", "nup", "rr", "mu", "alpha", "beta", "true_res", "err_a", "orth")

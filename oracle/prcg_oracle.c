@@ -551,3 +551,15 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the following calls (timing only: every result is the same
+ * for any count, since the inner products sum fixed chunks in index order). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -317,6 +317,18 @@ def test_oracle_is_independent_of_thread_count():
     assert outs[0] == outs[1]
 
 
+def test_set_threads_changes_nothing_but_time():
+    pr = P.config1()
+    outs = []
+    for th in (1, 4):
+        oracle.set_threads(th)
+        assert oracle.max_threads() == th
+        outs.append(run(pr.A, pr.b, "pr", "jacobi", 0.0, 60))
+    oracle.set_threads(os.cpu_count() or 1)
+    assert np.array_equal(outs[0]["x"], outs[1]["x"])
+    assert np.array_equal(outs[0]["history"], outs[1]["history"])
+
+
 def test_jacobi_setup():
     A = P.random_spd(30, 3.0, 2)
     assert np.allclose(oracle.jacobi(A.row_ptr, A.col_idx, A.values), 1.0 / A.diagonal(), rtol=0, atol=0)
