@@ -33,6 +33,7 @@ VARIANTS = {
     "gv": 5,
     "pr_norecompute": 6,
     "pipe_pr_nowrecompute": 7,
+    "cg": 8,
 }
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem"}
 

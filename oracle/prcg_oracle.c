@@ -14,6 +14,7 @@
  *   - pipe-PR-CG (Alg. 3, recurrences for w, w~, s~; recompute w = A r~),
  *   - M-CG and pipe-PR-M-CG (Appendix D; nu' = -nu + alpha^2 gamma),
  *   - GV-CG      (Appendix D, Ghysels-Vanroose pipelined CG),
+ *   - CG-CG      (Appendix D, Chronopoulos-Gear CG),
  *   - two ablations from Section 2: PR-CG without the recompute of nu
  *     (eq. nuk_norecomp) and pipe-PR-CG without the recompute of w.
  *
@@ -65,7 +66,8 @@ enum {
     ORC_PIPE_M = 4,
     ORC_GV = 5,
     ORC_PR_NO_RECOMPUTE = 6,      /* nu'_k from nu'_{k-1}; nu never recomputed */
-    ORC_PIPE_PR_NO_W_RECOMPUTE = 7 /* w kept as the predicted w'_k            */
+    ORC_PIPE_PR_NO_W_RECOMPUTE = 7, /* w kept as the predicted w'_k           */
+    ORC_CG = 8                      /* CG-CG (Chronopoulos-Gear, Appendix D)   */
 };
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
@@ -341,6 +343,7 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
     const int is_pr = variant == ORC_PR || variant == ORC_M || variant == ORC_PR_NO_RECOMPUTE;
     const int is_pipe = variant == ORC_PIPE_PR || variant == ORC_PIPE_M || variant == ORC_PIPE_PR_NO_W_RECOMPUTE;
     const int is_gv = variant == ORC_GV;
+    const int is_cg = variant == ORC_CG;
     const int meurant = variant == ORC_M || variant == ORC_PIPE_M;
 
     /* initialize (Appendix D) */
@@ -396,8 +399,8 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
             }
         }
         ++k;
-        if (dg && dg->nup && !is_gv) dg->nup[k] = nup;
-        if (dg && dg->beta && !is_gv) dg->beta[k] = beta;
+        if (dg && dg->nup && !is_gv && !is_cg) dg->nup[k] = nup;
+        if (dg && dg->beta && !is_gv && !is_cg) dg->beta[k] = beta;
         if (dg && dg->orth) memcpy(C->W.pold, p, (size_t)n * sizeof(double));
 
         if (is_pr) {
@@ -439,6 +442,21 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
             gamma = orc_dot(n, st, s);                         /* gamma_k = <s~_k, s_k>        */
             nu = orc_dot(n, rt, r);                            /* nu_k    = <r~_k, r_k>        */
             rr = pre ? orc_dot(n, r, r) : nu;
+        } else if (is_cg) {
+            /* CG-CG (Appendix D), iteration k */
+            orc_axpy(n, alpha, p, x);                          /* x_k = x_{k-1} + alpha p      */
+            orc_axpy(n, -alpha, s, r);                         /* r_k = r_{k-1} - alpha s      */
+            if (pre) orc_prec(n, dinv, r, rt);                 /* r~_k = M^-1 r_k              */
+            orc_spmv(&C->A, rt, w);                            /* w_k = A r~_k                 */
+            double nu_new = orc_dot(n, rt, r);                 /* nu_k  = <r~_k, r_k>          */
+            eta = orc_dot(n, rt, w);                           /* eta_k = <r~_k, w_k>          */
+            beta = nu_new / nu;                                /* beta_k = nu_k / nu_{k-1}     */
+            if (dg && dg->beta) dg->beta[k] = beta;
+            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta p_{k-1}    */
+            orc_xpay(n, w, beta, s);                           /* s_k = w_k + beta s_{k-1}     */
+            mu = eta - (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */
+            nu = nu_new;
+            rr = pre ? orc_dot(n, r, r) : nu;
         } else {
             /* GV-CG (Appendix D), iteration k */
             orc_axpy(n, alpha, p, x);                          /* x_k = x_{k-1} + alpha p      */
@@ -477,7 +495,7 @@ int orc_solve(int variant, int64_t n, const int32_t* row_ptr, const int32_t* col
 {
     if (n < 1 || !row_ptr || !col || !val || !b || !x || !iters_out || !(tol >= 0.0) || maxit < 0)
         return ORC_EINVAL;
-    if (variant < ORC_HS || variant > ORC_PIPE_PR_NO_W_RECOMPUTE) return ORC_EINVAL;
+    if (variant < ORC_HS || variant > ORC_CG) return ORC_EINVAL;
     *iters_out = 0;
 
     double bnorm = sqrt(orc_dot(n, b, b));
