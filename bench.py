@@ -85,10 +85,10 @@ def cpu_model() -> str:
 
 
 def variants_of(kern: str):
-    """Variants timed under a kernel structure (GV-CG has one structure)."""
+    """Variants timed under a kernel structure (GV-CG and CG-CG have one structure)."""
     if kern == "textbook":
         return ("hs",)
-    return ("hs", "pr", "pipe_pr", "gv") if kern in ("auto", "two_pass") else ("hs", "pr", "pipe_pr")
+    return ("hs", "pr", "pipe_pr", "gv", "cg") if kern in ("auto", "two_pass") else ("hs", "pr", "pipe_pr")
 
 
 def nu_split(M) -> bool:

@@ -64,6 +64,9 @@ typedef struct prcg_batch_s* prcg_batch;
  *   PRCG_PIPE_PR_NOWRECOMPUTE  the second ablation of Section 2: pipe-PR-CG
  *                that keeps w'_k (and w~'_k) as w_k instead of recomputing
  *                w_k = A r~_k; the product computes u = A s~ only.
+ *   PRCG_CG      CG-CG (Appendix D), the Chronopoulos-Gear variant: w = A r~
+ *                each iteration, nu_k and eta_k = <r~_k, w_k> in one
+ *                reduction, mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k.
  * The batched solver runs the first five. */
 typedef enum {
     PRCG_HS = 0,
@@ -73,7 +76,8 @@ typedef enum {
     PRCG_PIPE_M = 4,
     PRCG_GV = 5,
     PRCG_PR_NORECOMPUTE = 6,
-    PRCG_PIPE_PR_NOWRECOMPUTE = 7
+    PRCG_PIPE_PR_NOWRECOMPUTE = 7,
+    PRCG_CG = 8
 } prcg_variant;
 
 /* Preconditioners: none (M = I) or Jacobi (M^{-1} = diag(A)^{-1}). */

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, 
     } else if (variant == kHS) {
         step_hs_nu(st, t[3], PRE ? t[4] : t[3], hist, w);
         if (step0 == 2 && !st.done) step_hs_mu(st, t[0]);
-    } else if (variant == kGV) {
+    } else if (variant == kGV || variant == kCG) {
         step_gv_first(st, t, PRE, hist, w);
     } else if (step0) {
         step_one_reduction(st, t, PRE, nu_form(variant), hist, w);
@@ -579,6 +579,103 @@ __global__ __launch_bounds__(kBlock) void k_gv_spmv(SellView S, CsrView C, Split
         rows_of_group<LANES, 1>(S, C, g, PRE ? v.wt : v.w, nullptr, [&](int64_t i, double ti, double) { t[i] = ti; });
 }
 
+// ------------------------------------------------------------------ CG-CG
+
+// w0 = s0 for CG-CG (w0 = A r~0 = A p0, p0 = r~0), so that its first
+// direction update (beta = 0) reproduces p0 and s0.
+__global__ __launch_bounds__(kBlock) void k_init_w(Split sp, Vecs v)
+{
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    for (int64_t i = i0; i < i1; i += kBlock) v.w[i] = v.s[i];
+}
+
+// CG-CG (Appendix D) in three kernels per iteration.  This one finishes
+// iteration k-1's direction updates with beta_{k-1} and takes iteration k's
+// updates with alpha_{k-1}, all row-local:
+//   p = r~ + beta p; s = w + beta s; x += alpha p; r -= alpha s;
+//   r~ = M^{-1} r (stored for the product),
+// and writes the partials of nu_k = <r~_k, r_k> (+ <r_k, r_k>) to PN.
+// r~_{k-1} is recomputed as d * r_{k-1} (it is defined as M^{-1} r).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Split sp, const State* __restrict__ cur,
+                                                      double* __restrict__ PN, Vecs v)
+{
+    __shared__ double lds[kWaves * 2];
+    const State st = *cur;
+    if (st.done) return;
+    const double alpha = st.alpha, beta = st.beta;
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    double* __restrict__ rt = v.rt;
+    double* __restrict__ p = v.p;
+    double* __restrict__ s = v.s;
+    const double* __restrict__ w = v.w;
+    const double* __restrict__ d = v.d;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = i0; i < i1; i += kBlock) {
+        const double pi = p[i], si = s[i], wi = w[i], xi = x[i], ri = r[i];
+        const double di = PRE ? d[i] : 1.0;
+        const double rti = PRE ? di * ri : ri;                  // r~_{k-1}
+        const double pn = fma(beta, pi, rti);                   // p_{k-1}
+        const double sn = fma(beta, si, wi);                    // s_{k-1}
+        const double rn = fma(-alpha, sn, ri);                  // r_k
+        const double rtn = PRE ? di * rn : rn;                  // r~_k = M^{-1} r_k
+        x[i] = fma(alpha, pn, xi);                              // x_k
+        r[i] = rn;
+        p[i] = pn;
+        s[i] = sn;
+        if (PRE) rt[i] = rtn;
+        acc[0] = fma(rtn, rn, acc[0]);                          // nu_k
+        if (PRE) acc[1] = fma(rn, rn, acc[1]);
+    }
+    write_partials<2>(acc, PN, sp.Gs, blockIdx.x, lds);
+}
+
+// w_k = A r~_k and the partials of eta_k = <r~_k, w_k>.
+template <int LANES, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
+                                                    double* __restrict__ PS, Vecs v)
+{
+    __shared__ double lds[kWaves * 1];
+    if (cur->done) return;
+    int64_t g0, g1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    const double* __restrict__ rt = PRE ? v.rt : v.r;
+    double* __restrict__ w = v.w;
+    double acc[1] = {0.0};
+    for (int64_t g = g0; g < g1; ++g) {
+        rows_of_group<LANES, 1>(S, C, g, rt, nullptr, [&](int64_t i, double wi, double) {
+            w[i] = wi;
+            acc[0] = fma(rt[i], wi, acc[0]);
+        });
+    }
+    write_partials<1>(acc, PS, sp.Gs, blockIdx.x, lds);
+}
+
+// One workgroup: stage 2 of eta_k (PS) and nu_k, <r_k, r_k> (PN), then
+// beta_k, mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k, the tests and alpha_k
+// (the scalar step GV-CG shares).
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_finish(Split sp, const State* __restrict__ in,
+                                                      State* __restrict__ out, double* __restrict__ hist,
+                                                      const double* __restrict__ PS, const double* __restrict__ PN)
+{
+    __shared__ double lds[kWaves * 3];
+    State st = *in;
+    if (!st.done) {
+        double t[3];
+        reduce_partials_at<3, 1, kWholeGrid>(PS, PN, sp.G, sp.Gs, t, lds);  // eta, nu, rr
+        const double q[3] = {t[1], t[0], t[2]};                             // nu, eta, rr
+        step_gv(st, q, PRE, hist, threadIdx.x == 0);
+    }
+    if (threadIdx.x == 0) *out = st;
+}
+
 // ------------------------------------------------------------------ HS-CG
 
 // Stage 2 of mu_{k-1} (alpha_{k-1}), then x += alpha p, r -= alpha s and the
@@ -813,6 +910,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
             if (pipe || gv)
                 hipLaunchKernelGGL((k_init_u<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0,
                                    st, S, C, sp, v, gv);
+            if (variant == kCG) hipLaunchKernelGGL(k_init_w, dim3(sp.G), dim3(kBlock), 0, st, sp, v);
             return hipGetLastError();
         });
     });
@@ -829,6 +927,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
 int iter_kernel_count(int variant, const Split& sp)
 {
     if (variant == kGV) return 2;  // one structure for GV-CG
+    if (variant == kCG) return 3;  // and one for CG-CG
     if (sp.textbook && variant == kHS) return textbook_kernel_count(sp.textbook_pre);
     if (uses_fused(variant, sp)) return variant == kHS ? 2 : 1;
     if (variant == kHS) return stage2_of(sp, kHS) ? 5 : 3;
@@ -839,6 +938,7 @@ int iter_kernel_count(int variant, const Split& sp)
 const char* iter_kernel_name(int variant, const Split& sp, int j)
 {
     if (variant == kGV) return j == 0 ? "k_gv_update" : "k_gv_spmv";
+    if (variant == kCG) return j == 0 ? "k_cg_update" : (j == 1 ? "k_cg_spmv" : "k_cg_finish");
     if (sp.textbook && variant == kHS) return textbook_kernel_name(sp.textbook_pre, j);
     if (uses_fused(variant, sp)) {
         if (variant == kHS) return j == 0 ? "k_hs_xr" : "k_hs_fused";
@@ -877,6 +977,17 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
             int* tk = B.ticket;
             const bool s2 = stage2_of(sp, variant);
             switch (variant) {
+            case kCG:
+                if (j == 0) {
+                    launch(k_cg_update<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.PN, v);
+                } else if (j == 1) {
+                    launch(k_cg_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
+                } else {
+                    launch(k_cg_finish<PP>, dim3(1), block, st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                           (const double*)B.PS, (const double*)B.PN);
+                    cur = nxt;
+                }
+                break;
             case kGV:
                 if (j == 0) {
                     launch(k_gv_update<PP>, grid, block, st, ev, sp, (const State*)B.S[cur], B.PS, v);

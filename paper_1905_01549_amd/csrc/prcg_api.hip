@@ -402,7 +402,7 @@ prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double*
 
 prcg_status check_variant(int v)
 {
-    if (v < PRCG_HS || v > PRCG_PIPE_PR_NOWRECOMPUTE) return fail(PRCG_EINVAL, "unknown variant");
+    if (v < PRCG_HS || v > PRCG_CG) return fail(PRCG_EINVAL, "unknown variant");
     return PRCG_OK;
 }
 

@@ -14,8 +14,18 @@ constexpr int kGroupRows = kBlock;  // rows handled by one workgroup step (4 sli
 constexpr int kMaxDots = 5;
 constexpr int kMaxGrid = 4096;  // largest workgroup count of the row-parallel kernels
 
-enum Variant { kHS = 0, kPR = 1, kPipePR = 2, kM = 3, kPipeM = 4, kGV = 5, kPRNoRecompute = 6, kPipeNoWRecompute = 7 };
-constexpr int kNumVariants = 8;
+enum Variant {
+    kHS = 0,
+    kPR = 1,
+    kPipePR = 2,
+    kM = 3,
+    kPipeM = 4,
+    kGV = 5,
+    kPRNoRecompute = 6,
+    kPipeNoWRecompute = 7,
+    kCG = 8
+};
+constexpr int kNumVariants = 9;
 
 __host__ __device__ inline bool is_pipe(int variant)
 {
@@ -107,11 +117,11 @@ inline bool stage2_of(const Split& sp, int variant)
     return (sp.stage2 & bit) != 0;
 }
 
-// The fused structure covers HS, PR, pipe-PR and their forms; GV-CG and the
-// no-w-recompute ablation always run two-pass.
+// The fused structure covers HS, PR, pipe-PR and their forms; GV-CG, CG-CG
+// and the no-w-recompute ablation always run two-pass.
 inline bool uses_fused(int variant, const Split& sp)
 {
-    return sp.fused && variant != kGV && variant != kPipeNoWRecompute;
+    return sp.fused && variant != kGV && variant != kPipeNoWRecompute && variant != kCG;
 }
 
 // ---- setup kernels (kernels_setup.hip) ----

@@ -21,6 +21,9 @@ KERNEL_WORDS = {
     # GV-CG: the direction updates of k-1 and the updates of k in one pass
     ("gv", False): [("k_gv_update", 7, 6, False), ("k_gv_spmv", 1, 1, True)],
     ("gv", True): [("k_gv_update", 10, 9, False), ("k_gv_spmv", 1, 1, True)],
+    # CG-CG: direction updates of k-1 and updates of k in one pass; w = A r~
+    ("cg", False): [("k_cg_update", 5, 4, False), ("k_cg_spmv", 1, 1, True), ("k_cg_finish", 0, 0, False)],
+    ("cg", True): [("k_cg_update", 6, 5, False), ("k_cg_spmv", 1, 1, True), ("k_cg_finish", 0, 0, False)],
 }
 # fused structure (one kernel per PR / pipe-PR iteration, two per HS):
 # neighbour recomputation reads each double-buffered vector once

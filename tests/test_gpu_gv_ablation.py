@@ -159,7 +159,7 @@ def test_batched_rejects_the_comparator_and_ablations(prcg):
     A, offs = P.block_diag([P.poisson2d(8), P.poisson2d(9)])
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
-    for v in ("gv", "pr_norecompute", "pipe_pr_nowrecompute"):
+    for v in ("gv", "cg", "pr_norecompute", "pipe_pr_nowrecompute"):
         with pytest.raises(prcg.PrcgError):
             B.solve(np.ones(A.n), v, 1e-10, 100)
 
@@ -180,7 +180,7 @@ def test_model_problem_attainable_accuracy(prcg):
     and GV-CG ends orders of magnitude less accurate than PR-CG (Table 2:
     -10.23 vs -14.32), as do the two ablations against their parents."""
     med = {}
-    for v in ("pr", "gv", "pr_norecompute", "pipe_pr", "pipe_pr_nowrecompute"):
+    for v in ("pr", "gv", "cg", "pr_norecompute", "pipe_pr", "pipe_pr_nowrecompute"):
         gpu, orc = [], []
         for seed in range(8):
             pr = P.model_48_8_3(seed)
@@ -197,5 +197,6 @@ def test_model_problem_attainable_accuracy(prcg):
         assert abs(g - o) <= 0.1 * abs(o), (v, g, o)
         med[v] = g
     assert med["gv"] > med["pr"] + 2.0, med
+    assert abs(med["cg"] - med["pr"]) <= 0.1 * abs(med["pr"]), med  # Table 2: CG-CG -14.28
     assert med["pr_norecompute"] > med["pr"] + 2.0, med
     assert med["pipe_pr_nowrecompute"] > med["pipe_pr"] + 2.0, med

@@ -21,7 +21,7 @@ from paper_1905_01549_amd import problems as P
 pytestmark = pytest.mark.gpu
 
 EPS = 2.0 ** -53
-VARIANTS = ["hs", "pr", "pipe_pr", "m", "pipe_m"]
+VARIANTS = ["hs", "pr", "pipe_pr", "m", "pipe_m", "cg"]
 
 
 @pytest.fixture(scope="module")
