@@ -74,41 +74,55 @@ __global__ __launch_bounds__(kBlock) void k_tb_spmv(SellView S, CsrView C, Split
 
 // one workgroup: stage 2 of nu_k (and <r, r>), convergence test, beta_k
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_tb_nu(Split sp, const State* __restrict__ in, State* __restrict__ out,
+__global__ __launch_bounds__(kStage2Block) void k_tb_nu(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                   double* __restrict__ hist, const double* __restrict__ PU)
 {
-    __shared__ double lds[kWaves * 2];
+    __shared__ double lds[kLaneGroups * 2];
     State st = *in;
     if (!st.done) {
         double t[2];
-        reduce_partials<2, kWholeGrid>(PU, sp.G, sp.Gs, t, lds);
+        reduce_partials<2, kStage2Block>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
 }
 
 // one workgroup: stage 2 of mu_k, alpha_k
-__global__ __launch_bounds__(kBlock) void k_tb_mu(Split sp, const State* __restrict__ in, State* __restrict__ out,
+__global__ __launch_bounds__(kStage2Block) void k_tb_mu(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                   const double* __restrict__ PS)
 {
-    __shared__ double lds[kWaves];
+    __shared__ double lds[kLaneGroups * 1];
     State st = *in;
     if (!st.done) {
         double t[1];
-        reduce_partials<1, kWholeGrid>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials<1, kStage2Block>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
     }
     if (threadIdx.x == 0) *out = st;
 }
 
 template <class K, class... Args>
-hipError_t go(K kernel, dim3 grid, hipStream_t st, const LaunchEvents* ev, Args... args)
+hipError_t go_block(K kernel, dim3 grid, dim3 block, hipStream_t st, const LaunchEvents* ev, Args... args)
 {
     if (ev && ev->start)
-        hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, ev->start, ev->stop, 0, args...);
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev->start, ev->stop, 0, args...);
     else
-        hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, args...);
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
     return hipGetLastError();
+}
+
+// row-parallel kernels: kBlock threads per workgroup
+template <class K, class... Args>
+hipError_t go(K kernel, dim3 grid, hipStream_t st, const LaunchEvents* ev, Args... args)
+{
+    return go_block(kernel, grid, dim3(kBlock), st, ev, args...);
+}
+
+// one-workgroup reduction kernels: kStage2Block threads
+template <class K, class... Args>
+hipError_t go1(K kernel, hipStream_t st, const LaunchEvents* ev, Args... args)
+{
+    return go_block(kernel, dim3(1), dim3(kStage2Block), st, ev, args...);
 }
 
 const char* kNames[] = {"k_tb_mu", "k_tb_axpy_x", "k_tb_axpy_r", "k_tb_prec", "k_tb_dot_nu",
@@ -140,7 +154,7 @@ hipError_t launch_textbook_kernel(int pre, int j, int& cur, const SellView* sell
     hipError_t e = hipSuccess;
     switch (k) {
     case 0:  // alpha_{k-1} = nu_{k-1} / mu_{k-1}
-        e = go(k_tb_mu, dim3(1), st, ev, sp, S, B.S[nxt], (const double*)B.PS);
+        e = go1(k_tb_mu, st, ev, sp, S, B.S[nxt], (const double*)B.PS);
         cur = nxt;
         break;
     case 1: e = go(k_tb_axpy, grid, st, ev, sp, S, 1.0, (const double*)v.p, v.x); break;   // x += alpha p
@@ -149,8 +163,8 @@ hipError_t launch_textbook_kernel(int pre, int j, int& cur, const SellView* sell
     case 4: e = go(k_tb_dot, grid, st, ev, sp, S, (const double*)rt, (const double*)v.r, B.PU, 0); break;
     case 5: e = go(k_tb_dot, grid, st, ev, sp, S, (const double*)v.r, (const double*)v.r, B.PU, 1); break;
     case 6:  // nu_k, tests, beta_k
-        e = pre ? go(k_tb_nu<true>, dim3(1), st, ev, sp, S, B.S[nxt], B.hist, (const double*)B.PU)
-                : go(k_tb_nu<false>, dim3(1), st, ev, sp, S, B.S[nxt], B.hist, (const double*)B.PU);
+        e = pre ? go1(k_tb_nu<true>, st, ev, sp, S, B.S[nxt], B.hist, (const double*)B.PU)
+                : go1(k_tb_nu<false>, st, ev, sp, S, B.S[nxt], B.hist, (const double*)B.PU);
         cur = nxt;
         break;
     case 7: e = go(k_tb_xpay, grid, st, ev, sp, S, (const double*)rt, v.p); break;  // p = r~ + beta p

@@ -41,50 +41,75 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * N
 }
 
 // Stage 2 of a reduction: the G per-workgroup partials of each of NV values
-// are summed in a fixed order (G <= kMaxGrid).  Value i < N1 is read from
+// are summed in one fixed order (G <= kMaxGrid).  Value i < N1 is read from
 // P1[i * Gs + g], value i >= N1 from P2[(i - N1) * Gs + g] (two kernels may
-// produce the partials of one reduction).  Every thread of the calling
-// workgroup receives the totals.  Thread t adds the partials t, t + 256,
-// t + 512, ... in that order; they are loaded PIECE at a time, all loads of
-// a piece before its first addition.  Kernels that do nothing else use
-// PIECE = kMaxGrid / kBlock (one memory latency for any G); kernels that
-// reduce beside other work use 4, to keep their register count down.  The
-// order of additions is the same for every PIECE.
-template <int NV, int N1, int PIECE = 4>
+// produce the partials of one reduction).  The order is defined over
+// kLanes = 1024 virtual lanes: lane l adds the partials l, l + 1024,
+// l + 2048, l + 3072 (those below G) in that order; each group of 64 lanes
+// is summed by the wavefront butterfly, and the 16 group sums in order.  A
+// workgroup of BS threads (kBlock, or kStage2Block for the one-workgroup
+// stage-2 kernels) holds kLanes / BS lanes per thread and gets the same bits
+// whatever BS is; with BS = kStage2Block each thread issues all its loads
+// (4 per value) at once, so stage 2 costs one memory latency.  Every thread
+// receives the totals.  lds: kLaneGroups * NV doubles.
+constexpr int kLanes = 1024;
+constexpr int kLaneGroups = kLanes / 64;
+constexpr int kStage2Block = 1024;
+
+template <int NV, int N1, int BS = kBlock, int M>
 __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1, const double* __restrict__ P2, int G,
-                                                   int Gs, double (&tot)[NV], double* lds)
+                                                   int Gs, double (&tot)[NV], double (&lds)[M])
 {
-    constexpr int kPiece = PIECE;
+    static_assert(kMaxGrid % kLanes == 0 && kLanes % BS == 0, "lane layout");
+    static_assert(M >= kLaneGroups * NV, "lds must hold one sum per lane group and value");
+    constexpr int Q = kLanes / BS;        // lanes per thread
+    constexpr int J = kMaxGrid / kLanes;  // partials per lane
     const double* P[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+    const int t = threadIdx.x;
+    const int wave = t >> 6;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) tot[i] = 0.0;
-    for (int g0 = 0; g0 < G; g0 += kPiece * kBlock) {
-        double buf[NV][kPiece];
+    for (int q = 0; q < Q; ++q) {
+        const int l = t + BS * q;
+        double buf[NV][J];
 #pragma unroll
-        for (int j = 0; j < kPiece; ++j) {
-            const int g = g0 + (int)threadIdx.x + j * kBlock;
+        for (int j = 0; j < J; ++j) {
+            const int g = l + kLanes * j;
 #pragma unroll
             for (int i = 0; i < NV; ++i) buf[i][j] = g < G ? P[i][g] : 0.0;
         }
+        double v[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
+            double a = 0.0;
 #pragma unroll
-            for (int j = 0; j < kPiece; ++j) tot[i] += buf[i][j];
+            for (int j = 0; j < J; ++j) a += buf[i][j];
+            v[i] = wave_sum(a);
+        }
+        const int grp = wave + (BS / 64) * q;  // the lane group of lane l
+        if ((t & 63) == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) lds[grp * NV + i] = v[i];
         }
     }
-    block_sum<NV>(tot, lds);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double a = lds[i];
+#pragma unroll
+        for (int grp = 1; grp < kLaneGroups; ++grp) a += lds[grp * NV + i];
+        tot[i] = a;
+    }
+    __syncthreads();
 }
 
-template <int NV, int PIECE = 4>
+template <int NV, int BS = kBlock, int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
-                                                double* lds)
+                                                double (&lds)[M])
 {
-    reduce_partials_at<NV, NV, PIECE>(P, nullptr, G, Gs, tot, lds);
+    reduce_partials_at<NV, NV, BS>(P, nullptr, G, Gs, tot, lds);
 }
-
-constexpr int kWholeGrid = kMaxGrid / kBlock;  // PIECE of the one-workgroup stage-2 kernels
 
 // Stage 1: per-thread sums -> one partial per workgroup and value (value
 // i < N1 to P1, the others to P2, with the layout of reduce_partials_at).

@@ -345,6 +345,25 @@ def test_reduction_placements_agree_bitwise(prcg, torch_cuda):
                 assert np.array_equal(x, out[0][0]) and np.array_equal(h, out[0][2]), (v, pre)
 
 
+def test_reduction_order_is_independent_of_block_size(prcg, torch_cuda):
+    """With more than 1024 partials, the 256-thread in-kernel reductions
+    (redundant, last-workgroup) and the 1024-thread stage-2 kernels follow one
+    order over 1024 virtual lanes: identical bits."""
+    A = P.poisson3d(72)  # 1458 row groups
+    b = P.uniform_vector(A.n, 8)
+    for v in ("hs", "pr", "pipe_pr", "cg"):
+        out = []
+        for kernels in ("two_pass_redundant", "two_pass_stage2", "two_pass_last"):
+            M = gpu_matrix(prcg, A, "jacobi", kernels)
+            M.set_grid(1456)
+            assert M.props.grid == 1456
+            x, info = M.solve(b, v, 0.0, 150, history=True)
+            out.append((x.cpu().numpy(), info.history))
+            M.close()
+        for x, h in out[1:]:
+            assert np.array_equal(x, out[0][0]) and np.array_equal(h, out[0][1]), v
+
+
 def test_last_workgroup_ticket_survives_grid_changes(prcg, torch_cuda):
     """The ticket counter of the last-workgroup reduction returns to 0 after
     every kernel, so solves with different grids on one handle stay exact."""
