@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const
                                                      const double* __restrict__ Pin, double* __restrict__ Pout,
                                                      int form, FusedVecs f, int q)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     State st;
     if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, form, st, lds)) return;
     const double alpha = st.alpha, beta = st.beta;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, con
                                                        const double* __restrict__ Pin, double* __restrict__ Pout,
                                                        int form, FusedVecs f, int q)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     State st;
     if (!enter_one_reduction<PRE>(sp, in, out, hist, Pin, form, st, lds)) return;
     const double alpha = st.alpha, beta = st.beta;
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_fused(SellView S, Split sp, const
                                                      const double* __restrict__ PU, double* __restrict__ PS,
                                                      FusedVecs f, int q)
 {
-    __shared__ double lds[kLaneGroups * 2];
+    __shared__ double lds[kWaves * 2];
     State st = *in;
     if (st.done) {
         if (writer()) *out = st;

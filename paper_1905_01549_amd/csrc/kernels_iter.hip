@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_init_r(SellView S, CsrView C, Split 
                                                    const double* __restrict__ x0, Vecs v, int store_rt,
                                                    double* __restrict__ PB)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     double acc[1] = {0.0};
@@ -90,7 +90,7 @@ template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split sp, Vecs v, int store_st,
                                                    double* __restrict__ PS, double* __restrict__ PN)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -144,16 +144,16 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
 // product kernel); otherwise the first iteration kernel does.  HS with
 // step0 = 2 also forms alpha_0 from mu_0.
 template <bool PRE>
-__global__ __launch_bounds__(kStage2Block) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
+__global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
                                                         const double* __restrict__ PS, const double* __restrict__ PN,
                                                         State* __restrict__ out, double* __restrict__ hist, double tol,
                                                         int maxit)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     double bb[1];
-    reduce_partials<1, kStage2Block>(PB, sp.G, sp.Gs, bb, lds);
+    reduce_partials<1, true>(PB, sp.G, sp.Gs, bb, lds);
     double t[5];
-    reduce_partials_at<5, 3, kStage2Block>(PS, PN, sp.G, sp.Gs, t, lds);
+    reduce_partials_at<5, 3, true>(PS, PN, sp.G, sp.Gs, t, lds);
     State st = {};
     st.bnorm = sqrt(bb[0]);
     st.tol = tol;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
 {
     static_assert(!(REDUCE && NUDOT), "PN is read by every workgroup when REDUCE");
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     State st = *in;
     if (REDUCE) {
         if (st.done) {
@@ -274,45 +274,45 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
 // one-reduction variant (PR, M, pipe-PR, pipe-M), when neither the consuming
 // kernel nor the producing kernel reduces the partials itself.
 template <bool PRE>
-__global__ __launch_bounds__(kStage2Block) void k_finish_one(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, const double* __restrict__ PN,
                                                       int form)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     State st = *in;
     if (!st.done) {
         double t[5];
-        reduce_partials_at<5, 3, kStage2Block>(PS, PN, sp.G, sp.Gs, t, lds);
+        reduce_partials_at<5, 3, true>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
 }
 
 // One workgroup: stage 2 of HS-CG's mu_k (alpha_k) or nu_k (tests, beta_k).
-__global__ __launch_bounds__(kStage2Block) void k_hs_finish_mu(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_hs_finish_mu(Split sp, const State* __restrict__ in,
                                                          State* __restrict__ out, const double* __restrict__ PS)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     State st = *in;
     if (!st.done) {
         double t[1];
-        reduce_partials<1, kStage2Block>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
     }
     if (threadIdx.x == 0) *out = st;
 }
 
 template <bool PRE>
-__global__ __launch_bounds__(kStage2Block) void k_hs_finish_nu(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* __restrict__ in,
                                                          State* __restrict__ out, double* __restrict__ hist,
                                                          const double* __restrict__ PU)
 {
-    __shared__ double lds[kLaneGroups * 2];
+    __shared__ double lds[kWaves * 2];
     State st = *in;
     if (!st.done) {
         double t[2];
-        reduce_partials<2, kStage2Block>(PU, sp.G, sp.Gs, t, lds);
+        reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
 {
     static_assert(PRE || NUDOT, "without a preconditioner nu = <r, r> is formed here");
     constexpr int NV = NUDOT ? 5 : 3;
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     if (in->done) {
         if (LAST && writer_thread()) *out = *in;
         return;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
                                                         State* __restrict__ out, double* __restrict__ hist,
                                                         double* __restrict__ PS, int form, int* ticket, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     const State st = *in;
     if (st.done) {
         if (LAST && writer_thread()) *out = st;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, int form, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 5];
+    __shared__ double lds[kWaves * 5];
     const State st = *in;
     if (REDUCE && blockIdx.x == 0) {
         State nx = st;
@@ -499,7 +499,7 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_gv_update(Split sp, const State* __restrict__ cur,
                                                       double* __restrict__ PS, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 3];
+    __shared__ double lds[kWaves * 3];
     const State st = *cur;
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_gv_spmv(SellView S, CsrView C, Split
                                                     State* __restrict__ out, double* __restrict__ hist,
                                                     const double* __restrict__ PS, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 3];
+    __shared__ double lds[kWaves * 3];
     const State st = *in;
     if (blockIdx.x == 0) {
         State nx = st;
@@ -602,7 +602,7 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Split sp, const State* __restrict__ cur,
                                                       double* __restrict__ PN, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 2];
+    __shared__ double lds[kWaves * 2];
     const State st = *cur;
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
@@ -641,7 +641,7 @@ template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
                                                     double* __restrict__ PS, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     if (cur->done) return;
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
@@ -661,15 +661,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(SellView S, CsrView C, Split
 // beta_k, mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k, the tests and alpha_k
 // (the scalar step GV-CG shares).
 template <bool PRE>
-__global__ __launch_bounds__(kStage2Block) void k_cg_finish(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_cg_finish(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, const double* __restrict__ PN)
 {
-    __shared__ double lds[kLaneGroups * 3];
+    __shared__ double lds[kWaves * 3];
     State st = *in;
     if (!st.done) {
         double t[3];
-        reduce_partials_at<3, 1, kStage2Block>(PS, PN, sp.G, sp.Gs, t, lds);  // eta, nu, rr
+        reduce_partials_at<3, 1, true>(PS, PN, sp.G, sp.Gs, t, lds);  // eta, nu, rr
         const double q[3] = {t[1], t[0], t[2]};                             // nu, eta, rr
         step_gv(st, q, PRE, hist, threadIdx.x == 0);
     }
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
                                                   double* __restrict__ PU, int* ticket, Vecs v)
 {
     static_assert(!(REDUCE && LAST), "one state transition per kernel");
-    __shared__ double lds[kLaneGroups * 2];
+    __shared__ double lds[kWaves * 2];
     State st = *in;
     if (REDUCE) {
         if (st.done) {
@@ -739,7 +739,7 @@ template <bool PRE, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                  double* __restrict__ hist, const double* __restrict__ PU, Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 2];
+    __shared__ double lds[kWaves * 2];
     State st = *in;
     if (REDUCE) {
         if (st.done) {
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split
                                                     State* __restrict__ out, double* __restrict__ PS, int* ticket,
                                                     Vecs v)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     if (in->done) {
         if (LAST && writer_thread()) *out = *in;
         return;
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void k_final_res(SellView S, CsrView C, Spl
                                                       const double* __restrict__ b, const double* __restrict__ x,
                                                       double* __restrict__ xout, double* __restrict__ PB)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     const int zero = cur->zero_x;
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
@@ -826,11 +826,11 @@ __global__ __launch_bounds__(kBlock) void k_final_res(SellView S, CsrView C, Spl
     write_partials<1>(acc, PB, sp.Gs, blockIdx.x, lds);
 }
 
-__global__ __launch_bounds__(kStage2Block) void k_final_reduce(Split sp, const double* __restrict__ PB, State* __restrict__ st)
+__global__ __launch_bounds__(kBlock) void k_final_reduce(Split sp, const double* __restrict__ PB, State* __restrict__ st)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     double t[1];
-    reduce_partials<1, kStage2Block>(PB, sp.G, sp.Gs, t, lds);
+    reduce_partials<1, true>(PB, sp.G, sp.Gs, t, lds);
     if (threadIdx.x == 0) {
         const double bn = st->bnorm;
         st->relres_true = bn > 0.0 ? sqrt(t[0]) / bn : 0.0;
@@ -918,7 +918,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     return with_pre(pre, [&](auto P) {
         const bool pipe2 = is_pipe(variant) && !uses_fused(variant, sp);
         const int step0 = variant == kHS ? (sp.lastwg ? 2 : 1) : (pipe2 || sp.lastwg ? 1 : 0);
-        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kStage2Block), 0, st, variant, step0, sp,
+        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
                            B.PB, B.PS, pn_of(variant, pre, sp, B), B.S[0], B.hist, tol, (int)maxit);
         return hipGetLastError();
     });
@@ -983,7 +983,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 } else if (j == 1) {
                     launch(k_cg_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
                 } else {
-                    launch(k_cg_finish<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                    launch(k_cg_finish<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PS, (const double*)B.PN);
                     cur = nxt;
                 }
@@ -1035,7 +1035,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                         cur = nxt;
                     }
                 } else if (s2 && j == 0) {
-                    launch(k_finish_one<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                    launch(k_finish_one<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PS, (const double*)PN, form);
                     cur = nxt;
                 } else if (s2 && j == 1) {
@@ -1070,7 +1070,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                         launch(k_pipe_spmv<LL, PP, false, NW>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
                                B.S[nxt], B.hist, (const double*)B.PS, form, v);
                     } else if (s2) {
-                        launch(k_finish_one<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                        launch(k_finish_one<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                                B.hist, (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), form);
                         cur = nxt;
                     } else {
@@ -1100,14 +1100,14 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                         cur = nxt;
                     }
                 } else if (s2 && j == 0) {
-                    launch(k_hs_finish_mu, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                    launch(k_hs_finish_mu, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            (const double*)B.PS);
                     cur = nxt;
                 } else if (s2 && j == 1) {
                     launch(k_hs_xr<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            B.hist, (const double*)B.PS, B.PU, tk, v);
                 } else if (s2 && j == 2) {
-                    launch(k_hs_finish_nu<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                    launch(k_hs_finish_nu<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            B.hist, (const double*)B.PU);
                     cur = nxt;
                 } else if (s2 && j == 3) {
@@ -1144,7 +1144,7 @@ hipError_t launch_final(const SellView* sell, const CsrView* csr, const Split& s
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(kStage2Block), 0, st, sp, B.PB, B.S[cur]);
+    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(kBlock), 0, st, sp, B.PB, B.S[cur]);
     return hipGetLastError();
 }
 

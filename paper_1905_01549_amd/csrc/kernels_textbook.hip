@@ -74,55 +74,48 @@ __global__ __launch_bounds__(kBlock) void k_tb_spmv(SellView S, CsrView C, Split
 
 // one workgroup: stage 2 of nu_k (and <r, r>), convergence test, beta_k
 template <bool PRE>
-__global__ __launch_bounds__(kStage2Block) void k_tb_nu(Split sp, const State* __restrict__ in, State* __restrict__ out,
+__global__ __launch_bounds__(kBlock) void k_tb_nu(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                   double* __restrict__ hist, const double* __restrict__ PU)
 {
-    __shared__ double lds[kLaneGroups * 2];
+    __shared__ double lds[kWaves * 2];
     State st = *in;
     if (!st.done) {
         double t[2];
-        reduce_partials<2, kStage2Block>(PU, sp.G, sp.Gs, t, lds);
+        reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
     }
     if (threadIdx.x == 0) *out = st;
 }
 
 // one workgroup: stage 2 of mu_k, alpha_k
-__global__ __launch_bounds__(kStage2Block) void k_tb_mu(Split sp, const State* __restrict__ in, State* __restrict__ out,
+__global__ __launch_bounds__(kBlock) void k_tb_mu(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                   const double* __restrict__ PS)
 {
-    __shared__ double lds[kLaneGroups * 1];
+    __shared__ double lds[kWaves * 1];
     State st = *in;
     if (!st.done) {
         double t[1];
-        reduce_partials<1, kStage2Block>(PS, sp.G, sp.Gs, t, lds);
+        reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
     }
     if (threadIdx.x == 0) *out = st;
 }
 
 template <class K, class... Args>
-hipError_t go_block(K kernel, dim3 grid, dim3 block, hipStream_t st, const LaunchEvents* ev, Args... args)
+hipError_t go(K kernel, dim3 grid, hipStream_t st, const LaunchEvents* ev, Args... args)
 {
     if (ev && ev->start)
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev->start, ev->stop, 0, args...);
+        hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, ev->start, ev->stop, 0, args...);
     else
-        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+        hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, args...);
     return hipGetLastError();
 }
 
-// row-parallel kernels: kBlock threads per workgroup
-template <class K, class... Args>
-hipError_t go(K kernel, dim3 grid, hipStream_t st, const LaunchEvents* ev, Args... args)
-{
-    return go_block(kernel, grid, dim3(kBlock), st, ev, args...);
-}
-
-// one-workgroup reduction kernels: kStage2Block threads
+// one-workgroup reduction kernels
 template <class K, class... Args>
 hipError_t go1(K kernel, hipStream_t st, const LaunchEvents* ev, Args... args)
 {
-    return go_block(kernel, dim3(1), dim3(kStage2Block), st, ev, args...);
+    return go(kernel, dim3(1), st, ev, args...);
 }
 
 const char* kNames[] = {"k_tb_mu", "k_tb_axpy_x", "k_tb_axpy_r", "k_tb_prec", "k_tb_dot_nu",

@@ -41,74 +41,67 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * N
 }
 
 // Stage 2 of a reduction: the G per-workgroup partials of each of NV values
-// are summed in one fixed order (G <= kMaxGrid).  Value i < N1 is read from
-// P1[i * Gs + g], value i >= N1 from P2[(i - N1) * Gs + g] (two kernels may
-// produce the partials of one reduction).  The order is defined over
-// kLanes = 1024 virtual lanes: lane l adds the partials l, l + 1024,
-// l + 2048, l + 3072 (those below G) in that order; each group of 64 lanes
-// is summed by the wavefront butterfly, and the 16 group sums in order.  A
-// workgroup of BS threads (kBlock, or kStage2Block for the one-workgroup
-// stage-2 kernels) holds kLanes / BS lanes per thread and gets the same bits
-// whatever BS is; with BS = kStage2Block each thread issues all its loads
-// (4 per value) at once, so stage 2 costs one memory latency.  Every thread
-// receives the totals.  lds: kLaneGroups * NV doubles.
-constexpr int kLanes = 1024;
-constexpr int kLaneGroups = kLanes / 64;
-constexpr int kStage2Block = 1024;
-
-template <int NV, int N1, int BS = kBlock, int M>
+// are summed in one fixed order (G <= kMaxGrid) by a workgroup of kBlock
+// threads.  Value i < N1 is read from P1[i * Gs + g], value i >= N1 from
+// P2[(i - N1) * Gs + g] (two kernels may produce the partials of one
+// reduction).  Thread t adds the partials t, t + kBlock, t + 2 kBlock, ...
+// (those below G) in that order, then block_sum.  Every thread receives the
+// totals.  lds: kWaves * NV doubles.
+//
+// ALL: every load of a thread is issued before its first addition (the
+// one-workgroup stage-2 kernels: one memory latency for any G, kMaxGrid /
+// kBlock * NV registers); otherwise four per value at a time (kernels that
+// reduce beside other work, to keep their register count down).  The order
+// of additions is the same either way.  (Measured on MI355X: stage-2
+// kernels of 1024 threads are limited to 128 registers per thread, spill,
+// and take twice as long as these.)
+template <int NV, int N1, bool ALL = false, int M>
 __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1, const double* __restrict__ P2, int G,
                                                    int Gs, double (&tot)[NV], double (&lds)[M])
 {
-    static_assert(kMaxGrid % kLanes == 0 && kLanes % BS == 0, "lane layout");
-    static_assert(M >= kLaneGroups * NV, "lds must hold one sum per lane group and value");
-    constexpr int Q = kLanes / BS;        // lanes per thread
-    constexpr int J = kMaxGrid / kLanes;  // partials per lane
+    static_assert(kMaxGrid % kBlock == 0, "partials per thread");
+    static_assert(M >= kWaves * NV, "lds must hold one sum per wavefront and value");
+    constexpr int J = kMaxGrid / kBlock;  // partials per thread
+    constexpr int PIECE = ALL ? J : 4;    // loads per value in flight
     const double* P[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
     const int t = threadIdx.x;
-    const int wave = t >> 6;
+    double acc[NV];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int l = t + BS * q;
-        double buf[NV][J];
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int j0 = 0; j0 < J && j0 * kBlock < G; j0 += PIECE) {
+        // unconditional loads (index clamped to a valid partial, G >= 1) and
+        // a select, so that every load of the piece is in flight at once
+        double buf[NV][PIECE];
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int g = l + kLanes * j;
+        for (int j = 0; j < PIECE; ++j) {
+            const int g = t + kBlock * (j0 + j);
+            const int gc = g < G ? g : G - 1;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) buf[i][j] = g < G ? P[i][g] : 0.0;
+            for (int i = 0; i < NV; ++i) {
+                const double pv = P[i][gc];
+                buf[i][j] = g < G ? pv : 0.0;
+            }
         }
-        double v[NV];
+        // keep the scheduler from starting the sums before the last load
+        if (ALL) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            double a = 0.0;
 #pragma unroll
-            for (int j = 0; j < J; ++j) a += buf[i][j];
-            v[i] = wave_sum(a);
-        }
-        const int grp = wave + (BS / 64) * q;  // the lane group of lane l
-        if ((t & 63) == 0) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) lds[grp * NV + i] = v[i];
+            for (int j = 0; j < PIECE; ++j) acc[i] += buf[i][j];
         }
     }
-    __syncthreads();
+    block_sum<NV>(acc, lds);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double a = lds[i];
-#pragma unroll
-        for (int grp = 1; grp < kLaneGroups; ++grp) a += lds[grp * NV + i];
-        tot[i] = a;
-    }
-    __syncthreads();
+    for (int i = 0; i < NV; ++i) tot[i] = acc[i];
 }
 
-template <int NV, int BS = kBlock, int M>
+template <int NV, bool ALL = false, int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
                                                 double (&lds)[M])
 {
-    reduce_partials_at<NV, NV, BS>(P, nullptr, G, Gs, tot, lds);
+    reduce_partials_at<NV, NV, ALL>(P, nullptr, G, Gs, tot, lds);
 }
 
 // Stage 1: per-thread sums -> one partial per workgroup and value (value

@@ -345,10 +345,11 @@ def test_reduction_placements_agree_bitwise(prcg, torch_cuda):
                 assert np.array_equal(x, out[0][0]) and np.array_equal(h, out[0][2]), (v, pre)
 
 
-def test_reduction_order_is_independent_of_block_size(prcg, torch_cuda):
-    """With more than 1024 partials, the 256-thread in-kernel reductions
-    (redundant, last-workgroup) and the 1024-thread stage-2 kernels follow one
-    order over 1024 virtual lanes: identical bits."""
+def test_reduction_order_is_independent_of_load_batching(prcg, torch_cuda):
+    """With more than 1024 partials, the in-kernel reductions (redundant,
+    last-workgroup), which load four partials per thread and value at a
+    time, and the stage-2 kernels, which load all of them at once, add in one
+    order: identical bits."""
     A = P.poisson3d(72)  # 1458 row groups
     b = P.uniform_vector(A.n, 8)
     for v in ("hs", "pr", "pipe_pr", "cg"):
