@@ -32,15 +32,15 @@ __device__ __forceinline__ bool enter_one_reduction(const Split& sp, const State
                                                     const double* __restrict__ Pin, int form, State& st,
                                                     double (&lds)[M])
 {
-    st = *in;
+    st = load_state(in);
     if (st.done) {
-        if (writer()) *out = st;
+        if (writer()) store_state(out, st);
         return false;
     }
     double t[5];
     reduce_partials<5>(Pin, sp.G, sp.Gs, t, lds);
     step_one_reduction(st, t, PRE, form, hist, writer());
-    if (writer()) *out = st;
+    if (writer()) store_state(out, st);
     return !st.done;
 }
 
@@ -253,15 +253,15 @@ __global__ __launch_bounds__(kBlock) void k_hs_fused(SellView S, Split sp, const
                                                      FusedVecs f, int q)
 {
     __shared__ double lds[kWaves * 2];
-    State st = *in;
+    State st = load_state(in);
     if (st.done) {
-        if (writer()) *out = st;
+        if (writer()) store_state(out, st);
         return;
     }
     double t[2];
     reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
     step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, writer());
-    if (writer()) *out = st;
+    if (writer()) store_state(out, st);
     if (st.done) return;
     const double beta = st.beta;
     const double* __restrict__ p_o = f.p[q];

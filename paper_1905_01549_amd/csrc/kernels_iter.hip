@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, 
         step_one_reduction(st, t, PRE, nu_form(variant), hist, w);
     }
     // otherwise the first iteration kernel performs the step for k = 0
-    if (w) *out = st;
+    if (w) store_state(out, st);
 }
 
 // ------------------------------------------------------------------ PR-CG
@@ -206,16 +206,16 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
     static_assert(!(REDUCE && NUDOT), "PN is read by every workgroup when REDUCE");
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
     __shared__ double lds[kWaves * 5];
-    State st = *in;
+    State st = load_state(in);
     if (REDUCE) {
         if (st.done) {
-            if (writer_thread()) *out = st;
+            if (writer_thread()) store_state(out, st);
             return;
         }
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, form, hist, writer_thread());
-        if (writer_thread()) *out = st;
+        if (writer_thread()) store_state(out, st);
     }
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
@@ -280,13 +280,13 @@ __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __
                                                       int form)
 {
     __shared__ double lds[kWaves * 5];
-    State st = *in;
-    if (!st.done) {
-        double t[5];
-        reduce_partials_at<5, 3, true>(PS, PN, sp.G, sp.Gs, t, lds);
-        step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
-    }
-    if (threadIdx.x == 0) *out = st;
+    // the partials are read whether or not the solve has ended (the loads
+    // stay in bounds), so their latency overlaps that of the state
+    State st = load_state(in);
+    double t[5];
+    reduce_partials_at<5, 3, true>(PS, PN, sp.G, sp.Gs, t, lds);
+    if (!st.done) step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
+    if (threadIdx.x == 0) store_state(out, st);
 }
 
 // One workgroup: stage 2 of HS-CG's mu_k (alpha_k) or nu_k (tests, beta_k).
@@ -294,13 +294,11 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_mu(Split sp, const State* 
                                                          State* __restrict__ out, const double* __restrict__ PS)
 {
     __shared__ double lds[kWaves * 1];
-    State st = *in;
-    if (!st.done) {
-        double t[1];
-        reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);
-        step_hs_mu(st, t[0]);
-    }
-    if (threadIdx.x == 0) *out = st;
+    State st = load_state(in);
+    double t[1];
+    reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
+    if (!st.done) step_hs_mu(st, t[0]);
+    if (threadIdx.x == 0) store_state(out, st);
 }
 
 template <bool PRE>
@@ -309,13 +307,11 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* 
                                                          const double* __restrict__ PU)
 {
     __shared__ double lds[kWaves * 2];
-    State st = *in;
-    if (!st.done) {
-        double t[2];
-        reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);
-        step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
-    }
-    if (threadIdx.x == 0) *out = st;
+    State st = load_state(in);
+    double t[2];
+    reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
+    if (!st.done) step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
+    if (threadIdx.x == 0) store_state(out, st);
 }
 
 // s_k = A p_k, s~_k = M^{-1} s_k, and the inner products of Alg. 2
@@ -333,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
     constexpr int NV = NUDOT ? 5 : 3;
     __shared__ double lds[kWaves * 5];
     if (in->done) {
-        if (LAST && writer_thread()) *out = *in;
+        if (LAST && writer_thread()) store_state(out, load_state(in));
         return;
     }
     int64_t g0, g1;
@@ -358,11 +354,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
     }
     write_partials_at<NV, 3>(acc, PS, PN, sp.Gs, blockIdx.x, lds);
     if (LAST && take_last_ticket(ticket, sp.G)) {
-        State st = *in;
+        State st = load_state(in);
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
         step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
-        if (threadIdx.x == 0) *out = st;
+        if (threadIdx.x == 0) store_state(out, st);
     }
 }
 
@@ -385,9 +381,9 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
                                                         double* __restrict__ PS, int form, int* ticket, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
-    const State st = *in;
+    const State st = load_state(in);
     if (st.done) {
-        if (LAST && writer_thread()) *out = st;
+        if (LAST && writer_thread()) store_state(out, st);
         return;
     }
     const double alpha = st.alpha, beta = st.beta;
@@ -442,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
         double t[5];
         reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
         step_one_reduction(nx, t, PRE, form, hist, threadIdx.x == 0);
-        if (threadIdx.x == 0) *out = nx;
+        if (threadIdx.x == 0) store_state(out, nx);
     }
 }
 
@@ -462,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
                                                       const double* __restrict__ PS, int form, Vecs v)
 {
     __shared__ double lds[kWaves * 5];
-    const State st = *in;
+    const State st = load_state(in);
     if (REDUCE && blockIdx.x == 0) {
         State nx = st;
         if (!st.done) {
@@ -470,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Spl
             reduce_partials<5>(PS, sp.G, sp.Gs, t, lds);
             step_one_reduction(nx, t, PRE, form, hist, threadIdx.x == 0);
         }
-        if (threadIdx.x == 0) *out = nx;
+        if (threadIdx.x == 0) store_state(out, nx);
     }
     if (st.done) return;
     int64_t g0, g1;
@@ -500,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_gv_update(Split sp, const State* __r
                                                       double* __restrict__ PS, Vecs v)
 {
     __shared__ double lds[kWaves * 3];
-    const State st = *cur;
+    const State st = load_state(cur);
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
@@ -561,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_gv_spmv(SellView S, CsrView C, Split
                                                     const double* __restrict__ PS, Vecs v)
 {
     __shared__ double lds[kWaves * 3];
-    const State st = *in;
+    const State st = load_state(in);
     if (blockIdx.x == 0) {
         State nx = st;
         if (!st.done) {
@@ -569,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_gv_spmv(SellView S, CsrView C, Split
             reduce_partials<3>(PS, sp.G, sp.Gs, t, lds);
             step_gv(nx, t, PRE, hist, threadIdx.x == 0);
         }
-        if (threadIdx.x == 0) *out = nx;
+        if (threadIdx.x == 0) store_state(out, nx);
     }
     if (st.done) return;
     int64_t g0, g1;
@@ -603,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Split sp, const State* __r
                                                       double* __restrict__ PN, Vecs v)
 {
     __shared__ double lds[kWaves * 2];
-    const State st = *cur;
+    const State st = load_state(cur);
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
@@ -666,14 +662,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_finish(Split sp, const State* __r
                                                       const double* __restrict__ PS, const double* __restrict__ PN)
 {
     __shared__ double lds[kWaves * 3];
-    State st = *in;
+    State st = load_state(in);
+    double t[3];
+    reduce_partials_at<3, 1, true>(PS, PN, sp.G, sp.Gs, t, lds);  // eta, nu, rr; read whether or not the solve has ended
     if (!st.done) {
-        double t[3];
-        reduce_partials_at<3, 1, true>(PS, PN, sp.G, sp.Gs, t, lds);  // eta, nu, rr
-        const double q[3] = {t[1], t[0], t[2]};                             // nu, eta, rr
+        const double q[3] = {t[1], t[0], t[2]};  // nu, eta, rr
         step_gv(st, q, PRE, hist, threadIdx.x == 0);
     }
-    if (threadIdx.x == 0) *out = st;
+    if (threadIdx.x == 0) store_state(out, st);
 }
 
 // ------------------------------------------------------------------ HS-CG
@@ -690,19 +686,19 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
 {
     static_assert(!(REDUCE && LAST), "one state transition per kernel");
     __shared__ double lds[kWaves * 2];
-    State st = *in;
+    State st = load_state(in);
     if (REDUCE) {
         if (st.done) {
-            if (writer_thread()) *out = st;
+            if (writer_thread()) store_state(out, st);
             return;
         }
         double t[1];
         reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
-        if (writer_thread()) *out = st;
+        if (writer_thread()) store_state(out, st);
     }
     if (st.done) {
-        if (LAST && writer_thread()) *out = st;
+        if (LAST && writer_thread()) store_state(out, st);
         return;
     }
     const double alpha = st.alpha;
@@ -730,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
         double t[2];
         reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
-        if (threadIdx.x == 0) *out = st;
+        if (threadIdx.x == 0) store_state(out, st);
     }
 }
 
@@ -740,16 +736,16 @@ __global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restri
                                                  double* __restrict__ hist, const double* __restrict__ PU, Vecs v)
 {
     __shared__ double lds[kWaves * 2];
-    State st = *in;
+    State st = load_state(in);
     if (REDUCE) {
         if (st.done) {
-            if (writer_thread()) *out = st;
+            if (writer_thread()) store_state(out, st);
             return;
         }
         double t[2];
         reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
         step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, writer_thread());
-        if (writer_thread()) *out = st;
+        if (writer_thread()) store_state(out, st);
     }
     if (st.done) return;
     const double beta = st.beta;
@@ -780,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split
 {
     __shared__ double lds[kWaves * 1];
     if (in->done) {
-        if (LAST && writer_thread()) *out = *in;
+        if (LAST && writer_thread()) store_state(out, load_state(in));
         return;
     }
     int64_t g0, g1;
@@ -794,11 +790,11 @@ __global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split
     }
     write_partials<1>(acc, PS, sp.Gs, blockIdx.x, lds);
     if (LAST && take_last_ticket(ticket, sp.G)) {
-        State st = *in;
+        State st = load_state(in);
         double t[1];
         reduce_partials<1>(PS, sp.G, sp.Gs, t, lds);
         step_hs_mu(st, t[0]);
-        if (threadIdx.x == 0) *out = st;
+        if (threadIdx.x == 0) store_state(out, st);
     }
 }
 

@@ -78,13 +78,11 @@ __global__ __launch_bounds__(kBlock) void k_tb_nu(Split sp, const State* __restr
                                                   double* __restrict__ hist, const double* __restrict__ PU)
 {
     __shared__ double lds[kWaves * 2];
-    State st = *in;
-    if (!st.done) {
-        double t[2];
-        reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);
-        step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
-    }
-    if (threadIdx.x == 0) *out = st;
+    State st = load_state(in);
+    double t[2];
+    reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
+    if (!st.done) step_hs_nu(st, t[0], PRE ? t[1] : t[0], hist, threadIdx.x == 0);
+    if (threadIdx.x == 0) store_state(out, st);
 }
 
 // one workgroup: stage 2 of mu_k, alpha_k
@@ -92,13 +90,11 @@ __global__ __launch_bounds__(kBlock) void k_tb_mu(Split sp, const State* __restr
                                                   const double* __restrict__ PS)
 {
     __shared__ double lds[kWaves * 1];
-    State st = *in;
-    if (!st.done) {
-        double t[1];
-        reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);
-        step_hs_mu(st, t[0]);
-    }
-    if (threadIdx.x == 0) *out = st;
+    State st = load_state(in);
+    double t[1];
+    reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
+    if (!st.done) step_hs_mu(st, t[0]);
+    if (threadIdx.x == 0) store_state(out, st);
 }
 
 template <class K, class... Args>

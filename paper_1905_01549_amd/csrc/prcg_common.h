@@ -62,8 +62,11 @@ struct alignas(128) State {
     int32_t last;        // 1 when nu' <= 0 made the next iteration the final one
     int32_t maxit;
     int32_t zero_x;      // b = 0: the returned x is 0
-    int32_t pad[2];
+    int32_t spare0, spare1;
+    double spare2;  // no padding: every byte is a scalar field, so copies of
+                    // the state stay in registers
 };
+static_assert(sizeof(State) == 128, "State fills its 128-byte alignment");
 
 // SELL-64 matrix: rows are cut into slices of 64 (one wavefront, one row
 // per lane); slice s stores its slots column-major, slot j of row 64 s + l

@@ -71,25 +71,23 @@ __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     for (int j0 = 0; j0 < J && j0 * kBlock < G; j0 += PIECE) {
-        // unconditional loads (index clamped to a valid partial, G >= 1) and
-        // a select, so that every load of the piece is in flight at once
+        // unconditional loads (index clamped to a valid partial, G >= 1),
+        // then a select, so that every load of the piece is in flight at once
         double buf[NV][PIECE];
 #pragma unroll
         for (int j = 0; j < PIECE; ++j) {
             const int g = t + kBlock * (j0 + j);
             const int gc = g < G ? g : G - 1;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                const double pv = P[i][gc];
-                buf[i][j] = g < G ? pv : 0.0;
-            }
+            for (int i = 0; i < NV; ++i) buf[i][j] = P[i][gc];
         }
-        // keep the scheduler from starting the sums before the last load
+        // keep the scheduler from starting the selects and sums before the
+        // last load
         if (ALL) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
 #pragma unroll
-            for (int j = 0; j < PIECE; ++j) acc[i] += buf[i][j];
+            for (int j = 0; j < PIECE; ++j) acc[i] += t + kBlock * (j0 + j) < G ? buf[i][j] : 0.0;
         }
     }
     block_sum<NV>(acc, lds);
@@ -382,6 +380,55 @@ __device__ __forceinline__ void rows_of_group(const SellView& S, const CsrView& 
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Field-by-field copies of the solver state between memory and registers
+// (a whole-struct copy can leave part of the struct in a per-thread memory
+// array instead of registers).
+__device__ __forceinline__ State load_state(const State* __restrict__ p)
+{
+    State s;
+    s.alpha = p->alpha;
+    s.beta = p->beta;
+    s.nu = p->nu;
+    s.mu = p->mu;
+    s.sigma = p->sigma;
+    s.gamma = p->gamma;
+    s.rr = p->rr;
+    s.nup = p->nup;
+    s.bnorm = p->bnorm;
+    s.tol = p->tol;
+    s.relres_true = p->relres_true;
+    s.k = p->k;
+    s.done = p->done;
+    s.status = p->status;
+    s.last = p->last;
+    s.maxit = p->maxit;
+    s.zero_x = p->zero_x;
+    s.spare0 = s.spare1 = 0;
+    s.spare2 = 0.0;
+    return s;
+}
+
+__device__ __forceinline__ void store_state(State* __restrict__ p, const State& s)
+{
+    p->alpha = s.alpha;
+    p->beta = s.beta;
+    p->nu = s.nu;
+    p->mu = s.mu;
+    p->sigma = s.sigma;
+    p->gamma = s.gamma;
+    p->rr = s.rr;
+    p->nup = s.nup;
+    p->bnorm = s.bnorm;
+    p->tol = s.tol;
+    p->relres_true = s.relres_true;
+    p->k = s.k;
+    p->done = s.done;
+    p->status = s.status;
+    p->last = s.last;
+    p->maxit = s.maxit;
+    p->zero_x = s.zero_x;
+}
 
 // The scalar step after the reduction of iteration k of a one-reduction
 // variant (PR, M, pipe-PR, pipe-M): record ||r_k||, test convergence and
