@@ -34,6 +34,7 @@ VARIANTS = {
     "pr_norecompute": 6,
     "pipe_pr_nowrecompute": 7,
     "cg": 8,
+    "pr_unsimplified": 9,
 }
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem"}
 

@@ -16,7 +16,10 @@
  *   - GV-CG      (Appendix D, Ghysels-Vanroose pipelined CG),
  *   - CG-CG      (Appendix D, Chronopoulos-Gear CG),
  *   - two ablations from Section 2: PR-CG without the recompute of nu
- *     (eq. nuk_norecomp) and pipe-PR-CG without the recompute of w.
+ *     (eq. nuk_norecomp) and pipe-PR-CG without the recompute of w,
+ *   - PR-CG with the unsimplified four-term prediction of eq. nuk, which
+ *     keeps <s~, r> as an inner product of its own instead of taking it
+ *     equal to <r~, s> (Appendix C).
  *
  * Arithmetic model (Section 3, eq. fp): every + - * / is rounded separately
  * (built with -ffp-contract=off -fno-fast-math).  A sparse product sums each
@@ -67,7 +70,8 @@ enum {
     ORC_GV = 5,
     ORC_PR_NO_RECOMPUTE = 6,      /* nu'_k from nu'_{k-1}; nu never recomputed */
     ORC_PIPE_PR_NO_W_RECOMPUTE = 7, /* w kept as the predicted w'_k           */
-    ORC_CG = 8                      /* CG-CG (Chronopoulos-Gear, Appendix D)   */
+    ORC_CG = 8,                     /* CG-CG (Chronopoulos-Gear, Appendix D)   */
+    ORC_PR_UNSIMPLIFIED = 9         /* PR-CG predicting nu' with eq. nuk       */
 };
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
@@ -340,7 +344,9 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
     double* ut = pre ? C->W.ut : C->W.u;
     orc_diag* dg = C->dg;
 
-    const int is_pr = variant == ORC_PR || variant == ORC_M || variant == ORC_PR_NO_RECOMPUTE;
+    const int is_pr = variant == ORC_PR || variant == ORC_M || variant == ORC_PR_NO_RECOMPUTE ||
+                      variant == ORC_PR_UNSIMPLIFIED;
+    const int unsimplified = variant == ORC_PR_UNSIMPLIFIED;
     const int is_pipe = variant == ORC_PIPE_PR || variant == ORC_PIPE_M || variant == ORC_PIPE_PR_NO_W_RECOMPUTE;
     const int is_gv = variant == ORC_GV;
     const int is_cg = variant == ORC_CG;
@@ -357,6 +363,7 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
     if (pre) orc_prec(n, dinv, s, st);                         /* s~0 = M^-1 s0        */
     double sigma = orc_dot(n, rt, s);                          /* sigma0 = <r~0, s0>   */
     double gamma = orc_dot(n, st, s);                          /* gamma0 = <s~0, s0>   */
+    double delta = unsimplified ? orc_dot(n, st, r) : 0.0;     /* delta0 = <s~0, r0>   */
     double eta = 0.0;
     if (is_pipe || is_gv) {
         memcpy(w, s, (size_t)n * sizeof(double));             /* w0 = A r~0 = A p0 = s0 */
@@ -389,6 +396,8 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
                 nup = nup - 2.0 * alpha * sigma + alpha * alpha * gamma;  /* eq. nuk_norecomp   */
             else if (meurant)
                 nup = -nu + alpha * alpha * gamma;                        /* M-CG form           */
+            else if (unsimplified)
+                nup = nu - alpha * (sigma + delta) + alpha * alpha * gamma; /* eq. nuk            */
             else
                 nup = nu - 2.0 * alpha * sigma + alpha * alpha * gamma;   /* eq. nuk_simplified  */
             if (!orc_finite(nup) || !(nup > 0.0)) {
@@ -414,6 +423,7 @@ static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
             mu = orc_dot(n, p, s);                             /* mu_k    = <p_k, s_k>         */
             sigma = orc_dot(n, rt, s);                         /* sigma_k = <r~_k, s_k>        */
             gamma = orc_dot(n, st, s);                         /* gamma_k = <s~_k, s_k>        */
+            if (unsimplified) delta = orc_dot(n, st, r);       /* delta_k = <s~_k, r_k>        */
             if (variant == ORC_PR_NO_RECOMPUTE) {
                 nu = nup;                                      /* nu_k is never recomputed     */
                 rr = orc_dot(n, r, r);
@@ -495,7 +505,7 @@ int orc_solve(int variant, int64_t n, const int32_t* row_ptr, const int32_t* col
 {
     if (n < 1 || !row_ptr || !col || !val || !b || !x || !iters_out || !(tol >= 0.0) || maxit < 0)
         return ORC_EINVAL;
-    if (variant < ORC_HS || variant > ORC_CG) return ORC_EINVAL;
+    if (variant < ORC_HS || variant > ORC_PR_UNSIMPLIFIED) return ORC_EINVAL;
     *iters_out = 0;
 
     double bnorm = sqrt(orc_dot(n, b, b));
