@@ -85,10 +85,12 @@ def cpu_model() -> str:
 
 
 def variants_of(kern: str):
-    """Variants timed under a kernel structure (GV-CG and CG-CG have one structure)."""
+    """Variants timed under a kernel structure (GV-CG, CG-CG and PR-CG with eq. nuk have one)."""
     if kern == "textbook":
         return ("hs",)
-    return ("hs", "pr", "pipe_pr", "gv", "cg") if kern in ("auto", "two_pass") else ("hs", "pr", "pipe_pr")
+    if kern in ("auto", "two_pass"):
+        return ("hs", "pr", "pipe_pr", "gv", "cg", "pr_unsimplified")
+    return ("hs", "pr", "pipe_pr")
 
 
 def nu_split(M) -> bool:

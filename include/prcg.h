@@ -67,6 +67,11 @@ typedef struct prcg_batch_s* prcg_batch;
  *   PRCG_CG      CG-CG (Appendix D), the Chronopoulos-Gear variant: w = A r~
  *                each iteration, nu_k and eta_k = <r~_k, w_k> in one
  *                reduction, mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k.
+ *   PRCG_PR_UNSIMPLIFIED  PR-CG predicting nu'_{k+1} with the four terms of
+ *                eq. nuk: delta_k = <s~_k, r_k> joins the reduction instead
+ *                of being taken equal to sigma_k = <r~_k, s_k> (Appendix C
+ *                discusses when the two differ).  Without a preconditioner
+ *                it computes exactly what PRCG_PR does; for study.
  * The batched solver runs the first five. */
 typedef enum {
     PRCG_HS = 0,
@@ -77,7 +82,8 @@ typedef enum {
     PRCG_GV = 5,
     PRCG_PR_NORECOMPUTE = 6,
     PRCG_PIPE_PR_NOWRECOMPUTE = 7,
-    PRCG_CG = 8
+    PRCG_CG = 8,
+    PRCG_PR_UNSIMPLIFIED = 9
 } prcg_variant;
 
 /* Preconditioners: none (M = I) or Jacobi (M^{-1} = diag(A)^{-1}). */

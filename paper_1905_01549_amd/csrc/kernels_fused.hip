@@ -321,7 +321,7 @@ hipError_t launch_fused_kernel(int variant, int pre, int j, int it, int& cur, co
         return hipGetLastError();
     };
     hipError_t e = hipSuccess;
-    if (variant == kPR || variant == kM || variant == kPRNoRecompute) {
+    if (is_pr_family(variant)) {
         e = pre ? go(k_pr_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
                      Pq[1 - q], form, f, q)
                 : go(k_pr_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],

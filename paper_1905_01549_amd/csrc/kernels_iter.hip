@@ -85,15 +85,18 @@ __global__ __launch_bounds__(kBlock) void k_init_r(SellView S, CsrView C, Split 
 }
 
 // s0 = A p0 (s~0 = M^{-1} s0 stored when it evolves by recurrence);
-// partials of mu0, sigma0, gamma0 (to PS) and nu0, <r0, r0> (to PN).
+// partials of mu0, sigma0, gamma0 (to PS) and nu0, <r0, r0> (to PN), and,
+// when PD is given (PR-CG with eq. nuk), of delta0 = <s~0, r0> (to PD).
 template <int LANES, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split sp, Vecs v, int store_st,
-                                                   double* __restrict__ PS, double* __restrict__ PN)
+                                                   double* __restrict__ PS, double* __restrict__ PN,
+                                                   double* __restrict__ PD)
 {
     __shared__ double lds[kWaves * 5];
     int64_t g0, g1;
     chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double dacc[1] = {0.0};
     for (int64_t g = g0; g < g1; ++g) {
         rows_of_group<LANES, 1>(S, C, g, v.p, nullptr, [&](int64_t i, double si, double) {
             v.s[i] = si;
@@ -107,9 +110,11 @@ __global__ __launch_bounds__(kBlock) void k_init_s(SellView S, CsrView C, Split 
             acc[2] = fma(sti, si, acc[2]);     // gamma0 = <s~0, s0>
             acc[3] = fma(rti, ri, acc[3]);     // nu0    = <r~0, r0>
             acc[4] = fma(ri, ri, acc[4]);      // <r0, r0>
+            dacc[0] = fma(sti, ri, dacc[0]);   // delta0 = <s~0, r0>
         });
     }
     write_partials_at<5, 3>(acc, PS, PN, sp.Gs, blockIdx.x, lds);
+    if (PD) write_partials<1>(dacc, PD, sp.Gs, blockIdx.x, lds);
 }
 
 // pipe-PR-CG and GV-CG: w0 = A r~0 = A p0 = s0 (copied) and u0 = A s~0; the
@@ -146,14 +151,16 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
                                                         const double* __restrict__ PS, const double* __restrict__ PN,
-                                                        State* __restrict__ out, double* __restrict__ hist, double tol,
-                                                        int maxit)
+                                                        const double* __restrict__ PD, State* __restrict__ out,
+                                                        double* __restrict__ hist, double tol, int maxit)
 {
     __shared__ double lds[kWaves * 5];
     double bb[1];
     reduce_partials<1, true>(PB, sp.G, sp.Gs, bb, lds);
     double t[5];
     reduce_partials_at<5, 3, true>(PS, PN, sp.G, sp.Gs, t, lds);
+    double dd[1] = {t[1]};  // delta0 = sigma0 without a preconditioner
+    if (PD) reduce_partials<1, true>(PD, sp.G, sp.Gs, dd, lds);
     State st = {};
     st.bnorm = sqrt(bb[0]);
     st.tol = tol;
@@ -174,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, 
     } else if (variant == kGV || variant == kCG) {
         step_gv_first(st, t, PRE, hist, w);
     } else if (step0) {
-        step_one_reduction(st, t, PRE, nu_form(variant), hist, w);
+        step_one_reduction(st, t, PRE, nu_form(variant), hist, w, dd[0]);
     }
     // otherwise the first iteration kernel performs the step for k = 0
     if (w) store_state(out, st);
@@ -197,11 +204,13 @@ __device__ __forceinline__ void row_range(const Split& sp, int64_t g0, int64_t g
 // NUDOT (Jacobi, REDUCE = false): this kernel also writes the partials of
 // nu_{k+1} = <r~, r> and <r, r> of the rows it has just updated to PN, so
 // the product kernel need not read r again.
+// PD (nullable): the partials of delta_k = <s~_k, r_k> (eq. nuk with a
+// preconditioner), reduced together with the others when REDUCE.
 template <bool PRE, bool REDUCE, bool NUDOT>
 __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, double* __restrict__ PN,
-                                                      int form, Vecs v)
+                                                      const double* __restrict__ PD, int form, Vecs v)
 {
     static_assert(!(REDUCE && NUDOT), "PN is read by every workgroup when REDUCE");
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
@@ -214,7 +223,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
         }
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
-        step_one_reduction(st, t, PRE, form, hist, writer_thread());
+        double dd[1] = {t[1]};
+        if (PD) reduce_partials<1>(PD, sp.G, sp.Gs, dd, lds);
+        step_one_reduction(st, t, PRE, form, hist, writer_thread(), dd[0]);
         if (writer_thread()) store_state(out, st);
     }
     if (st.done) return;
@@ -277,7 +288,7 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, const double* __restrict__ PN,
-                                                      int form)
+                                                      const double* __restrict__ PD, int form)
 {
     __shared__ double lds[kWaves * 5];
     // the partials are read whether or not the solve has ended (the loads
@@ -285,7 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __
     State st = load_state(in);
     double t[5];
     reduce_partials_at<5, 3, true>(PS, PN, sp.G, sp.Gs, t, lds);
-    if (!st.done) step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
+    double dd[1] = {t[1]};  // delta = sigma without a preconditioner
+    if (PD) reduce_partials<1, true>(PD, sp.G, sp.Gs, dd, lds);
+    if (!st.done) step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0, dd[0]);
     if (threadIdx.x == 0) store_state(out, st);
 }
 
@@ -317,15 +330,17 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* 
 // s_k = A p_k, s~_k = M^{-1} s_k, and the inner products of Alg. 2
 // mu = <p, s>, sigma = <r~, s>, gamma = <s~, s> (to PS) and, with NUDOT,
 // nu = <r~, r> (+ <r, r>) (to PN; otherwise the update kernel wrote them).
+// DELTA (eq. nuk with a preconditioner): also delta = <s~, r> (to PD).
 // LAST: the last workgroup also runs stage 2 and the scalar step, advancing
 // the state from `in` to `out`.
-template <int LANES, bool PRE, bool LAST, bool NUDOT>
+template <int LANES, bool PRE, bool LAST, bool NUDOT, bool DELTA = false>
 __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ hist,
-                                                    double* __restrict__ PS, double* __restrict__ PN, int form,
-                                                    int* ticket, Vecs v)
+                                                    double* __restrict__ PS, double* __restrict__ PN,
+                                                    double* __restrict__ PD, int form, int* ticket, Vecs v)
 {
     static_assert(PRE || NUDOT, "without a preconditioner nu = <r, r> is formed here");
+    static_assert(PRE || !DELTA, "without a preconditioner delta = sigma");
     constexpr int NV = NUDOT ? 5 : 3;
     __shared__ double lds[kWaves * 5];
     if (in->done) {
@@ -337,6 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    double dacc[1] = {0.0};
     for (int64_t g = g0; g < g1; ++g) {
         rows_of_group<LANES, 1>(S, C, g, v.p, nullptr, [&](int64_t i, double si, double) {
             v.s[i] = si;
@@ -345,19 +361,25 @@ __global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split
             acc[0] = fma(v.p[i], si, acc[0]);
             acc[1] = fma(rti, si, acc[1]);
             acc[2] = fma(sti, si, acc[2]);
-            if constexpr (NUDOT) {
+            if constexpr (NUDOT || DELTA) {
                 const double ri = PRE ? v.r[i] : rti;
-                acc[3] = fma(rti, ri, acc[3]);
-                if (PRE) acc[4] = fma(ri, ri, acc[4]);
+                if constexpr (NUDOT) {
+                    acc[3] = fma(rti, ri, acc[3]);
+                    if (PRE) acc[4] = fma(ri, ri, acc[4]);
+                }
+                if constexpr (DELTA) dacc[0] = fma(sti, ri, dacc[0]);
             }
         });
     }
     write_partials_at<NV, 3>(acc, PS, PN, sp.Gs, blockIdx.x, lds);
+    if (DELTA) write_partials<1>(dacc, PD, sp.Gs, blockIdx.x, lds);
     if (LAST && take_last_ticket(ticket, sp.G)) {
         State st = load_state(in);
         double t[5];
         reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
-        step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0);
+        double dd[1] = {t[1]};
+        if (DELTA) reduce_partials<1>(PD, sp.G, sp.Gs, dd, lds);
+        step_one_reduction(st, t, PRE, form, hist, threadIdx.x == 0, dd[0]);
         if (threadIdx.x == 0) store_state(out, st);
     }
 }
@@ -876,9 +898,12 @@ CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullpt
 // five inner products, and PN is the tail of PS.
 bool nu_in_update(int variant, int pre, const Split& sp)
 {
-    const bool pr = variant == kPR || variant == kM || variant == kPRNoRecompute;
-    return pre && pr && !uses_fused(variant, sp) && (stage2_of(sp, kPR) || sp.lastwg);
+    return pre && is_pr_family(variant) && !uses_fused(variant, sp) && (stage2_of(sp, kPR) || sp.lastwg);
 }
+
+// The partials of delta = <s~, r> (PR-CG with eq. nuk and a preconditioner;
+// without one delta = sigma and no partials are formed).
+double* pd_of(int variant, int pre, const Bufs& B) { return variant == kPRUnsimplified && pre ? B.PD : nullptr; }
 
 double* pn_of(int variant, int pre, const Split& sp, const Bufs& B)
 {
@@ -902,7 +927,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
             hipLaunchKernelGGL((k_init_r<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
                                S, C, sp, b, x0, v, store_rt, B.PB);
             hipLaunchKernelGGL((k_init_s<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0, st,
-                               S, C, sp, v, store_st, B.PS, pn_of(variant, pre, sp, B));
+                               S, C, sp, v, store_st, B.PS, pn_of(variant, pre, sp, B), pd_of(variant, pre, B));
             if (pipe || gv)
                 hipLaunchKernelGGL((k_init_u<decltype(L)::value, decltype(P)::value>), dim3(sp.G), dim3(kBlock), 0,
                                    st, S, C, sp, v, gv);
@@ -915,7 +940,8 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
         const bool pipe2 = is_pipe(variant) && !uses_fused(variant, sp);
         const int step0 = variant == kHS ? (sp.lastwg ? 2 : 1) : (pipe2 || sp.lastwg ? 1 : 0);
         hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
-                           B.PB, B.PS, pn_of(variant, pre, sp, B), B.S[0], B.hist, tol, (int)maxit);
+                           B.PB, B.PS, pn_of(variant, pre, sp, B), (const double*)pd_of(variant, pre, B), B.S[0],
+                           B.hist, tol, (int)maxit);
         return hipGetLastError();
     });
 }
@@ -949,6 +975,7 @@ const char* iter_kernel_name(int variant, const Split& sp, int j)
     case kPR:
     case kM:
     case kPRNoRecompute:
+    case kPRUnsimplified:
         if (stage2_of(sp, kPR)) return j == 0 ? "k_finish_one" : (j == 1 ? "k_pr_update" : "k_pr_spmv");
         return j == 0 ? "k_pr_update" : "k_pr_spmv";
     default:
@@ -995,33 +1022,46 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 break;
             case kPR:
             case kM:
-            case kPRNoRecompute: {
+            case kPRNoRecompute:
+            case kPRUnsimplified: {
                 double* PN = pn_of(variant, pre, sp, B);
+                double* PD = pd_of(variant, pre, B);
                 const bool nu_up = nu_in_update(variant, pre, sp);
                 // the update kernel without a reduction, forming nu when nu_up
                 auto update = [&]() {
                     if constexpr (PP) {
                         if (nu_up) {
                             launch(k_pr_update<PP, false, true>, grid, block, st, ev, sp, (const State*)B.S[cur],
-                                   B.S[nxt], B.hist, (const double*)B.PS, PN, form, v);
+                                   B.S[nxt], B.hist, (const double*)B.PS, PN, (const double*)PD, form, v);
                             return;
                         }
                     }
                     launch(k_pr_update<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, PN, form, v);
+                           B.hist, (const double*)B.PS, PN, (const double*)PD, form, v);
                 };
-                // the product kernel (LAST: with the reduction in its last workgroup)
+                // the product kernel (LAST: with the reduction in its last
+                // workgroup; with delta's partials when PD)
                 auto product = [&](auto last) {
                     constexpr bool LA = decltype(last)::value;
                     if constexpr (PP) {
+                        if (nu_up && PD) {
+                            launch(k_pr_spmv<LL, PP, LA, false, true>, grid, block, st, ev, S, C, sp,
+                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, PD, form, tk, v);
+                            return;
+                        }
+                        if (PD) {
+                            launch(k_pr_spmv<LL, PP, LA, true, true>, grid, block, st, ev, S, C, sp,
+                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, PD, form, tk, v);
+                            return;
+                        }
                         if (nu_up) {
                             launch(k_pr_spmv<LL, PP, LA, false>, grid, block, st, ev, S, C, sp,
-                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, form, tk, v);
+                                   (const State*)B.S[cur], B.S[nxt], B.hist, B.PS, PN, PD, form, tk, v);
                             return;
                         }
                     }
                     launch(k_pr_spmv<LL, PP, LA, true>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
-                           B.S[nxt], B.hist, B.PS, PN, form, tk, v);
+                           B.S[nxt], B.hist, B.PS, PN, PD, form, tk, v);
                 };
                 if (sp.lastwg) {
                     if (j == 0) {
@@ -1032,13 +1072,13 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                     }
                 } else if (s2 && j == 0) {
                     launch(k_finish_one<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
-                           (const double*)B.PS, (const double*)PN, form);
+                           (const double*)B.PS, (const double*)PN, (const double*)PD, form);
                     cur = nxt;
                 } else if (s2 && j == 1) {
                     update();
                 } else if (j == 0) {
                     launch(k_pr_update<PP, true, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, PN, form, v);
+                           B.hist, (const double*)B.PS, PN, (const double*)PD, form, v);
                     cur = nxt;
                 } else {
                     product(std::false_type{});
@@ -1067,7 +1107,8 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                                B.S[nxt], B.hist, (const double*)B.PS, form, v);
                     } else if (s2) {
                         launch(k_finish_one<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                               B.hist, (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs), form);
+                               B.hist, (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs),
+                               (const double*)nullptr, form);
                         cur = nxt;
                     } else {
                         launch(k_pipe_spmv<LL, PP, true, NW>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],

@@ -89,7 +89,7 @@ struct prcg_matrix_s {
     State* S = nullptr;      // two copies
     double* hist = nullptr;
     int64_t hist_cap = 0;
-    double* partials = nullptr;  // PS | PU | PB | PS2 | PN
+    double* partials = nullptr;  // PS | PU | PB | PS2 | PN | PD
     int32_t* dflags = nullptr;   // [0..3] setup flags, [4] reduction ticket
     State* hstate = nullptr;     // pinned, two slots
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -149,6 +149,7 @@ struct prcg_matrix_s {
         B.PB = partials + (size_t)(kMaxDots + 2) * kMaxGrid;
         B.PS2 = partials + (size_t)(kMaxDots + 3) * kMaxGrid;
         B.PN = partials + (size_t)(2 * kMaxDots + 3) * kMaxGrid;
+        B.PD = partials + (size_t)(2 * kMaxDots + 5) * kMaxGrid;
         B.ticket = dflags + 4;
         return B;
     }
@@ -402,7 +403,7 @@ prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double*
 
 prcg_status check_variant(int v)
 {
-    if (v < PRCG_HS || v > PRCG_CG) return fail(PRCG_EINVAL, "unknown variant");
+    if (v < PRCG_HS || v > PRCG_PR_UNSIMPLIFIED) return fail(PRCG_EINVAL, "unknown variant");
     return PRCG_OK;
 }
 
@@ -564,7 +565,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     HTRY(hipMalloc(&A->S, sizeof(State) * 2));
     HTRY(hipMemsetAsync(A->S, 0, sizeof(State) * 2, A->stream));
     // partials sized for the largest grid, so the grid can change later
-    HTRY(hipMalloc(&A->partials, sizeof(double) * (2 * kMaxDots + 5) * (size_t)kMaxGrid));
+    HTRY(hipMalloc(&A->partials, sizeof(double) * (2 * kMaxDots + 6) * (size_t)kMaxGrid));
     HTRY(hipStreamSynchronize(A->stream));
     TRY(ensure_hist(A, 1024));
     *out = A;

@@ -23,9 +23,10 @@ enum Variant {
     kGV = 5,
     kPRNoRecompute = 6,
     kPipeNoWRecompute = 7,
-    kCG = 8
+    kCG = 8,
+    kPRUnsimplified = 9
 };
-constexpr int kNumVariants = 9;
+constexpr int kNumVariants = 10;
 
 __host__ __device__ inline bool is_pipe(int variant)
 {
@@ -34,12 +35,20 @@ __host__ __device__ inline bool is_pipe(int variant)
 
 // How a one-reduction variant forms nu and nu' (step_one_reduction):
 // 0 PR (eq. nuk_simplified), 1 Meurant (nu' = -nu + alpha^2 gamma),
-// 2 PR without the recompute (nu_k := nu'_k, eq. nuk_norecomp).
-enum NuForm { kFormPR = 0, kFormMeurant = 1, kFormNoRecompute = 2 };
+// 2 PR without the recompute (nu_k := nu'_k, eq. nuk_norecomp),
+// 3 PR with the four-term eq. nuk (delta = <s~, r> of its own).
+enum NuForm { kFormPR = 0, kFormMeurant = 1, kFormNoRecompute = 2, kFormUnsimplified = 3 };
 __host__ __device__ inline int nu_form(int variant)
 {
     if (variant == kM || variant == kPipeM) return kFormMeurant;
+    if (variant == kPRUnsimplified) return kFormUnsimplified;
     return variant == kPRNoRecompute ? kFormNoRecompute : kFormPR;
+}
+
+// The variants that run PR-CG's kernels (Alg. 2 with one nu' form or another).
+__host__ __device__ inline bool is_pr_family(int variant)
+{
+    return variant == kPR || variant == kM || variant == kPRNoRecompute || variant == kPRUnsimplified;
 }
 enum Status { kOK = 0, kNotConverged = 1, kBreakdown = 2 };
 
@@ -120,11 +129,12 @@ inline bool stage2_of(const Split& sp, int variant)
     return (sp.stage2 & bit) != 0;
 }
 
-// The fused structure covers HS, PR, pipe-PR and their forms; GV-CG, CG-CG
-// and the no-w-recompute ablation always run two-pass.
+// The fused structure covers HS, PR, pipe-PR and their forms; GV-CG, CG-CG,
+// the no-w-recompute ablation and PR-CG with eq. nuk always run two-pass.
 inline bool uses_fused(int variant, const Split& sp)
 {
-    return sp.fused && variant != kGV && variant != kPipeNoWRecompute && variant != kCG;
+    return sp.fused && variant != kGV && variant != kPipeNoWRecompute && variant != kCG &&
+           variant != kPRUnsimplified;
 }
 
 // ---- setup kernels (kernels_setup.hip) ----
@@ -168,6 +178,7 @@ struct Bufs {
     double* hist;
     double* PS;   // [mu, sigma, gamma, nu, rr] partials
     double* PN;   // [nu, rr] partials when PR's update kernel produces them
+    double* PD;   // [delta] partials (PR-CG with eq. nuk and a preconditioner)
     double* PU;   // [nu, rr] partials (HS)
     double* PB;   // [bb] or [tt] partials
     double* PS2;  // second copy of PS (fused kernels alternate between the two)

@@ -436,9 +436,13 @@ __device__ __forceinline__ void store_state(State* __restrict__ p, const State& 
 // eq. nuk_simplified; Meurant: nu' = -nu + alpha^2 gamma).  form =
 // kFormNoRecompute is the ablation of Section 2 that keeps the predicted
 // nu'_k as nu_k (eq. nuk_norecomp; nu'_0 := nu_0), so the recomputed inner
-// product serves only as ||r_k||^2 when M = I.
+// product serves only as ||r_k||^2 when M = I.  form = kFormUnsimplified
+// predicts with the four terms of eq. nuk, delta = <s~_k, r_k> (the caller
+// passes sigma when M = I, where the two sums are the same); the middle
+// terms are grouped as alpha (sigma + delta), which with delta = sigma
+// rounds exactly like 2 alpha sigma.
 __device__ inline void step_one_reduction(State& st, const double (&t)[5], bool pre, int form, double* hist,
-                                          bool writer)
+                                          bool writer, double delta = 0.0)
 {
     const double mu = t[0], sigma = t[1], gamma = t[2];
     const double nu = (form == kFormNoRecompute && st.k >= 0) ? st.nup : t[3];
@@ -468,8 +472,9 @@ __device__ inline void step_one_reduction(State& st, const double (&t)[5], bool 
         return;
     }
     const double alpha = nu / mu;
-    const double nup = form == kFormMeurant ? -nu + alpha * alpha * gamma
-                                            : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
+    const double nup = form == kFormMeurant        ? -nu + alpha * alpha * gamma
+                       : form == kFormUnsimplified ? nu - alpha * (sigma + delta) + alpha * alpha * gamma
+                                                   : nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
     st.alpha = alpha;
     st.nup = nup;
     if (!finite(nup) || !(nup > 0.0)) {

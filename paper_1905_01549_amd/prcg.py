@@ -20,10 +20,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprcg.so")
 
 PRCG_HS, PRCG_PR, PRCG_PIPE_PR, PRCG_M, PRCG_PIPE_M, PRCG_GV = 0, 1, 2, 3, 4, 5
-PRCG_PR_NORECOMPUTE, PRCG_PIPE_PR_NOWRECOMPUTE, PRCG_CG = 6, 7, 8
+PRCG_PR_NORECOMPUTE, PRCG_PIPE_PR_NOWRECOMPUTE, PRCG_CG, PRCG_PR_UNSIMPLIFIED = 6, 7, 8, 9
 VARIANTS = {"hs": PRCG_HS, "pr": PRCG_PR, "pipe_pr": PRCG_PIPE_PR, "m": PRCG_M, "pipe_m": PRCG_PIPE_M,
             "gv": PRCG_GV, "pr_norecompute": PRCG_PR_NORECOMPUTE, "pipe_pr_nowrecompute": PRCG_PIPE_PR_NOWRECOMPUTE,
-            "cg": PRCG_CG}
+            "cg": PRCG_CG, "pr_unsimplified": PRCG_PR_UNSIMPLIFIED}
 PRECONDS = {"none": 0, "jacobi": 1}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem", -3: "edevice"}
 

@@ -54,6 +54,9 @@ for _tab in (KERNEL_WORDS_FUSED,):
 # reads/writes w~' with Jacobi); the product reads only s~ of the pair
 KERNEL_WORDS[("pipe_pr_nowrecompute", False)] = [("k_pipe_update", 6, 5, False), ("k_pipe_spmv", 2, 1, True)]
 KERNEL_WORDS[("pipe_pr_nowrecompute", True)] = [("k_pipe_update", 10, 8, False), ("k_pipe_spmv", 2, 1, True)]
+# PR-CG with eq. nuk: with Jacobi the product also reads r for delta = <s~, r>
+KERNEL_WORDS[("pr_unsimplified", False)] = KERNEL_WORDS[("pr", False)]
+KERNEL_WORDS[("pr_unsimplified", True)] = KERNEL_WORDS[("pr", True)]
 KERNEL_WORDS[("pr_norecompute", False)] = KERNEL_WORDS[("pr", False)]
 KERNEL_WORDS[("pr_norecompute", True)] = KERNEL_WORDS[("pr", True)]
 KERNEL_WORDS[("m", False)] = KERNEL_WORDS[("pr", False)]
@@ -71,7 +74,7 @@ def kernel_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int, fused: b
     out = {}
     table = KERNEL_WORDS_TEXTBOOK if textbook else (KERNEL_WORDS_FUSED if fused else KERNEL_WORDS)
     for name, r, w, mat in table[(variant, jacobi)]:
-        if nu_in_update and jacobi and not fused and name == "k_pr_spmv":
+        if nu_in_update and jacobi and not fused and name == "k_pr_spmv" and variant != "pr_unsimplified":
             r -= 1
         out[name] = 8 * n * (r + w) + (matrix_bytes if mat else 0)
     return out

@@ -47,3 +47,19 @@ def test_binding_refuses_missing_library(tmp_path):
             prcg.load_library(str(tmp_path / "nope.so"))
     finally:
         prcg._LIB = saved
+
+
+def header_enum(name):
+    """{constant: value} of a typedef'd enum of include/prcg.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef enum \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    return {k: int(v) for k, v in re.findall(r"(PRCG_[A-Z_]+)\s*=\s*(-?\d+)", body)}
+
+
+def test_binding_constants_match_the_header():
+    from paper_1905_01549_amd import prcg
+    variants = header_enum("prcg_variant")
+    assert sorted(variants.values()) == sorted(prcg.VARIANTS.values())
+    for key, code in prcg.VARIANTS.items():
+        assert variants["PRCG_" + key.upper()] == code, key
+    assert header_enum("prcg_precond") == {"PRCG_PRECOND_" + k.upper(): v for k, v in prcg.PRECONDS.items()}

@@ -159,7 +159,7 @@ def test_batched_rejects_the_comparator_and_ablations(prcg):
     A, offs = P.block_diag([P.poisson2d(8), P.poisson2d(9)])
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
-    for v in ("gv", "cg", "pr_norecompute", "pipe_pr_nowrecompute"):
+    for v in ("gv", "cg", "pr_norecompute", "pipe_pr_nowrecompute", "pr_unsimplified"):
         with pytest.raises(prcg.PrcgError):
             B.solve(np.ones(A.n), v, 1e-10, 100)
 

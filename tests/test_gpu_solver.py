@@ -21,7 +21,7 @@ from paper_1905_01549_amd import problems as P
 pytestmark = pytest.mark.gpu
 
 EPS = 2.0 ** -53
-VARIANTS = ["hs", "pr", "pipe_pr", "m", "pipe_m", "cg"]
+VARIANTS = ["hs", "pr", "pipe_pr", "m", "pipe_m", "cg", "pr_unsimplified"]
 
 
 @pytest.fixture(scope="module")
@@ -149,6 +149,29 @@ def test_poisson3d_jacobi_parity(prcg, torch_cuda, variant, kernels):
     A = P.poisson3d(40, 37, 33)  # n = 48,840: several tiles and a ragged tail
     b = P.uniform_vector(A.n, 2)
     check_parity(prcg, A, b, variant, "jacobi", 1e-10, 3000, kernels=kernels)
+
+
+@pytest.mark.parametrize("kernels", ["auto", "two_pass_redundant", "two_pass_stage2", "two_pass_last"])
+def test_unsimplified_nu_with_variable_diagonal(prcg, torch_cuda, kernels):
+    """eq. nuk with a non-constant Jacobi diagonal, where delta = <s~, r>
+    and sigma = <r~, s> differ by rounding (Appendix C): parity with the
+    oracle under every placement of the reduction's second stage."""
+    A = P.varcoef7(24, 5)
+    b = P.uniform_vector(A.n, 5)
+    check_parity(prcg, A, b, "pr_unsimplified", "jacobi", 1e-10, 3000, kernels=kernels)
+
+
+def test_unsimplified_nu_without_preconditioner_is_pr(prcg, torch_cuda):
+    """With M = I, delta = sigma and the prediction alpha (sigma + delta)
+    rounds like 2 alpha sigma: the same kernels give PR-CG's bits."""
+    A = P.poisson3d(24)
+    b = P.uniform_vector(A.n, 4)
+    M = gpu_matrix(prcg, A, "none", "two_pass_stage2")
+    x1, i1 = M.solve(b, "pr", 1e-10, 2000, history=True)
+    x2, i2 = M.solve(b, "pr_unsimplified", 1e-10, 2000, history=True)
+    assert i1.status == i2.status == "ok" and i1.iters == i2.iters
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy()) and np.array_equal(i1.history, i2.history)
+    M.close()
 
 
 @pytest.mark.parametrize("kernels", ["two_pass", "two_pass_redundant", "two_pass_last"])
