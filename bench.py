@@ -25,8 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# kernel structures compared ("auto", the library's default, is "fused" below
-# 64 workgroups and otherwise "two_pass", which places stage 2 by size)
+# kernel structures compared ("auto", the library's default, is "fused" for
+# HS-CG and PR-CG below 2048 workgroups and otherwise "two_pass", which places
+# stage 2 by size)
 STRUCTURES = ("auto", "two_pass", "two_pass_redundant", "two_pass_stage2", "two_pass_last", "fused", "textbook")
 TOL = 1e-10
 MAXIT = 1000
@@ -287,7 +288,6 @@ def main():
     b = torch.as_tensor(pr.b, device="cuda")
     props = M.props
     n = A.n
-    fused = props.kernels == 0  # the structure in use (auto resolves to fused or two-pass)
 
     if args.kernels_only:
         # a plain copy of known size (256 MiB read + 256 MiB written) to
@@ -297,6 +297,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         kt = M.time_kernels(args.variant, 200)
+        fused = any("fused" in name for name, _ in kt)  # the structure the variant runs
         kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
         print(json.dumps({"workload": workload, "variant": args.variant, "launches": 200,
                           "kernels": {k: {"us": ms * 1e3, "bytes": kb.get(k, 0),
@@ -340,9 +341,9 @@ def main():
                 vi = solve(v)
                 torch.cuda.synchronize()
                 best = min(best, time.perf_counter() - t)
-            fz = M.props.kernels == 0
-            it_bytes = traffic.iteration_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook", nu_split(M))
             kt = M.time_kernels(v, 50)
+            fz = any("fused" in name for name, _ in kt)  # the structure this variant ran
+            it_bytes = traffic.iteration_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook", nu_split(M))
             kb = traffic.kernel_bytes(v, True, n, props.matrix_bytes, fz, kern == "textbook", nu_split(M))
             variants[f"{v}/{kern}"] = {
                 "iters": vi.iters,
@@ -358,6 +359,7 @@ def main():
 
     # dominant kernel of the flagship variant: the SpMV + inner-product kernel
     kt = dict(M.time_kernels(args.variant, 200))
+    fused = any("fused" in name for name in kt)  # the structure the variant runs
     kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
     dom = max((k for k in kt if k in kb), key=lambda k: kt[k])
     achieved = kb[dom] / (kt[dom] * 1e-3) / 1e9

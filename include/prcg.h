@@ -130,10 +130,11 @@ typedef struct {
 
 /* Options (prcg_set_option).
  *   PRCG_OPT_KERNELS  kernel structure of an iteration:
- *     PRCG_KERNELS_AUTO (default): FUSED when A is stored as SELL-64 and the
- *       row-parallel kernels have fewer than 64 workgroups (16k rows: the
- *       iteration is latency-bound and one kernel per iteration wins),
- *       TWO_PASS otherwise.  prcg_get_props reports the structure chosen.
+ *     PRCG_KERNELS_AUTO (default): FUSED for HS-CG and the PR-CG forms when
+ *       A is stored as SELL-64 and the row-parallel kernels have fewer than
+ *       2048 workgroups (below 8192 row groups of 256 by the default grid),
+ *       for pipe-PR-CG only below 64 workgroups; TWO_PASS otherwise.
+ *       prcg_get_props reports the structure chosen for HS-CG and PR-CG.
  *     PRCG_KERNELS_FUSED: PR-CG and pipe-PR-CG run one kernel per
  *       iteration, HS-CG two; the sparse product recomputes the new
  *       direction at neighbouring rows from double-buffered vectors, with
@@ -142,8 +143,8 @@ typedef struct {
  *     PRCG_KERNELS_TWO_PASS: an update kernel and a product kernel
  *       per reduction (PR: 2, pipe-PR: 2, HS: 3 kernels per iteration), with
  *       stage 2 of each reduction (the sum of the per-workgroup partials)
- *       placed by size: HS-CG and PR-CG as STAGE2 from 64 workgroups up,
- *       else as REDUNDANT; pipe-PR-CG always as REDUNDANT.
+ *       placed by size: HS-CG and PR-CG as STAGE2 from 2048 workgroups
+ *       up, else as REDUNDANT; pipe-PR-CG always as REDUNDANT.
  *     PRCG_KERNELS_TWO_PASS_REDUNDANT: stage 2 runs redundantly in every
  *       workgroup of the kernel that consumes the totals (pipe-PR-CG: in
  *       workgroup 0 of the product kernel, before its share of the

@@ -265,12 +265,19 @@ constexpr int64_t kBigGroups = 8192;
 //
 // Stage-2 placement of the default two-pass structure.  The redundant form
 // costs every workgroup of the consuming kernel a read of all partials
-// (G^2 reads of the same few cache lines per reduction: 5-15 us on MI355X
-// from 64 workgroups up); a one-workgroup kernel costs one launch (about
-// 4 us).  HS-CG and PR-CG therefore take the separate kernel from 64
-// workgroups up.  pipe-PR-CG reduces in one workgroup of its product kernel
-// before that workgroup's share of the product, which hides the reduction.
-constexpr int kStage2MinGrid = 64;
+// (G^2 reads of the same few cache lines per reduction); a one-workgroup
+// kernel costs one launch and one memory round trip (4-5 us on MI355X).
+// Measured: at 1024 workgroups the redundant form is 1-4 us per reduction
+// faster than the separate kernel, at 4096 it is 8-22 us slower.  HS-CG and
+// PR-CG therefore take the separate kernel from kStage2MinGrid workgroups
+// up.  pipe-PR-CG reduces in one workgroup of its product kernel before
+// that workgroup's share of the product, which hides the reduction.
+// AUTO also picks the fused structure (SELL-64 only) below kStage2MinGrid:
+// at 1024 workgroups it is the fastest for HS-CG and PR-CG on the 262k-,
+// 885k- and 1M-row problems (PR-CG 15.1 / 28.5 / 18.3 us per iteration
+// against 19.1 / 29.8 / 24.1 two-pass), at 4096 it is 1.5x slower.
+constexpr int kStage2MinGrid = 2048;
+constexpr int kPipeFusedMaxGrid = 64;
 Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
 {
     Split sp{};
@@ -284,9 +291,18 @@ Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
     sp.G = (int)std::max<int64_t>(G, 1);
     sp.Gs = (sp.G + 63) / 64 * 64;
     // AUTO: the fused structure for problems of fewer than kStage2MinGrid
-    // workgroups (latency-bound; one kernel per iteration wins), two-pass above
+    // workgroups, two-pass above
     const bool small = sp.G < kStage2MinGrid;
-    sp.fused = lanes == 1 && (kernels_mode == PRCG_KERNELS_FUSED || (kernels_mode == PRCG_KERNELS_AUTO && small)) ? 1 : 0;
+    // (pipe-PR-CG only below kPipeFusedMaxGrid: its two-pass product kernel
+    // already hides the reduction, and its fused form gathers five vectors
+    // per entry; 16.0 against 17.5 us per iteration at 1024 workgroups, but
+    // 8.7 against 9.7 at 16)
+    const bool tiny = sp.G < kPipeFusedMaxGrid;
+    sp.fused = lanes != 1                                               ? 0
+               : kernels_mode == PRCG_KERNELS_FUSED                     ? 3
+               : kernels_mode == PRCG_KERNELS_AUTO && tiny              ? 3
+               : kernels_mode == PRCG_KERNELS_AUTO && small             ? 1
+                                                                         : 0;
     if (kernels_mode == PRCG_KERNELS_TWO_PASS_STAGE2) {
         sp.stage2 = 7;
     } else if (kernels_mode == PRCG_KERNELS_TWO_PASS || kernels_mode == PRCG_KERNELS_TEXTBOOK ||

@@ -118,7 +118,7 @@ struct Split {
                     // the partials reduces them (ticket counter)
                     // (neither: every workgroup of the consuming kernel
                     // reduces them redundantly)
-    int fused;      // 1 = fused kernels (SELL-64 only), 0 = two-pass kernels
+    int fused;      // fused kernels (SELL-64 only): bit 0 HS/PR forms, bit 1 pipe-PR forms; 0 = two-pass
     int textbook;   // 1 = HS-CG as one kernel per algorithm line
     int textbook_pre;  // preconditioned (the textbook kernel list depends on it)
 };
@@ -131,10 +131,12 @@ inline bool stage2_of(const Split& sp, int variant)
 
 // The fused structure covers HS, PR, pipe-PR and their forms; GV-CG, CG-CG,
 // the no-w-recompute ablation and PR-CG with eq. nuk always run two-pass.
+// sp.fused bit 0: HS-CG and the PR-CG forms fused; bit 1: pipe-PR-CG too.
 inline bool uses_fused(int variant, const Split& sp)
 {
-    return sp.fused && variant != kGV && variant != kPipeNoWRecompute && variant != kCG &&
-           variant != kPRUnsimplified;
+    if (!sp.fused || variant == kGV || variant == kPipeNoWRecompute || variant == kCG || variant == kPRUnsimplified)
+        return false;
+    return is_pipe(variant) ? (sp.fused & 2) != 0 : (sp.fused & 1) != 0;
 }
 
 // ---- setup kernels (kernels_setup.hip) ----

@@ -251,8 +251,8 @@ class Matrix:
         return prcg_get_props(self.handle)
 
     def set_kernels(self, mode: str):
-        """Kernel structure: "auto" (default: "fused" below 64 workgroups,
-        else "two_pass"), "two_pass" (stage-2 placement by size),
+        """Kernel structure: "auto" (default: "fused" for HS-CG and PR-CG
+        below 2048 workgroups, else "two_pass"), "two_pass" (stage-2 placement by size),
         "two_pass_redundant", "two_pass_stage2", "two_pass_last", "fused" or
         "textbook" (HS-CG one kernel per algorithm line)."""
         prcg_set_option(self.handle, OPT_KERNELS, KERNELS[mode])

@@ -432,14 +432,24 @@ def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
 
 
 def test_auto_structure_by_size(prcg, torch_cuda):
-    """The default structure is fused on small SELL-64 problems and two-pass
-    (with stage 2 in its own kernel) on large ones; props report the choice."""
+    """The default structure is fused on SELL-64 problems of up to 1024
+    workgroups (pipe-PR-CG: below 64) and two-pass (with stage 2 in its own
+    kernel) from 2048 workgroups up; vector CSR is always two-pass, reducing
+    in every consuming workgroup below 2048; props report the choice."""
     small = gpu_matrix(prcg, P.poisson2d(64), "none", "auto")
     assert small.props.kernels == prcg.KERNELS["fused"] and small.props.grid < 64
-    big = gpu_matrix(prcg, P.poisson3d(40), "jacobi", "auto")
-    assert big.props.kernels == prcg.KERNELS["two_pass"] and big.props.stage2 == 3
+    assert "k_pipe_fused" in dict(small.time_kernels("pipe_pr", 3))  # below 64 workgroups pipe-PR-CG too
+    mid = gpu_matrix(prcg, P.poisson3d(40), "jacobi", "auto")
+    assert mid.props.kernels == prcg.KERNELS["fused"] and mid.props.grid == 248
+    assert "k_pr_fused" in dict(mid.time_kernels("pr", 3))
+    assert "k_pipe_update" in dict(mid.time_kernels("pipe_pr", 3))  # pipe-PR-CG stays two-pass
+    big = gpu_matrix(prcg, P.poisson3d(81), "jacobi", "auto")
+    big.set_grid(2048)
+    assert big.props.kernels == prcg.KERNELS["two_pass"] and big.props.stage2 == 3 and big.props.grid == 2048
+    big.set_grid(1024)
+    assert big.props.kernels == prcg.KERNELS["fused"]
     csr = prcg.Matrix(*(lambda A: (A.row_ptr, A.col_idx, A.values))(P.arrowhead(5000, 2)), "none")
-    assert csr.props.kernels == prcg.KERNELS["two_pass"]  # vector CSR: no fused structure
+    assert csr.props.kernels == prcg.KERNELS["two_pass"] and csr.props.stage2 == 0  # vector CSR: no fused structure
 
 
 def test_time_kernels_capacity_is_checked(prcg, torch_cuda):
