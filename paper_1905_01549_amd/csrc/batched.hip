@@ -73,29 +73,50 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
     const SellView& A = B.A;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    // the metadata of the next group of slices is loaded while the current
+    // group is multiplied
+    struct Meta {
+        int64_t base[Q], end[Q], row0[Q];
+        int meta[Q], nrows[Q];
+    };
+    auto load_meta = [&](int64_t s0, Meta& m) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t sq = s0 + (int64_t)q * NW;
+            m.base[q] = A.slice_ptr[sq];
+            m.end[q] = A.slice_ptr[sq + 1];
+            m.meta[q] = A.slice_meta[sq];
+            m.row0[q] = B.slice_row0[sq];
+            m.nrows[q] = B.slice_nrows[sq];
+        }
+    };
     int64_t sl = sl0 + w;
+    Meta cur;
+    if (sl + (int64_t)(Q - 1) * NW < sl1) load_meta(sl, cur);
     for (; sl + (int64_t)(Q - 1) * NW < sl1; sl += (int64_t)Q * NW) {
-        int64_t sq[Q], base[Q], row[Q];
-        int width[Q], meta[Q];
+        Meta nxt = cur;
+        const int64_t sn = sl + (int64_t)Q * NW;
+        if (sn + (int64_t)(Q - 1) * NW < sl1) load_meta(sn, nxt);
+        int64_t sq[Q], row[Q];
+        int width[Q];
         bool valid[Q];
         bool group = true;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             sq[q] = sl + (int64_t)q * NW;
-            base[q] = A.slice_ptr[sq[q]];
-            width[q] = (int)((A.slice_ptr[sq[q] + 1] - base[q]) >> 6);
-            meta[q] = A.slice_meta[sq[q]];
-            row[q] = B.slice_row0[sq[q]] + lane;
-            valid[q] = lane < B.slice_nrows[sq[q]];
-            group = group && meta[q] >= 0 && width[q] == width[0];
+            width[q] = (int)((cur.end[q] - cur.base[q]) >> 6);
+            row[q] = cur.row0[q] + lane;
+            valid[q] = lane < cur.nrows[q];
+            group = group && cur.meta[q] >= 0 && width[q] == width[0];
         }
         group = group && width[0] >= 1 && width[0] <= kWMax;
         double y0[Q], y1[Q];
         if (group) {
             const int32_t* off[Q];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) off[q] = A.soff + meta[q];
+            for (int q = 0; q < Q; ++q) off[q] = A.soff + cur.meta[q];
             const int32_t* const(&co)[Q] = off;
+            const int64_t(&base)[Q] = cur.base;
             switch (width[0]) {
             case 1: aligned_group<1, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
             case 2: aligned_group<2, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
@@ -113,6 +134,7 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (valid[q]) f(row[q], y0[q], y1[q]);
+        cur = nxt;
     }
     for (; sl < sl1; sl += NW) {
         const int64_t row = B.slice_row0[sl] + lane;

@@ -54,6 +54,25 @@ def test_batched_matches_oracle(prcg, variant, precond):
     assert nt in (256, 512, 1024) and grid >= 1
 
 
+@pytest.mark.parametrize("config", ["512,2", "1024,1"])
+@pytest.mark.parametrize("variant", ["pr", "pipe_pr", "hs"])
+def test_packed_and_mixed_slices(prcg, variant, config, monkeypatch):
+    """Systems whose slices are packed (explicit columns, rows of different
+    lengths) next to stencil systems (offset-aligned slices, paired in the
+    product), and tiny systems of fewer slices than wavefronts: each system
+    against the oracle."""
+    monkeypatch.setenv("PRCG_BATCH_CONFIG", config)
+    mats = [P.random_spd(700 + 173 * s, 5.0, 20 + s) for s in range(3)]
+    mats += [P.batch_system(s, 64, 3000)[0] for s in range(3)]
+    mats += [P.poisson2d(3), P.random_spd(40, 3.0, 9)]
+    bs = [P.uniform_vector(A.n, 30 + s) for s, A in enumerate(mats)]
+    A, offs = P.block_diag(mats)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    B = prcg.Batch(M, offs)
+    x, iters, status = B.solve(np.concatenate(bs), variant, 1e-10, 5000)
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, variant, "jacobi", 1e-10)
+
+
 @pytest.mark.parametrize("config", ["256,1", "512,2", "1024,1"])
 def test_every_workgroup_size(prcg, config, monkeypatch):
     monkeypatch.setenv("PRCG_BATCH_CONFIG", config)
