@@ -164,9 +164,9 @@ typedef struct {
  *   All two-pass placements add the partials in the same fixed order:
  *   results are bitwise identical across them.
  *   PRCG_OPT_GRID  largest number of workgroups of the row-parallel kernels
- *     (8..4096; the actual count is a multiple of 8), or 0 (the default):
- *     by size, two 256-row groups per workgroup from 8192 groups (2M rows)
- *     up, else at most 1024. */
+ *     (8..8192; the actual count is a multiple of 8), or 0 (the default):
+ *     by size, one 256-row group per workgroup from 8192 groups (2M rows)
+ *     up (at most 8192 workgroups), else at most 1024. */
 typedef enum { PRCG_OPT_KERNELS = 0, PRCG_OPT_GRID = 1 } prcg_option;
 typedef enum {
     PRCG_KERNELS_FUSED = 0,

@@ -149,12 +149,12 @@ __global__ __launch_bounds__(kBlock) void k_init_u(SellView S, CsrView C, Split 
 // product kernel); otherwise the first iteration kernel does.  HS with
 // step0 = 2 also forms alpha_0 from mu_0.
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
+__global__ __launch_bounds__(kStage2Block) void k_init_finish(int variant, int step0, Split sp, const double* __restrict__ PB,
                                                         const double* __restrict__ PS, const double* __restrict__ PN,
                                                         const double* __restrict__ PD, State* __restrict__ out,
                                                         double* __restrict__ hist, double tol, int maxit)
 {
-    __shared__ double lds[kWaves * 5];
+    __shared__ double lds[kStage2Waves * 5];
     double bb[1];
     reduce_partials<1, true>(PB, sp.G, sp.Gs, bb, lds);
     double t[5];
@@ -285,12 +285,12 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
 // one-reduction variant (PR, M, pipe-PR, pipe-M), when neither the consuming
 // kernel nor the producing kernel reduces the partials itself.
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kStage2Block) void k_finish_one(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, const double* __restrict__ PN,
                                                       const double* __restrict__ PD, int form)
 {
-    __shared__ double lds[kWaves * 5];
+    __shared__ double lds[kStage2Waves * 5];
     // the partials are read whether or not the solve has ended (the loads
     // stay in bounds), so their latency overlaps that of the state
     State st = load_state(in);
@@ -303,10 +303,10 @@ __global__ __launch_bounds__(kBlock) void k_finish_one(Split sp, const State* __
 }
 
 // One workgroup: stage 2 of HS-CG's mu_k (alpha_k) or nu_k (tests, beta_k).
-__global__ __launch_bounds__(kBlock) void k_hs_finish_mu(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kStage2Block) void k_hs_finish_mu(Split sp, const State* __restrict__ in,
                                                          State* __restrict__ out, const double* __restrict__ PS)
 {
-    __shared__ double lds[kWaves * 1];
+    __shared__ double lds[kStage2Waves * 1];
     State st = load_state(in);
     double t[1];
     reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
@@ -315,11 +315,11 @@ __global__ __launch_bounds__(kBlock) void k_hs_finish_mu(Split sp, const State* 
 }
 
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_hs_finish_nu(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kStage2Block) void k_hs_finish_nu(Split sp, const State* __restrict__ in,
                                                          State* __restrict__ out, double* __restrict__ hist,
                                                          const double* __restrict__ PU)
 {
-    __shared__ double lds[kWaves * 2];
+    __shared__ double lds[kStage2Waves * 2];
     State st = load_state(in);
     double t[2];
     reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
@@ -679,11 +679,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(SellView S, CsrView C, Split
 // beta_k, mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k, the tests and alpha_k
 // (the scalar step GV-CG shares).
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_cg_finish(Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kStage2Block) void k_cg_finish(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, const double* __restrict__ PN)
 {
-    __shared__ double lds[kWaves * 3];
+    __shared__ double lds[kStage2Waves * 3];
     State st = load_state(in);
     double t[3];
     reduce_partials_at<3, 1, true>(PS, PN, sp.G, sp.Gs, t, lds);  // eta, nu, rr; read whether or not the solve has ended
@@ -844,9 +844,9 @@ __global__ __launch_bounds__(kBlock) void k_final_res(SellView S, CsrView C, Spl
     write_partials<1>(acc, PB, sp.Gs, blockIdx.x, lds);
 }
 
-__global__ __launch_bounds__(kBlock) void k_final_reduce(Split sp, const double* __restrict__ PB, State* __restrict__ st)
+__global__ __launch_bounds__(kStage2Block) void k_final_reduce(Split sp, const double* __restrict__ PB, State* __restrict__ st)
 {
-    __shared__ double lds[kWaves * 1];
+    __shared__ double lds[kStage2Waves * 1];
     double t[1];
     reduce_partials<1, true>(PB, sp.G, sp.Gs, t, lds);
     if (threadIdx.x == 0) {
@@ -939,7 +939,7 @@ hipError_t launch_init(int variant, int pre, const SellView* sell, const CsrView
     return with_pre(pre, [&](auto P) {
         const bool pipe2 = is_pipe(variant) && !uses_fused(variant, sp);
         const int step0 = variant == kHS ? (sp.lastwg ? 2 : 1) : (pipe2 || sp.lastwg ? 1 : 0);
-        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kBlock), 0, st, variant, step0, sp,
+        hipLaunchKernelGGL((k_init_finish<decltype(P)::value>), dim3(1), dim3(kStage2Block), 0, st, variant, step0, sp,
                            B.PB, B.PS, pn_of(variant, pre, sp, B), (const double*)pd_of(variant, pre, B), B.S[0],
                            B.hist, tol, (int)maxit);
         return hipGetLastError();
@@ -1006,7 +1006,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 } else if (j == 1) {
                     launch(k_cg_spmv<LL, PP>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur], B.PS, v);
                 } else {
-                    launch(k_cg_finish<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                    launch(k_cg_finish<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PS, (const double*)B.PN);
                     cur = nxt;
                 }
@@ -1071,7 +1071,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                         cur = nxt;
                     }
                 } else if (s2 && j == 0) {
-                    launch(k_finish_one<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
+                    launch(k_finish_one<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PS, (const double*)PN, (const double*)PD, form);
                     cur = nxt;
                 } else if (s2 && j == 1) {
@@ -1106,7 +1106,7 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                         launch(k_pipe_spmv<LL, PP, false, NW>, grid, block, st, ev, S, C, sp, (const State*)B.S[cur],
                                B.S[nxt], B.hist, (const double*)B.PS, form, v);
                     } else if (s2) {
-                        launch(k_finish_one<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                        launch(k_finish_one<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                                B.hist, (const double*)B.PS, (const double*)(B.PS + 3 * (int64_t)sp.Gs),
                                (const double*)nullptr, form);
                         cur = nxt;
@@ -1137,14 +1137,14 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                         cur = nxt;
                     }
                 } else if (s2 && j == 0) {
-                    launch(k_hs_finish_mu, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                    launch(k_hs_finish_mu, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            (const double*)B.PS);
                     cur = nxt;
                 } else if (s2 && j == 1) {
                     launch(k_hs_xr<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            B.hist, (const double*)B.PS, B.PU, tk, v);
                 } else if (s2 && j == 2) {
-                    launch(k_hs_finish_nu<PP>, dim3(1), dim3(kBlock), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                    launch(k_hs_finish_nu<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt],
                            B.hist, (const double*)B.PU);
                     cur = nxt;
                 } else if (s2 && j == 3) {
@@ -1181,7 +1181,7 @@ hipError_t launch_final(const SellView* sell, const CsrView* csr, const Split& s
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(kBlock), 0, st, sp, B.PB, B.S[cur]);
+    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(kStage2Block), 0, st, sp, B.PB, B.S[cur]);
     return hipGetLastError();
 }
 

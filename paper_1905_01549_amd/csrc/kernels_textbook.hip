@@ -74,10 +74,10 @@ __global__ __launch_bounds__(kBlock) void k_tb_spmv(SellView S, CsrView C, Split
 
 // one workgroup: stage 2 of nu_k (and <r, r>), convergence test, beta_k
 template <bool PRE>
-__global__ __launch_bounds__(kBlock) void k_tb_nu(Split sp, const State* __restrict__ in, State* __restrict__ out,
+__global__ __launch_bounds__(kStage2Block) void k_tb_nu(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                   double* __restrict__ hist, const double* __restrict__ PU)
 {
-    __shared__ double lds[kWaves * 2];
+    __shared__ double lds[kStage2Waves * 2];
     State st = load_state(in);
     double t[2];
     reduce_partials<2, true>(PU, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
@@ -86,10 +86,10 @@ __global__ __launch_bounds__(kBlock) void k_tb_nu(Split sp, const State* __restr
 }
 
 // one workgroup: stage 2 of mu_k, alpha_k
-__global__ __launch_bounds__(kBlock) void k_tb_mu(Split sp, const State* __restrict__ in, State* __restrict__ out,
+__global__ __launch_bounds__(kStage2Block) void k_tb_mu(Split sp, const State* __restrict__ in, State* __restrict__ out,
                                                   const double* __restrict__ PS)
 {
-    __shared__ double lds[kWaves * 1];
+    __shared__ double lds[kStage2Waves * 1];
     State st = load_state(in);
     double t[1];
     reduce_partials<1, true>(PS, sp.G, sp.Gs, t, lds);  // read whether or not the solve has ended
@@ -107,11 +107,15 @@ hipError_t go(K kernel, dim3 grid, hipStream_t st, const LaunchEvents* ev, Args.
     return hipGetLastError();
 }
 
-// one-workgroup reduction kernels
+// one-workgroup reduction kernels (kStage2Block threads)
 template <class K, class... Args>
 hipError_t go1(K kernel, hipStream_t st, const LaunchEvents* ev, Args... args)
 {
-    return go(kernel, dim3(1), st, ev, args...);
+    if (ev && ev->start)
+        hipExtLaunchKernelGGL(kernel, dim3(1), dim3(kStage2Block), 0, st, ev->start, ev->stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, dim3(1), dim3(kStage2Block), 0, st, args...);
+    return hipGetLastError();
 }
 
 const char* kNames[] = {"k_tb_mu", "k_tb_axpy_x", "k_tb_axpy_r", "k_tb_prec", "k_tb_dot_nu",

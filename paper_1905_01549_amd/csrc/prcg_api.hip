@@ -256,11 +256,12 @@ void invalidate_graphs(prcg_matrix A)
 
 // Choose the work split: G workgroups (multiple of 8 when G >= 8, so every
 // XCD gets the same number), at most gmax_opt (PRCG_OPT_GRID), or by size
-// when gmax_opt is 0 (the default): from kBigGroups 256-row groups up, two
-// groups per workgroup (at most kMaxGrid), below that at most 1024
-// workgroups.  Measured on MI355X: 4096 workgroups run the 128^3 iteration
-// 3-10% faster than 1024 (more waves in flight per SIMD), while problems of
-// 1-4k groups run best at 1024.
+// when gmax_opt is 0 (the default): from kBigGroups 256-row groups up, one
+// group per workgroup (at most kMaxGrid workgroups), below that at most 1024
+// workgroups.  Measured on MI355X: at 128^3 8192 workgroups run PR-CG 1.7%
+// and HS-CG 2% faster per iteration than 4096 (1536 and 2048 are slower);
+// at 160^3 (27-point) 8192 are 2-4% faster than 4096; problems of 1-4k
+// groups run best at 1024.
 constexpr int64_t kBigGroups = 8192;
 //
 // Stage-2 placement of the default two-pass structure.  The redundant form
@@ -285,7 +286,7 @@ Split make_split(int64_t n, int lanes, int gmax_opt, int kernels_mode)
     sp.lanes = lanes;
     sp.ngroups = (n + kGroupRows - 1) / kGroupRows;
     int64_t gmax = gmax_opt > 0 ? std::min(kMaxGrid, std::max(8, gmax_opt))
-                                : (sp.ngroups >= kBigGroups ? std::min<int64_t>(kMaxGrid, sp.ngroups / 2) : 1024);
+                                : (sp.ngroups >= kBigGroups ? std::min<int64_t>(kMaxGrid, sp.ngroups) : 1024);
     int64_t G = std::min<int64_t>(sp.ngroups, gmax);
     if (G >= 8) G -= G % 8;
     sp.G = (int)std::max<int64_t>(G, 1);
@@ -599,7 +600,7 @@ prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value)
         A->kernels_mode = value;
     } else if (option == PRCG_OPT_GRID) {
         if (value != 0 && (value < 8 || value > kMaxGrid))
-            return fail(PRCG_EINVAL, "grid must be 0 (by size) or in [8, 4096]");
+            return fail(PRCG_EINVAL, "grid must be 0 (by size) or in [8, 8192]");
         A->grid_opt = value;
     } else {
         return fail(PRCG_EINVAL, "unknown option");

@@ -41,56 +41,130 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * N
 }
 
 // Stage 2 of a reduction: the G per-workgroup partials of each of NV values
-// are summed in one fixed order (G <= kMaxGrid) by a workgroup of kBlock
-// threads.  Value i < N1 is read from P1[i * Gs + g], value i >= N1 from
-// P2[(i - N1) * Gs + g] (two kernels may produce the partials of one
-// reduction).  Thread t adds the partials t, t + kBlock, t + 2 kBlock, ...
-// (those below G) in that order, then block_sum.  Every thread receives the
-// totals.  lds: kWaves * NV doubles.
+// are summed in one fixed order (G <= kMaxGrid).  Value i < N1 is read from
+// P1[i * Gs + g], value i >= N1 from P2[(i - N1) * Gs + g] (two kernels may
+// produce the partials of one reduction; the rows are 16-byte aligned).  The
+// order: the partials are taken in pairs (2k, 2k + 1), read as one 16-byte
+// load; lane t < kBlock owns the pairs k = t + kBlock j, j = 0 .. 2 kLanePairs
+// - 1 (partials at or beyond G count as absent), and adds the partials of
+// the first kLanePairs of them in order from 0.0, then those of the rest
+// likewise, and adds the two sums; the kBlock lane sums go through
+// block_sum.  Every thread receives the totals.
 //
-// ALL: every load of a thread is issued before its first addition (the
-// one-workgroup stage-2 kernels: one memory latency for any G, kMaxGrid /
-// kBlock * NV registers); otherwise four per value at a time (kernels that
-// reduce beside other work, to keep their register count down).  The order
-// of additions is the same either way.  (Measured on MI355X: stage-2
-// kernels of 1024 threads are limited to 128 registers per thread, spill,
-// and take twice as long as these.)
+// ALL = false (kernels that reduce beside other work, kBlock threads):
+// thread t is lane t and loads two pairs per value at a time (one in the
+// second half), to keep its register count down.  lds: kWaves * NV doubles.
+// ALL = true (the one-workgroup stage-2 kernels, kStage2Block = 2 kBlock
+// threads): threads t and t + kBlock take the two halves of lane t, each
+// with all its loads issued before its first addition, so stage 2 costs one
+// memory round trip; the second half's wavefronts load nothing when G fits
+// in the first.  lds: kStage2Waves * NV doubles.
+// (Measured on MI355X: a one-workgroup reduction is bound by its load
+// instructions, so 16-byte loads halve its cost; 1024-thread workgroups are
+// limited to 128 registers per thread and spilled.)  The bits are the same
+// either way.
+constexpr int kLanePairs = kMaxGrid / kBlock / 4;  // pairs per lane half
+constexpr int kStage2Block = 2 * kBlock;
+constexpr int kStage2Waves = kStage2Block / 64;
+
+// The pair k of row P (k < G / 2 rounded up), partials beyond G as 0.0; the
+// load itself is clamped to the last pair, so it stays in bounds.
+__device__ __forceinline__ double2 load_pair(const double* __restrict__ P, int k, int G)
+{
+    const int kc = min(k, (G - 1) >> 1);
+    return reinterpret_cast<const double2*>(P)[kc];
+}
+
 template <int NV, int N1, bool ALL = false, int M>
 __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1, const double* __restrict__ P2, int G,
                                                    int Gs, double (&tot)[NV], double (&lds)[M])
 {
-    static_assert(kMaxGrid % kBlock == 0, "partials per thread");
-    static_assert(M >= kWaves * NV, "lds must hold one sum per wavefront and value");
-    constexpr int J = kMaxGrid / kBlock;  // partials per thread
-    constexpr int PIECE = ALL ? J : 4;    // loads per value in flight
+    static_assert(kMaxGrid % (4 * kBlock) == 0, "two halves of whole pairs per lane");
+    static_assert(M >= (ALL ? kStage2Waves : kWaves) * NV, "lds must hold one sum per wavefront and value");
     const double* P[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
-    const int t = threadIdx.x;
+    // adds pair k's partials that lie below G to a
+    auto add_pair = [G](double a, double2 v, int k) {
+        a += 2 * k < G ? v.x : 0.0;
+        a += 2 * k + 1 < G ? v.y : 0.0;
+        return a;
+    };
     double acc[NV];
+    if constexpr (ALL) {
+        __shared__ double hi[NV][kBlock];  // the second half of each lane
+        const int lane = threadIdx.x % kBlock;
+        const int half = threadIdx.x / kBlock;  // uniform per wavefront
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int j0 = 0; j0 < J && j0 * kBlock < G; j0 += PIECE) {
-        // unconditional loads (index clamped to a valid partial, G >= 1),
-        // then a select, so that every load of the piece is in flight at once
-        double buf[NV][PIECE];
+        for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+        if (half == 0 || 2 * kBlock * kLanePairs < G) {
+            double2 buf[NV][kLanePairs];
 #pragma unroll
-        for (int j = 0; j < PIECE; ++j) {
-            const int g = t + kBlock * (j0 + j);
-            const int gc = g < G ? g : G - 1;
+            for (int j = 0; j < kLanePairs; ++j) {
+                const int k = lane + kBlock * (half * kLanePairs + j);
 #pragma unroll
-            for (int i = 0; i < NV; ++i) buf[i][j] = P[i][gc];
+                for (int i = 0; i < NV; ++i) buf[i][j] = load_pair(P[i], k, G);
+            }
+            // keep the scheduler from starting the sums before the last load
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+#pragma unroll
+                for (int j = 0; j < kLanePairs; ++j)
+                    acc[i] = add_pair(acc[i], buf[i][j], lane + kBlock * (half * kLanePairs + j));
+            }
         }
-        // keep the scheduler from starting the selects and sums before the
-        // last load
-        if (ALL) __builtin_amdgcn_sched_barrier(0);
+        if (half == 1) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-#pragma unroll
-            for (int j = 0; j < PIECE; ++j) acc[i] += t + kBlock * (j0 + j) < G ? buf[i][j] : 0.0;
+            for (int i = 0; i < NV; ++i) hi[i][lane] = acc[i];
         }
+        __syncthreads();
+        if (half == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + hi[i][lane];
+        }
+        // every wavefront writes its sum; only the first kWaves (lanes
+        // 0 .. kBlock - 1) are added
+        block_sum<NV, kWaves>(acc, lds);
+    } else {
+        // the first half two pairs per value at a time; the second half
+        // (only when G exceeds the first) one pair at a time, so that its
+        // accumulators cost no registers beyond the first half's
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+        for (int j0 = 0; j0 < kLanePairs && 2 * kBlock * j0 < G; j0 += 2) {
+            double2 buf[NV][2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) buf[i][j] = load_pair(P[i], t + kBlock * (j0 + j), G);
+            }
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i] = add_pair(acc[i], buf[i][j], t + kBlock * (j0 + j));
+            }
+        }
+        if (2 * kBlock * kLanePairs < G) {
+            double hv[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) hv[i] = 0.0;
+            for (int j = kLanePairs; j < 2 * kLanePairs && 2 * kBlock * j < G; ++j) {
+                double2 buf[NV];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) buf[i] = load_pair(P[i], t + kBlock * j, G);
+#pragma unroll
+                for (int i = 0; i < NV; ++i) hv[i] = add_pair(hv[i], buf[i], t + kBlock * j);
+            }
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + hv[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + 0.0;  // the empty second half
+        }
+        block_sum<NV>(acc, lds);
     }
-    block_sum<NV>(acc, lds);
 #pragma unroll
     for (int i = 0; i < NV; ++i) tot[i] = acc[i];
 }

@@ -190,20 +190,34 @@ def test_grid_sizes(prcg, torch_cuda, variant, grid, kernels):
 
 @pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
 def test_varcoef27_parity(prcg, torch_cuda, variant):
-    """High-contrast coefficients (lognormal(0,1) cells): the residual norms of
-    two correct rounding orders part ways after a dozen iterations while both
-    converge, so histories are compared over the first 12 iterations and the
-    attainable accuracy by the paper's 10%-on-a-log-scale criterion."""
+    """High-contrast coefficients (lognormal(0,1) cells) make the iteration
+    rounding-sensitive: the residual norms of two correct rounding orders part
+    ways after a dozen iterations while both converge, and in the oracle
+    alone moving every entry of b by one ulp moves x_12 by up to 5e-11
+    relative, x_30 by up to 9e-9 and x_139 (the solution) by up to 4e-11.  So
+    x_12 and the first 12 residual norms are compared with the oracle element
+    by element at the history bar (1e-8 relative); the solve to 1e-10 by
+    status, iteration count (within one) and the true residual of the
+    returned x, computed on the host; and the attainable accuracy by the
+    paper's 10%-on-a-log-scale criterion."""
     A = P.varcoef27(20, 3)
     xs = P.uniform_vector(A.n, 3)
     b = P.rhs_from_solution(A, xs)
-    info = check_parity(prcg, A, b, variant, "none", 1e-10, 3000, hist_len=12)
     M = gpu_matrix(prcg, A)
+    x12, i12 = M.solve(b, variant, 0.0, 12, history=True)
+    ref = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, "none", 0.0, 12)
+    assert np.linalg.norm(x12.cpu().numpy() - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+    assert hist_close(i12.history, ref["history"])
+    x, info = M.solve(b, variant, 1e-10, 3000)
+    stop = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, "none", 1e-10, 3000)
+    assert info.status == stop["status"] == "ok" and abs(info.iters - stop["iters"]) <= 1
+    true = np.linalg.norm(b - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert true <= 2e-10 and abs(info.relres_true - true) <= 1e-6 * true
     _, deep = M.solve(b, variant, 1e-16, 1500)
     ref = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, "none", 0.0, 1500, diagnostics=["true_res"])
     a_o = np.nanmin(ref["true_res"])
     assert abs(np.log10(deep.relres_true) - np.log10(a_o)) <= 0.1 * abs(np.log10(a_o))
-    assert info.status == "ok"
+    M.close()
 
 
 @pytest.mark.parametrize("fmt", ["csr8", "csr64"])
@@ -368,20 +382,26 @@ def test_reduction_placements_agree_bitwise(prcg, torch_cuda):
                 assert np.array_equal(x, out[0][0]) and np.array_equal(h, out[0][2]), (v, pre)
 
 
-def test_reduction_order_is_independent_of_load_batching(prcg, torch_cuda):
-    """With more than 1024 partials, the in-kernel reductions (redundant,
-    last-workgroup), which load four partials per thread and value at a
-    time, and the stage-2 kernels, which load all of them at once, add in one
-    order: identical bits."""
-    A = P.poisson3d(72)  # 1458 row groups
-    b = P.uniform_vector(A.n, 8)
+@pytest.mark.parametrize("grid", [1456, 8192])
+def test_reduction_order_is_independent_of_load_batching(prcg, torch_cuda, grid):
+    """With more partials than a lane's first half holds (8192: both halves
+    of every lane), the in-kernel reductions (redundant, last-workgroup),
+    which load two pairs of partials per thread and value at a time, and the
+    stage-2 kernels, which split each lane over two threads that load all of
+    theirs at once, add in one order: identical bits."""
+    if grid == 1456:
+        A = P.poisson3d(72)  # 1458 row groups
+        b = P.uniform_vector(A.n, 8)
+    else:
+        pr = P.config2()  # 8192 row groups
+        A, b = pr.A, pr.b
     for v in ("hs", "pr", "pipe_pr", "cg"):
         out = []
         for kernels in ("two_pass_redundant", "two_pass_stage2", "two_pass_last"):
             M = gpu_matrix(prcg, A, "jacobi", kernels)
-            M.set_grid(1456)
-            assert M.props.grid == 1456
-            x, info = M.solve(b, v, 0.0, 150, history=True)
+            M.set_grid(grid)
+            assert M.props.grid == grid
+            x, info = M.solve(b, v, 0.0, 60, history=True)
             out.append((x.cpu().numpy(), info.history))
             M.close()
         for x, h in out[1:]:
