@@ -451,6 +451,23 @@ def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
         assert np.linalg.norm(xg - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
 
 
+@pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr", "cg"])
+def test_ragged_full_scale_jacobi(prcg, torch_cuda, variant):
+    """A 131x127x129 grid (n = 2,146,173: a partial last slice, 8384 row
+    groups over the default 8192 workgroups, so some workgroups take two
+    groups, and partials in both halves of every lane of the reduction):
+    x_60 and the first 60 residual norms against the oracle."""
+    A = P.poisson3d(131, 127, 129)
+    b = P.uniform_vector(A.n, 12)
+    M = gpu_matrix(prcg, A, "jacobi", "auto")
+    assert M.props.grid == 8192
+    x, info = M.solve(b, variant, 0.0, 60, history=True)
+    ref = oracle_solve(A, b, variant, "jacobi", 0.0, 60)
+    assert info.iters == 60 and hist_close(info.history, ref["history"])
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+    M.close()
+
+
 def test_auto_structure_by_size(prcg, torch_cuda):
     """The default structure is fused on SELL-64 problems of up to 1024
     workgroups (pipe-PR-CG: below 64) and two-pass (with stage 2 in its own
