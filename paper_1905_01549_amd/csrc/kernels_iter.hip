@@ -195,36 +195,56 @@ __device__ __forceinline__ void row_range(const Split& sp, int64_t g0, int64_t g
     i1 = g1 * kGroupRows < sp.n ? g1 * kGroupRows : sp.n;
 }
 
+// Stage 2 of a PR-CG reduction in kWaves workgroups: the sums of the lane
+// groups of mu, sigma, gamma (PS) and nu, <r, r> (PN), to W; the update
+// kernel adds them and performs the scalar step in every workgroup.  Same
+// bits as a one-workgroup stage 2, at a quarter of its loads per workgroup.
+__global__ __launch_bounds__(kWaveBlock) void k_stage2_waves(Split sp, const double* __restrict__ PS,
+                                                             const double* __restrict__ PN, double* __restrict__ W)
+{
+    wave_partial_sums<5, 3>(PS, PN, sp.G, sp.Gs, W);
+}
+
 // Stage 2 of iteration k + scalar step, then the vector updates of
 // iteration k+1 (Alg. 2): x += alpha p; r -= alpha s; r~ -= alpha s~;
-// p = r~ + beta p.  The partials of iteration k are read from PS (mu, sigma,
-// gamma) and PN (nu, <r, r>).
-// REDUCE = false: the state was already advanced (k_finish_one, or the last
-// workgroup of the product kernel) and `in` is the current state.
-// NUDOT (Jacobi, REDUCE = false): this kernel also writes the partials of
+// p = r~ + beta p.
+// RED: how the state of iteration k is reached.  0: already advanced (a
+// one-workgroup kernel, or the last workgroup of the product kernel) and
+// `in` is the current state; 1: every workgroup sums all partials of PS
+// (mu, sigma, gamma) and PN (nu, <r, r>); 2: every workgroup adds the lane
+// group sums W of k_stage2_waves.  With RED != 0 every workgroup performs
+// the scalar step (`in` -> `out`, written by workgroup 0).
+// NUDOT (Jacobi, RED != 1): this kernel also writes the partials of
 // nu_{k+1} = <r~, r> and <r, r> of the rows it has just updated to PN, so
 // the product kernel need not read r again.
-// PD (nullable): the partials of delta_k = <s~_k, r_k> (eq. nuk with a
-// preconditioner), reduced together with the others when REDUCE.
-template <bool PRE, bool REDUCE, bool NUDOT>
+// PD (nullable, RED = 1): the partials of delta_k = <s~_k, r_k> (eq. nuk
+// with a preconditioner), reduced together with the others.
+template <bool PRE, int RED, bool NUDOT>
 __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, double* __restrict__ PN,
-                                                      const double* __restrict__ PD, int form, Vecs v)
+                                                      const double* __restrict__ PD, const double* __restrict__ W,
+                                                      int form, Vecs v)
 {
-    static_assert(!(REDUCE && NUDOT), "PN is read by every workgroup when REDUCE");
+    static_assert(!(RED == 1 && NUDOT), "PN is read by every workgroup when RED = 1");
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
     __shared__ double lds[kWaves * 5];
     State st = load_state(in);
-    if (REDUCE) {
+    if (RED != 0) {
         if (st.done) {
             if (writer_thread()) store_state(out, st);
             return;
         }
         double t[5];
-        reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
-        double dd[1] = {t[1]};
-        if (PD) reduce_partials<1>(PD, sp.G, sp.Gs, dd, lds);
+        double dd[1];
+        if (RED == 1) {
+            reduce_partials_at<5, 3>(PS, PN, sp.G, sp.Gs, t, lds);
+            dd[0] = t[1];
+            if (PD) reduce_partials<1>(PD, sp.G, sp.Gs, dd, lds);
+        } else {
+            sum_wave_sums<5>(W, t);
+            dd[0] = t[1];
+        }
         step_one_reduction(st, t, PRE, form, hist, writer_thread(), dd[0]);
         if (writer_thread()) store_state(out, st);
     }
@@ -976,7 +996,9 @@ const char* iter_kernel_name(int variant, const Split& sp, int j)
     case kM:
     case kPRNoRecompute:
     case kPRUnsimplified:
-        if (stage2_of(sp, kPR)) return j == 0 ? "k_finish_one" : (j == 1 ? "k_pr_update" : "k_pr_spmv");
+        if (stage2_of(sp, kPR))
+            return j == 0 ? (variant == kPRUnsimplified && sp.textbook_pre ? "k_finish_one" : "k_stage2_waves")
+                          : (j == 1 ? "k_pr_update" : "k_pr_spmv");
         return j == 0 ? "k_pr_update" : "k_pr_spmv";
     default:
         if (stage2_of(sp, variant)) return j == 0 ? "k_pipe_update" : (j == 1 ? "k_pipe_spmv" : "k_finish_one");
@@ -1027,17 +1049,24 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 double* PN = pn_of(variant, pre, sp, B);
                 double* PD = pd_of(variant, pre, B);
                 const bool nu_up = nu_in_update(variant, pre, sp);
-                // the update kernel without a reduction, forming nu when nu_up
-                auto update = [&]() {
+                // stage 2 split over kWaves workgroups, the scalar step in every
+                // workgroup of the update kernel (PD, eq. nuk with a
+                // preconditioner, keeps the one-workgroup stage 2)
+                const bool waves = s2 && !PD;
+                // the update kernel (RED 0: no reduction, 2: the wave sums),
+                // forming nu when nu_up
+                auto update = [&](auto red) {
+                    constexpr int RD = decltype(red)::value;
                     if constexpr (PP) {
                         if (nu_up) {
-                            launch(k_pr_update<PP, false, true>, grid, block, st, ev, sp, (const State*)B.S[cur],
-                                   B.S[nxt], B.hist, (const double*)B.PS, PN, (const double*)PD, form, v);
+                            launch(k_pr_update<PP, RD, true>, grid, block, st, ev, sp, (const State*)B.S[cur],
+                                   B.S[nxt], B.hist, (const double*)B.PS, PN, (const double*)PD,
+                                   (const double*)B.PW, form, v);
                             return;
                         }
                     }
-                    launch(k_pr_update<PP, false, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, PN, (const double*)PD, form, v);
+                    launch(k_pr_update<PP, RD, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, PN, (const double*)PD, (const double*)B.PW, form, v);
                 };
                 // the product kernel (LAST: with the reduction in its last
                 // workgroup; with delta's partials when PD)
@@ -1065,20 +1094,26 @@ hipError_t launch_iter_kernel(int variant, int pre, int j, int& cur, const SellV
                 };
                 if (sp.lastwg) {
                     if (j == 0) {
-                        update();
+                        update(std::integral_constant<int, 0>{});
                     } else {
                         product(std::true_type{});
                         cur = nxt;
                     }
+                } else if (waves && j == 0) {
+                    launch(k_stage2_waves, dim3(kWaves), dim3(kWaveBlock), st, ev, sp, (const double*)B.PS,
+                           (const double*)PN, B.PW);
+                } else if (waves && j == 1) {
+                    update(std::integral_constant<int, 2>{});
+                    cur = nxt;
                 } else if (s2 && j == 0) {
                     launch(k_finish_one<PP>, dim3(1), dim3(kStage2Block), st, ev, sp, (const State*)B.S[cur], B.S[nxt], B.hist,
                            (const double*)B.PS, (const double*)PN, (const double*)PD, form);
                     cur = nxt;
                 } else if (s2 && j == 1) {
-                    update();
+                    update(std::integral_constant<int, 0>{});
                 } else if (j == 0) {
-                    launch(k_pr_update<PP, true, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
-                           B.hist, (const double*)B.PS, PN, (const double*)PD, form, v);
+                    launch(k_pr_update<PP, 1, false>, grid, block, st, ev, sp, (const State*)B.S[cur], B.S[nxt],
+                           B.hist, (const double*)B.PS, PN, (const double*)PD, (const double*)B.PW, form, v);
                     cur = nxt;
                 } else {
                     product(std::false_type{});

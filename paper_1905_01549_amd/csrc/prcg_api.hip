@@ -89,7 +89,7 @@ struct prcg_matrix_s {
     State* S = nullptr;      // two copies
     double* hist = nullptr;
     int64_t hist_cap = 0;
-    double* partials = nullptr;  // PS | PU | PB | PS2 | PN | PD
+    double* partials = nullptr;  // PS | PU | PB | PS2 | PN | PD | PW
     int32_t* dflags = nullptr;   // [0..3] setup flags, [4] reduction ticket
     State* hstate = nullptr;     // pinned, two slots
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -150,6 +150,7 @@ struct prcg_matrix_s {
         B.PS2 = partials + (size_t)(kMaxDots + 3) * kMaxGrid;
         B.PN = partials + (size_t)(2 * kMaxDots + 3) * kMaxGrid;
         B.PD = partials + (size_t)(2 * kMaxDots + 5) * kMaxGrid;
+        B.PW = partials + (size_t)(2 * kMaxDots + 6) * kMaxGrid;
         B.ticket = dflags + 4;
         return B;
     }
@@ -582,7 +583,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     HTRY(hipMalloc(&A->S, sizeof(State) * 2));
     HTRY(hipMemsetAsync(A->S, 0, sizeof(State) * 2, A->stream));
     // partials sized for the largest grid, so the grid can change later
-    HTRY(hipMalloc(&A->partials, sizeof(double) * (2 * kMaxDots + 6) * (size_t)kMaxGrid));
+    HTRY(hipMalloc(&A->partials, sizeof(double) * (2 * kMaxDots + 7) * (size_t)kMaxGrid));
     HTRY(hipStreamSynchronize(A->stream));
     TRY(ensure_hist(A, 1024));
     *out = A;

@@ -181,6 +181,7 @@ struct Bufs {
     double* PS;   // [mu, sigma, gamma, nu, rr] partials
     double* PN;   // [nu, rr] partials when PR's update kernel produces them
     double* PD;   // [delta] partials (PR-CG with eq. nuk and a preconditioner)
+    double* PW;   // [value][kWaves] lane-group sums of a split stage 2
     double* PU;   // [nu, rr] partials (HS)
     double* PB;   // [bb] or [tt] partials
     double* PS2;  // second copy of PS (fused kernels alternate between the two)

@@ -169,6 +169,74 @@ __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1
     for (int i = 0; i < NV; ++i) tot[i] = acc[i];
 }
 
+// Stage 2 split over kWaves workgroups (grid kWaves, kWaveBlock threads):
+// workgroup w forms the sum of lanes 64 w .. 64 w + 63 of reduce_partials_at's
+// order (each lane's two halves, threads h * 64 + l taking half h of lane
+// 64 w + l, then the wavefront butterfly) and writes it to W[i * kWaves + w].
+// sum_wave_sums adds W[i * kWaves + 0 .. kWaves - 1] in order, which is
+// block_sum's last step: the totals have reduce_partials_at's bits.  The
+// wavefronts of the second halves load nothing when G fits in the first.
+constexpr int kWaveBlock = 128;
+
+template <int NV, int N1>
+__device__ __forceinline__ void wave_partial_sums(const double* __restrict__ P1, const double* __restrict__ P2, int G,
+                                                  int Gs, double* __restrict__ W)
+{
+    __shared__ double hi[NV][64];
+    const double* P[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+    const int l = threadIdx.x & 63;
+    const int half = threadIdx.x >> 6;  // uniform per wavefront
+    const int lane = 64 * blockIdx.x + l;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    if (half == 0 || 2 * kBlock * kLanePairs < G) {
+        double2 buf[NV][kLanePairs];
+#pragma unroll
+        for (int j = 0; j < kLanePairs; ++j) {
+            const int k = lane + kBlock * (half * kLanePairs + j);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) buf[i][j] = load_pair(P[i], k, G);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+#pragma unroll
+            for (int j = 0; j < kLanePairs; ++j) {
+                const int k = lane + kBlock * (half * kLanePairs + j);
+                acc[i] += 2 * k < G ? buf[i][j].x : 0.0;
+                acc[i] += 2 * k + 1 < G ? buf[i][j].y : 0.0;
+            }
+        }
+    }
+    if (half == 1) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) hi[i][l] = acc[i];
+    }
+    __syncthreads();
+    if (half == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double v = wave_sum(acc[i] + hi[i][l]);
+            if (l == 0) W[i * kWaves + blockIdx.x] = v;
+        }
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void sum_wave_sums(const double* __restrict__ W, double (&t)[NV])
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double a = W[i * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) a += W[i * kWaves + q];
+        t[i] = a;
+    }
+}
+
 template <int NV, bool ALL = false, int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int G, int Gs, double (&tot)[NV],
                                                 double (&lds)[M])
