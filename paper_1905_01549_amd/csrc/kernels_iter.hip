@@ -229,6 +229,39 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
     static_assert(!(RED == 1 && NUDOT), "PN is read by every workgroup when RED = 1");
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
     __shared__ double lds[kWaves * 5];
+    int64_t g0, g1, i0, i1;
+    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    row_range(sp, g0, g1, i0, i1);
+    double* __restrict__ x = v.x;
+    double* __restrict__ r = v.r;
+    double* __restrict__ rt = v.rt;
+    double* __restrict__ p = v.p;
+    const double* __restrict__ s = v.s;
+    const double* __restrict__ d = v.d;
+    // two rows per step (i and i + kBlock), every load issued before the
+    // first store
+    struct Rows {
+        double s[2], p[2], x[2], r[2], rt[2], d[2];
+    };
+    auto load = [&](int64_t i, Rows& q) {
+        const int64_t j = i + kBlock;
+        const int64_t jj = j < i1 ? j : i;
+        q.s[0] = s[i], q.s[1] = s[jj];
+        q.p[0] = p[i], q.p[1] = p[jj];
+        q.x[0] = x[i], q.x[1] = x[jj];
+        q.r[0] = r[i], q.r[1] = r[jj];
+        if (PRE) {
+            q.rt[0] = rt[i], q.rt[1] = rt[jj];
+            q.d[0] = d[i], q.d[1] = d[jj];
+        } else {
+            q.rt[0] = q.rt[1] = q.d[0] = q.d[1] = 0.0;
+        }
+    };
+    // the first step's rows are loaded before the state is examined (row 0
+    // when this thread has none; every index stays below i1 <= n), so that
+    // their latency overlaps the stage-2 sums and the scalar step
+    Rows q;
+    load(i0 < i1 ? i0 : 0, q);
     State st = load_state(in);
     if (RED != 0) {
         if (st.done) {
@@ -250,51 +283,33 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
     }
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
-    int64_t g0, g1, i0, i1;
-    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
-    row_range(sp, g0, g1, i0, i1);
-    double* __restrict__ x = v.x;
-    double* __restrict__ r = v.r;
-    double* __restrict__ rt = v.rt;
-    double* __restrict__ p = v.p;
-    const double* __restrict__ s = v.s;
-    const double* __restrict__ d = v.d;
     double acc[2] = {0.0, 0.0};
-    // two rows per step, every load issued before the first store
     for (int64_t i = i0; i < i1; i += 2 * kBlock) {
+        if (i != i0) load(i, q);
         const int64_t j = i + kBlock;
         const bool two = j < i1;
-        const int64_t jj = two ? j : i;
-        const double s0 = s[i], s1 = s[jj];
-        const double p0 = p[i], p1 = p[jj];
-        const double x0 = x[i], x1 = x[jj];
-        const double r0 = r[i], r1 = r[jj];
-        double rt0 = 0.0, rt1 = 0.0, d0 = 0.0, d1 = 0.0;
-        if (PRE) {
-            rt0 = rt[i];
-            rt1 = rt[jj];
-            d0 = d[i];
-            d1 = d[jj];
+        double rn[2], rtn[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            rn[u] = fma(-alpha, q.s[u], q.r[u]);
+            rtn[u] = PRE ? fma(-alpha, q.d[u] * q.s[u], q.rt[u]) : rn[u];
         }
-        const double rn0 = fma(-alpha, s0, r0), rn1 = fma(-alpha, s1, r1);
-        const double rtn0 = PRE ? fma(-alpha, d0 * s0, rt0) : rn0;
-        const double rtn1 = PRE ? fma(-alpha, d1 * s1, rt1) : rn1;
-        x[i] = fma(alpha, p0, x0);
-        r[i] = rn0;
-        if (PRE) rt[i] = rtn0;
-        p[i] = fma(beta, p0, rtn0);
+        x[i] = fma(alpha, q.p[0], q.x[0]);
+        r[i] = rn[0];
+        if (PRE) rt[i] = rtn[0];
+        p[i] = fma(beta, q.p[0], rtn[0]);
         if (NUDOT) {
-            acc[0] = fma(rtn0, rn0, acc[0]);
-            acc[1] = fma(rn0, rn0, acc[1]);
+            acc[0] = fma(rtn[0], rn[0], acc[0]);
+            acc[1] = fma(rn[0], rn[0], acc[1]);
         }
         if (two) {
-            x[j] = fma(alpha, p1, x1);
-            r[j] = rn1;
-            if (PRE) rt[j] = rtn1;
-            p[j] = fma(beta, p1, rtn1);
+            x[j] = fma(alpha, q.p[1], q.x[1]);
+            r[j] = rn[1];
+            if (PRE) rt[j] = rtn[1];
+            p[j] = fma(beta, q.p[1], rtn[1]);
             if (NUDOT) {
-                acc[0] = fma(rtn1, rn1, acc[0]);
-                acc[1] = fma(rn1, rn1, acc[1]);
+                acc[0] = fma(rtn[1], rn[1], acc[0]);
+                acc[1] = fma(rn[1], rn[1], acc[1]);
             }
         }
     }
