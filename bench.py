@@ -106,6 +106,28 @@ def nu_split(M) -> bool:
     return bool(p.stage2 & 2) or p.kernels == 4
 
 
+def stream_triad(torch, n=64 * 1024 * 1024, reps=20):
+    """A STREAM triad a = b + s c on three float64 arrays of 512 MiB each
+    (beyond the 256 MB Infinity Cache), with torch's elementwise kernel: a
+    measured reference bandwidth for the mix of two reads and one write, to
+    set the kernels' GB/s against besides the 8 TB/s peak."""
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    for _ in range(3):
+        torch.add(b, c, alpha=3.0, out=a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.add(b, c, alpha=3.0, out=a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b, c
+    return 3 * 8 * n / sec / 1e9
+
+
 def batched_section(torch, prcg, problems, traffic):
     """512 anisotropic systems in one persistent launch vs one prcg_solve per system."""
     A, offs, b, xs, eps = problems.config4()
@@ -402,6 +424,7 @@ def main():
                     "iters_per_s_one_thread": one["iters"] / dt1,
                     "one_thread_sample": f"{one['iters']} iterations from x0 = 0 ({dt1:.1f} s, incl. setup)"}
 
+    triad = stream_triad(torch)
     batched = None if args.no_batched else batched_section(torch, prcg, problems, traffic)
     adjoint = None if args.no_adjoint else adjoint_section(torch, prcg, problems)
 
@@ -424,6 +447,9 @@ def main():
                    f"csr{props.lanes_per_row}", "grid": props.grid, "parallelism": "single GPU"},
         "hbm_GBps_algorithmic": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"],
         "hbm_frac": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"] / HBM_PEAK_GBS,
+        "stream_triad_GBps": triad,
+        "frac_of_stream_triad": {"iteration": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"] / triad,
+                                 roofline["kernel"]: roofline["achieved"] / triad},
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
