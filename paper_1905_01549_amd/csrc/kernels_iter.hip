@@ -368,8 +368,15 @@ __global__ __launch_bounds__(kStage2Block) void k_hs_finish_nu(Split sp, const S
 // DELTA (eq. nuk with a preconditioner): also delta = <s~, r> (to PD).
 // LAST: the last workgroup also runs stage 2 and the scalar step, advancing
 // the state from `in` to `out`.
+// Occupancy of the product kernels: at least 7 wavefronts per SIMD (at most
+// 72 registers; measured on MI355X, PR-CG's product is 1.5 us faster at
+// 128^3 than with the 78 registers the compiler would take), pipe-PR-CG's
+// paired product at least 6.
+constexpr int kSpmvWaves = 7;
+constexpr int kPipeSpmvWaves = 6;
+
 template <int LANES, bool PRE, bool LAST, bool NUDOT, bool DELTA = false>
-__global__ __launch_bounds__(kBlock) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock, kSpmvWaves) void k_pr_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ hist,
                                                     double* __restrict__ PS, double* __restrict__ PN,
                                                     double* __restrict__ PD, int form, int* ticket, Vecs v)
@@ -510,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
 // state instead.  NOW (no recompute of w): only u = A s~ is stored; w keeps
 // the update kernel's w'.
 template <int LANES, bool PRE, bool REDUCE, bool NOW = false>
-__global__ __launch_bounds__(kBlock) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock, kPipeSpmvWaves) void k_pipe_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                       State* __restrict__ out, double* __restrict__ hist,
                                                       const double* __restrict__ PS, int form, Vecs v)
 {
@@ -609,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_gv_update(Split sp, const State* __r
 // share of the product: the reduction overlaps the product, as GV-CG is
 // designed for.
 template <int LANES, bool PRE>
-__global__ __launch_bounds__(kBlock) void k_gv_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock, kSpmvWaves) void k_gv_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ hist,
                                                     const double* __restrict__ PS, Vecs v)
 {
@@ -691,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Split sp, const State* __r
 
 // w_k = A r~_k and the partials of eta_k = <r~_k, w_k>.
 template <int LANES, bool PRE>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
+__global__ __launch_bounds__(kBlock, kSpmvWaves) void k_cg_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ cur,
                                                     double* __restrict__ PS, Vecs v)
 {
     __shared__ double lds[kWaves * 1];
@@ -827,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_p(Split sp, const State* __restri
 // s_k = A p_k and the partials of mu_k = <p_k, s_k>.  LAST: the last
 // workgroup also reduces mu_k and forms alpha_k (`in` -> `out`).
 template <int LANES, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_hs_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
+__global__ __launch_bounds__(kBlock, kSpmvWaves) void k_hs_spmv(SellView S, CsrView C, Split sp, const State* __restrict__ in,
                                                     State* __restrict__ out, double* __restrict__ PS, int* ticket,
                                                     Vecs v)
 {
