@@ -50,10 +50,6 @@ struct SlotIter {
     const int32_t* col;   // packed: column of the first slot of this lane
     const double* val;
     int row, last;
-    __device__ __forceinline__ int column(int j) const
-    {
-        return off ? min(max(row + off[j], 0), last) : col[(int64_t)j * 64];
-    }
     __device__ __forceinline__ double value(int j) const { return val[(int64_t)j * 64]; }
 };
 
@@ -69,6 +65,57 @@ __device__ __forceinline__ SlotIter slots_of(const SellView& A, int64_t slice, i
     it.row = (int)row;
     it.last = (int)A.n - 1;
     return it;
+}
+
+// Calls f(c, a) for the slots of a SELL-64 row in stored order, with the
+// slot's column c and value a.  Aligned and packed slices take separate
+// code (one uniform branch per slice), and the slots go in pieces of
+// kFusedPiece whose columns (an aligned piece's offsets in one scalar load)
+// and values are loaded before the first call, so the gathers of a piece are
+// in flight together.
+constexpr int kFusedPiece = 4;
+
+template <int K, bool ALIGNED, class F>
+__device__ __forceinline__ void fused_piece(const SlotIter& it, int j0, F&& f)
+{
+    int c[K];
+    double a[K];
+    if constexpr (ALIGNED) {
+        int o[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) o[u] = it.off[j0 + u];
+#pragma unroll
+        for (int u = 0; u < K; ++u) c[u] = min(max(it.row + o[u], 0), it.last);
+    } else {
+#pragma unroll
+        for (int u = 0; u < K; ++u) c[u] = it.col[(int64_t)(j0 + u) * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) a[u] = it.value(j0 + u);
+#pragma unroll
+    for (int u = 0; u < K; ++u) f(c[u], a[u]);
+}
+
+template <bool ALIGNED, class F>
+__device__ __forceinline__ void fused_slots_of(const SlotIter& it, int width, F&& f)
+{
+    int j0 = 0;
+    for (; j0 + kFusedPiece <= width; j0 += kFusedPiece) fused_piece<kFusedPiece, ALIGNED>(it, j0, f);
+    switch (width - j0) {
+    case 1: fused_piece<1, ALIGNED>(it, j0, f); break;
+    case 2: fused_piece<2, ALIGNED>(it, j0, f); break;
+    case 3: fused_piece<3, ALIGNED>(it, j0, f); break;
+    default: break;
+    }
+}
+
+template <class F>
+__device__ __forceinline__ void fused_slots(const SlotIter& it, int width, F&& f)
+{
+    if (it.off)
+        fused_slots_of<true>(it, width, f);
+    else
+        fused_slots_of<false>(it, width, f);
 }
 
 // PR-CG, one kernel per iteration (Alg. 2):
@@ -127,17 +174,14 @@ __global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const
         int width;
         const SlotIter it = slots_of(S, slice, lane, i, width);
         double sn = 0.0;
-#pragma unroll 2
-        for (int j = 0; j < width; ++j) {
-            const int c = it.column(j);
-            const double a = it.value(j);
+        fused_slots(it, width, [&](int c, double a) {
             const double sc = s_o[c];
             const double tc = t_o[c];
             const double pc = p_o[c];
             const double dc = PRE ? d[c] : 1.0;
             const double tnc = PRE ? fma(-alpha, dc * sc, tc) : fma(-alpha, sc, tc);
             sn = fma(a, fma(beta, pc, tnc), sn);
-        }
+        });
         if (own) {
             s_n[i] = sn;
             const double stn = PRE ? di * sn : sn;
@@ -218,10 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, con
         int width;
         const SlotIter it = slots_of(S, slice, lane, i, width);
         double un = 0.0, wn = 0.0;
-#pragma unroll 2
-        for (int j = 0; j < width; ++j) {
-            const int c = it.column(j);
-            const double a = it.value(j);
+        fused_slots(it, width, [&](int c, double a) {
             const double tc = t_o[c], zc = z_o[c], wc = w_o[c], uc = u_o[c];
             double tnc, znc;
             if (PRE) {
@@ -234,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, con
             }
             un = fma(a, znc, un);
             wn = fma(a, tnc, wn);
-        }
+        });
         if (own) {
             u_n[i] = un;
             w_n[i] = wn;
@@ -288,12 +329,10 @@ __global__ __launch_bounds__(kBlock) void k_hs_fused(SellView S, Split sp, const
         int width;
         const SlotIter it = slots_of(S, slice, lane, i, width);
         double sn = 0.0;
-#pragma unroll 2
-        for (int j = 0; j < width; ++j) {
-            const int c = it.column(j);
+        fused_slots(it, width, [&](int c, double a) {
             const double rc = r[c];
-            sn = fma(it.value(j), fma(beta, p_o[c], PRE ? d[c] * rc : rc), sn);
-        }
+            sn = fma(a, fma(beta, p_o[c], PRE ? d[c] * rc : rc), sn);
+        });
         if (own) {
             s[i] = sn;
             acc[0] = fma(pn, sn, acc[0]);
