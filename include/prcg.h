@@ -126,6 +126,9 @@ typedef struct {
     int32_t stage2;           /* two-pass stage-2 reductions in one-workgroup
                                  kernels of their own: bit 0 HS-CG, bit 1 PR-CG
                                  and M-CG                                         */
+    int64_t streamed_entries; /* SELL-64: value slots read with nontemporal loads
+                                 (offset-aligned slices past the first 128 MiB of
+                                 values, which stay cacheable between products)   */
 } prcg_matrix_props;
 
 /* Options (prcg_set_option).

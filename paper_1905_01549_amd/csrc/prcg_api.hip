@@ -76,8 +76,10 @@ struct prcg_matrix_s {
     int32_t* scol = nullptr;
     double* sval = nullptr;
     int64_t nslices = 0;
+    int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
     int64_t stored = 0;          // value slots, padding included
     int64_t stored_packed = 0;   // slots of packed slices (they also read a column index)
+    int64_t stored_streamed = 0; // slots read with nontemporal loads
     int64_t noffsets = 0;        // offsets of aligned slices
     double* d = nullptr;
     Split sp{};
@@ -95,7 +97,12 @@ struct prcg_matrix_s {
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipGraphExec_t graph[kNumVariants] = {};
 
-    SellView sell() const { return SellView{slice_ptr, slice_meta, soff, scol, sval, n, nslices}; }
+    SellView sell() const
+    {
+        SellView s{slice_ptr, slice_meta, soff, scol, sval, n, nslices};
+        s.stream_from = stream_from;
+        return s;
+    }
     CsrView csr() const { return CsrView{row_ptr, col, val, n}; }
     const SellView* sellp() const { return sp.lanes == 1 ? &sell_storage : nullptr; }
     const CsrView* csrp() const { return sp.lanes == 1 ? nullptr : &csr_storage; }
@@ -545,6 +552,13 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         }
     }
     A->stored = hptr[A->nslices];
+    for (int64_t q = 0; q < A->nslices; ++q)
+        if (hptr[q + 1] * (int64_t)sizeof(double) > kCachedValueBytes) {
+            A->stream_from = q + 1;
+            break;
+        }
+    for (int64_t q = A->stream_from; q < A->nslices; ++q)
+        if (aligned[q]) A->stored_streamed += hptr[q + 1] - hptr[q];
     int lanes = 1;
     const char* fmt = std::getenv("PRCG_FORMAT");
     const double mean = (double)nnz / (double)n;
@@ -695,6 +709,7 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
     props->aligned_slices_frac = 0.0;
     if (A->sp.lanes == 1 && A->nslices > 0)
         props->aligned_slices_frac = 1.0 - (double)A->stored_packed / (double)std::max<int64_t>(A->stored, 1);
+    props->streamed_entries = A->sp.lanes == 1 ? A->stored_streamed : 0;
     return PRCG_OK;
 }
 

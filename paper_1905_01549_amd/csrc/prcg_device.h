@@ -327,7 +327,7 @@ struct SlotCols {
 
 // K slots starting at j0; G(c) returns the gathered entry (double or
 // double2) at column c, F(acc, a, g) accumulates.
-template <int K, bool ALIGNED, class T, class Gather, class Acc>
+template <int K, bool ALIGNED, class T, bool NT, class Gather, class Acc>
 __device__ __forceinline__ void slot_piece(const double* __restrict__ v, const SlotCols& cols, int j0, Gather&& gather,
                                            Acc&& acc)
 {
@@ -346,39 +346,48 @@ __device__ __forceinline__ void slot_piece(const double* __restrict__ v, const S
     T g[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-        a[u] = v[(int64_t)(j0 + u) * 64];
+        if constexpr (NT)
+            a[u] = __builtin_nontemporal_load(v + (int64_t)(j0 + u) * 64);
+        else
+            a[u] = v[(int64_t)(j0 + u) * 64];
         g[u] = gather(c[u]);
     }
 #pragma unroll
     for (int u = 0; u < K; ++u) acc(a[u], g[u]);
 }
 
-template <bool ALIGNED, class T, class Gather, class Acc>
+template <bool ALIGNED, class T, bool NT, class Gather, class Acc>
 __device__ __forceinline__ void slot_loop_of(const double* __restrict__ v, const SlotCols& cols, int width,
                                              Gather&& gather, Acc&& acc)
 {
     int j0 = 0;
-    for (; j0 + kChunk <= width; j0 += kChunk) slot_piece<kChunk, ALIGNED, T>(v, cols, j0, gather, acc);
+    for (; j0 + kChunk <= width; j0 += kChunk) slot_piece<kChunk, ALIGNED, T, NT>(v, cols, j0, gather, acc);
     switch (width - j0) {
-    case 1: slot_piece<1, ALIGNED, T>(v, cols, j0, gather, acc); break;
-    case 2: slot_piece<2, ALIGNED, T>(v, cols, j0, gather, acc); break;
-    case 3: slot_piece<3, ALIGNED, T>(v, cols, j0, gather, acc); break;
-    case 4: slot_piece<4, ALIGNED, T>(v, cols, j0, gather, acc); break;
-    case 5: slot_piece<5, ALIGNED, T>(v, cols, j0, gather, acc); break;
-    case 6: slot_piece<6, ALIGNED, T>(v, cols, j0, gather, acc); break;
-    case 7: slot_piece<7, ALIGNED, T>(v, cols, j0, gather, acc); break;
+    case 1: slot_piece<1, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
+    case 2: slot_piece<2, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
+    case 3: slot_piece<3, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
+    case 4: slot_piece<4, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
+    case 5: slot_piece<5, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
+    case 6: slot_piece<6, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
+    case 7: slot_piece<7, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
     default: break;
     }
 }
 
+// stream: load the values nontemporally (offset-aligned slices only; a
+// packed slice's extra branch would push the pipelined product into spills).
 template <class T, class Gather, class Acc>
-__device__ __forceinline__ void slot_loop(const double* __restrict__ v, const SlotCols& cols, int width,
+__device__ __forceinline__ void slot_loop(const double* __restrict__ v, const SlotCols& cols, int width, bool stream,
                                           Gather&& gather, Acc&& acc)
 {
-    if (cols.off)
-        slot_loop_of<true, T>(v, cols, width, gather, acc);
-    else
-        slot_loop_of<false, T>(v, cols, width, gather, acc);
+    if (cols.off) {
+        if (stream)
+            slot_loop_of<true, T, true>(v, cols, width, gather, acc);
+        else
+            slot_loop_of<true, T, false>(v, cols, width, gather, acc);
+    } else {
+        slot_loop_of<false, T, false>(v, cols, width, gather, acc);
+    }
 }
 
 __device__ __forceinline__ SlotCols slot_cols(const SellView& A, int64_t slice, int lane, int64_t row64,
@@ -406,10 +415,10 @@ __device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int l
     const double* __restrict__ v = A.val + base + lane;
     double a0 = 0.0, a1 = 0.0;
     if (NX == 1) {
-        slot_loop<double>(v, cols, width, [&](int c) { return x0[c]; },
+        slot_loop<double>(v, cols, width, slice >= A.stream_from, [&](int c) { return x0[c]; },
                           [&](double a, double g) { a0 = fma(a, g, a0); });
     } else {
-        slot_loop<double2>(v, cols, width, [&](int c) { return make_double2(x0[c], x1[c]); },
+        slot_loop<double2>(v, cols, width, slice >= A.stream_from, [&](int c) { return make_double2(x0[c], x1[c]); },
                            [&](double a, double2 g) {
                                a0 = fma(a, g.x, a0);
                                a1 = fma(a, g.y, a1);
@@ -429,7 +438,7 @@ __device__ __forceinline__ void sell_row_pair(const SellView& A, int64_t slice, 
     const SlotCols cols = slot_cols(A, slice, lane, row64, base, width);
     const double* __restrict__ v = A.val + base + lane;
     double a0 = 0.0, a1 = 0.0;
-    slot_loop<double2>(v, cols, width, [&](int c) { return xy[c]; },
+    slot_loop<double2>(v, cols, width, slice >= A.stream_from, [&](int c) { return xy[c]; },
                        [&](double a, double2 g) {
                            a0 = fma(a, g.x, a0);
                            a1 = fma(a, g.y, a1);

@@ -51,7 +51,8 @@ class prcg_matrix_props(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("stored_entries", ctypes.c_int64),
                 ("format", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
-                ("aligned_slices_frac", ctypes.c_double), ("kernels", ctypes.c_int32), ("stage2", ctypes.c_int32)]
+                ("aligned_slices_frac", ctypes.c_double), ("kernels", ctypes.c_int32), ("stage2", ctypes.c_int32),
+                ("streamed_entries", ctypes.c_int64)]
 
 
 _VP = ctypes.c_void_p

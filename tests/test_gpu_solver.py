@@ -468,6 +468,45 @@ def test_ragged_full_scale_jacobi(prcg, torch_cuda, variant):
     M.close()
 
 
+@pytest.fixture(scope="module")
+def varcoef27_160():
+    return P.config3b()
+
+
+def test_streamed_values_product_full_scale(prcg, torch_cuda, varcoef27_160):
+    """The 27-point 160^3 matrix (885 MB of values) is read past its first
+    128 MiB with nontemporal loads: every row of the product, on both sides
+    of the first streamed slice, against the oracle's."""
+    pr = varcoef27_160
+    M = gpu_matrix(prcg, pr.A, "none", "auto")
+    props = M.props
+    cached = (128 << 20) // 8
+    assert 0 < props.streamed_entries < props.stored_entries
+    assert cached <= props.stored_entries - props.streamed_entries <= cached + 64 * 27
+    x = P.uniform_vector(pr.A.n, 31)
+    y = M.spmv(x).cpu().numpy()
+    yo = oracle.spmv(pr.A.row_ptr, pr.A.col_idx, pr.A.values, x)
+    scale = np.abs(pr.A.scipy()) @ np.abs(x)
+    assert np.all(np.abs(y - yo) <= (np.diff(pr.A.row_ptr) + 2) * EPS * scale)
+    M.close()
+    small = gpu_matrix(prcg, P.config2().A, "jacobi", "auto")
+    assert small.props.streamed_entries == 0  # 118 MB of values: all cached
+    small.close()
+
+
+@pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
+def test_streamed_values_solve_full_scale(prcg, torch_cuda, varcoef27_160, variant):
+    """The 27-point 160^3 workload in the default structure (streamed value
+    loads): x_15 and the first 15 residual norms against the oracle."""
+    pr = varcoef27_160
+    M = gpu_matrix(prcg, pr.A, "none", "auto")
+    x, info = M.solve(pr.b, variant, 0.0, 15, history=True)
+    ref = oracle_solve(pr.A, pr.b, variant, "none", 0.0, 15)
+    assert info.iters == 15 and hist_close(info.history, ref["history"])
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+    M.close()
+
+
 def test_auto_structure_by_size(prcg, torch_cuda):
     """The default structure is fused on SELL-64 problems of up to 1024
     workgroups (pipe-PR-CG: below 64) and two-pass (with stage 2 in its own
