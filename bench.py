@@ -129,7 +129,8 @@ def stream_triad(torch, n=64 * 1024 * 1024, reps=20):
 
 
 def batched_section(torch, prcg, problems, traffic):
-    """512 anisotropic systems in one persistent launch vs one prcg_solve per system."""
+    """512 anisotropic systems in one batched solve (the mode the solver picks;
+    both modes are timed) vs one prcg_solve per system."""
     A, offs, b, xs, eps = problems.config4()
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
@@ -144,6 +145,19 @@ def batched_section(torch, prcg, problems, traffic):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t) / reps
     nt, grid = B.config("pr")
+    mode = B.mode("pr")
+    per_mode = {}
+    for m in ("persistent", "lockstep"):
+        B.set_mode(m)
+        B.solve(bt, "pr", 1e-10, 20000)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, it_m, st_m = B.solve(bt, "pr", 1e-10, 20000)
+        torch.cuda.synchronize()
+        assert all(st == "ok" for st in st_m)
+        per_mode[m] = {"solves_per_s": (len(offs) - 1) / ((time.perf_counter() - t) / reps),
+                       "iterations_total": int(it_m.sum())}
     sizes = np.diff(offs)
     # algorithmic bytes: per system-iteration 10 vectors (PR two-pass, no preconditioner) + its matrix
     per_row_matrix = 8.0 * 5  # offset-aligned slices: 8 bytes per stored entry, 5 entries per row
@@ -168,7 +182,8 @@ def batched_section(torch, prcg, problems, traffic):
             "nnz_total": int(A.nnz), "batched_solves_per_s": len(sizes) / t_batch, "batched_ms": t_batch * 1e3,
             "sequential_solves_per_s": len(sizes) / t_seq, "sequential_ms": t_seq * 1e3,
             "speedup": t_seq / t_batch, "iterations_total": int(iters.sum()), "sequential_iterations": seq_iters,
-            "algorithmic_GBps": moved / t_batch / 1e9, "threads_per_workgroup": nt, "workgroups": grid}
+            "algorithmic_GBps": moved / t_batch / 1e9, "mode": mode, "modes": per_mode,
+            "threads_per_workgroup": nt, "workgroups": grid}
 
 
 def unrolled_pr_cg(torch, rows, cols, vals, b, iters):

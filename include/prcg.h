@@ -284,7 +284,10 @@ prcg_status prcg_create_batch(prcg_matrix blockdiag, int32_t nsys, const int64_t
  * iterations of every system under each candidate launch shape (threads per
  * workgroup x workgroups per compute unit), timed with HIP events; the
  * fastest is kept for the batch.  The persistent launch is captured in a
- * HIP graph.  Reductions are deterministic for a fixed configuration. */
+ * HIP graph.  For PR-CG and M-CG the first call also times one whole solve
+ * in the persistent mode and one in the lockstep mode (see
+ * prcg_batch_set_mode) and keeps the faster, unless a mode was set.
+ * Reductions are deterministic for a fixed configuration and mode. */
 prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, double* x, double tol,
                                int32_t maxit, int32_t* iters, int32_t* status);
 
@@ -294,6 +297,26 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
  * The environment variable PRCG_BATCH_CONFIG="threads,per_cu" (threads in
  * 256/512/1024, 1 <= per_cu <= 8) fixes it instead. */
 prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, int32_t* grid);
+
+/* How the batched solver runs PR-CG and M-CG (HS-CG and the pipelined
+ * variants always run persistent):
+ *   PRCG_BATCH_PERSISTENT  one persistent kernel, a workgroup per system;
+ *   PRCG_BATCH_LOCKSTEP    three launches per iteration over the row groups
+ *     (up to 256 rows of one system) of every system still running: the
+ *     vector update, the product with one partial per group of each inner
+ *     product, then one workgroup per system that sums its partials in a
+ *     fixed order and takes the scalar step (Alg. 2); the host checks every
+ *     16 iterations whether a system is still running;
+ *   PRCG_BATCH_AUTO (default)  the faster of the two on the first solve. */
+typedef enum { PRCG_BATCH_AUTO = 0, PRCG_BATCH_PERSISTENT = 1, PRCG_BATCH_LOCKSTEP = 2 } prcg_batch_mode_t;
+
+/* Request a mode (PRCG_BATCH_*) for later solves; forgets earlier choices.
+ * PRCG_EINVAL for an unknown mode. */
+prcg_status prcg_batch_set_mode(prcg_batch B, int32_t mode);
+
+/* The mode in use for variant v (PRCG_BATCH_PERSISTENT or _LOCKSTEP; 0
+ * before the first prcg_solve_batched with that variant). */
+prcg_status prcg_batch_mode(prcg_batch B, prcg_variant v, int32_t* mode);
 
 /*
  * Adjoint of a solve (not in the paper): for L(x) with x = A^{-1} b and

@@ -18,6 +18,27 @@ struct BatchView {
     int32_t nsys;
 };
 
+// Row groups of the lockstep solver: group g is up to four consecutive
+// slices of system grp_sys[g] from slice grp_slice0[g]; system s owns groups
+// [sys_grp0[s], sys_grp0[s+1]).
+struct GroupView {
+    const int32_t* grp_sys;     // [ngroups]
+    const int64_t* grp_slice0;  // [ngroups]
+    const int64_t* sys_grp0;    // [nsys + 1]
+    int64_t ngroups;
+};
+
+// Lockstep PR-CG / M-CG (variant kPR or kM): the initialisation (three
+// launches), then `iterations` iterations of three launches each and the
+// count of running systems into *active.  P: 6 * ngroups doubles; S: nsys
+// states.  All launches go on `st` and may be captured in a graph.
+hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const Vecs& v, const double* b, State* S,
+                                double* P, double tol, int maxit, int variant, int pre, int32_t* iters,
+                                int32_t* status, hipStream_t st);
+hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, const Vecs& v, State* S, double* P,
+                                      int iterations, int variant, int pre, int32_t* iters, int32_t* status,
+                                      int32_t* active, hipStream_t st);
+
 // Reset the queue and launch the persistent kernel (nt threads per
 // workgroup: 256, 512 or 1024; grid workgroups).  Both launches go on `st`
 // and may be captured in a graph.

@@ -188,6 +188,22 @@ struct prcg_batch_s {
     hipGraphExec_t graph[kNumVariants] = {};
     double graph_tol[kNumVariants] = {};
     int32_t graph_maxit[kNumVariants] = {};
+    int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
+    // lockstep solver (PR-CG, M-CG): row groups, per-system states, partials
+    int64_t ngroups = 0;
+    int32_t* grp_sys = nullptr;
+    int64_t* grp_slice0 = nullptr;
+    int64_t* sys_grp0 = nullptr;
+    State* lstate = nullptr;
+    double* lpart = nullptr;   // 6 * ngroups
+    int32_t* lactive = nullptr;
+    int32_t* hactive = nullptr;  // pinned, two slots
+    hipEvent_t lev[2] = {nullptr, nullptr};
+    hipGraphExec_t ls_graph[kNumVariants] = {};
+    int32_t mode_req = PRCG_BATCH_AUTO;
+    int32_t mode[3] = {0, 0, 0};  // per kind: 0 undecided, else PRCG_BATCH_PERSISTENT / _LOCKSTEP
+
+    GroupView groups() const { return GroupView{grp_sys, grp_slice0, sys_grp0, ngroups}; }
 
     Vecs vecs_view() const
     {
@@ -212,6 +228,7 @@ struct prcg_batch_s {
     {
         BatchView b;
         b.A = SellView{slice_ptr, slice_meta, soff, scol, sval, A->n, nslices};
+        b.A.stream_from = stream_from;
         b.slice_row0 = slice_row0;
         b.slice_nrows = slice_nrows;
         b.sys_row0 = sys_row0;
@@ -230,8 +247,14 @@ void free_batch(prcg_batch B)
     (void)hipSetDevice(B->A->device);
     for (auto& g : B->graph)
         if (g) (void)hipGraphExecDestroy(g);
+    for (auto& g : B->ls_graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& e : B->lev)
+        if (e) (void)hipEventDestroy(e);
+    if (B->hactive) (void)hipHostFree(B->hactive);
     void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
-                   B->slice_meta, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status};
+                   B->slice_meta, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
+                   B->grp_sys, B->grp_slice0, B->sys_grp0, B->lstate, B->lpart, B->lactive};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     delete B;
@@ -897,6 +920,35 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         if (aligned[q]) noff += width[q];
     }
     B->stored = hptr[ns];
+    for (int64_t q = 0; q < ns; ++q)
+        if (hptr[q + 1] * (int64_t)sizeof(double) > kCachedValueBytes) {
+            B->stream_from = q + 1;
+            break;
+        }
+    // row groups of the lockstep solver: up to four slices of one system
+    std::vector<int32_t> grp_sys;
+    std::vector<int64_t> grp_slice0, sys_grp0((size_t)nsys + 1);
+    for (int32_t q = 0; q < nsys; ++q) {
+        sys_grp0[q] = (int64_t)grp_sys.size();
+        for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1]; s0 += kWaves) {
+            grp_sys.push_back(q);
+            grp_slice0.push_back(s0);
+        }
+    }
+    sys_grp0[nsys] = (int64_t)grp_sys.size();
+    B->ngroups = sys_grp0[nsys];
+    BTRY(hipMalloc(&B->grp_sys, sizeof(int32_t) * B->ngroups));
+    BTRY(hipMalloc(&B->grp_slice0, sizeof(int64_t) * B->ngroups));
+    BTRY(hipMalloc(&B->sys_grp0, sizeof(int64_t) * (nsys + 1)));
+    BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
+    BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * B->ngroups));
+    BTRY(hipMalloc(&B->lactive, sizeof(int32_t) * 4));
+    BTRY(hipHostMalloc(&B->hactive, sizeof(int32_t) * 2, hipHostMallocDefault));
+    BTRY(hipEventCreateWithFlags(&B->lev[0], hipEventDisableTiming));
+    BTRY(hipEventCreateWithFlags(&B->lev[1], hipEventDisableTiming));
+    BTRY(hipMemcpyAsync(B->grp_sys, grp_sys.data(), sizeof(int32_t) * B->ngroups, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->grp_slice0, grp_slice0.data(), sizeof(int64_t) * B->ngroups, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->sys_grp0, sys_grp0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
     BTRY(hipMalloc(&B->slice_ptr, sizeof(int64_t) * (ns + 1)));
     BTRY(hipMalloc(&B->slice_meta, sizeof(int32_t) * ns));
     BTRY(hipMalloc(&B->soff, sizeof(int32_t) * std::max<int64_t>(noff, 1)));
@@ -943,6 +995,46 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
     const BatchView view = B->view();
     const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
     HIP_TRY(hipMemcpyAsync(bvec, b, nb, hipMemcpyDeviceToDevice, st));
+    // lockstep solve of the batch in vv.x (PR-CG, M-CG): the initialisation,
+    // then graphs of kLockstepChunk iterations until no system is running;
+    // the count of a chunk is read while the next chunk runs.  Every system
+    // is done after maxit iterations, so the chunk count is bounded.
+    constexpr int kLockstepChunk = 16;
+    const GroupView gv = B->groups();
+    auto run_lockstep = [&]() -> hipError_t {
+        hipError_t e = launch_lockstep_init(view, gv, vv, bvec, B->lstate, B->lpart, tol, maxit, v, A->precond,
+                                            B->iters, B->status, st);
+        if (e != hipSuccess) return e;
+        if (!B->ls_graph[v]) {
+            e = hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            hipError_t e1 = launch_lockstep_iterations(view, gv, vv, B->lstate, B->lpart, kLockstepChunk, v,
+                                                       A->precond, B->iters, B->status, B->lactive, A->capture);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(A->capture, &g);
+            hipError_t e3 = (e1 == hipSuccess && e2 == hipSuccess) ? hipGraphInstantiate(&B->ls_graph[v], g, nullptr,
+                                                                                         nullptr, 0)
+                                                                   : (e1 != hipSuccess ? e1 : e2);
+            if (g) (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess) {
+                B->ls_graph[v] = nullptr;
+                return e3;
+            }
+        }
+        const int64_t chunks = (int64_t)maxit / kLockstepChunk + 2;
+        for (int64_t c = 0; c < chunks; ++c) {
+            if ((e = hipGraphLaunch(B->ls_graph[v], st)) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(B->hactive + (c & 1), B->lactive, sizeof(int32_t), hipMemcpyDeviceToHost, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = hipEventRecord(B->lev[c & 1], st)) != hipSuccess) return e;
+            if (c > 0) {
+                if ((e = hipEventSynchronize(B->lev[(c - 1) & 1])) != hipSuccess) return e;
+                if (B->hactive[(c - 1) & 1] == 0) break;
+            }
+        }
+        return hipSuccess;
+    };
     // autotune once per kind: workgroup size x workgroups per CU, timed on a
     // short run of this batch (tol = 0, a few iterations per system)
     if (B->tuned_nt[kind] == 0) {
@@ -979,27 +1071,62 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
             (void)hipEventDestroy(e1);
         }
     }
-    // one graph per (kind, variant, tol, maxit): reset the queue + persistent kernel
-    if (!B->graph[v] || B->graph_tol[v] != tol || B->graph_maxit[v] != maxit) {
-        if (B->graph[v]) (void)hipGraphExecDestroy(B->graph[v]);
-        B->graph[v] = nullptr;
-        HIP_TRY(hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal));
-        hipError_t err = launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
-                                      B->tuned_grid[kind], B->queue, B->iters, B->status, A->capture);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(A->capture, &g);
-        if (err != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(PRCG_EDEVICE, "batched graph capture failed");
+    // persistent or lockstep: PR-CG and M-CG time one whole solve of each on
+    // this batch (the persistent kernel's tail, where a few large systems
+    // run on one workgroup each, is what lockstep avoids)
+    if (B->mode[kind] == 0) {
+        if (kind != 1 || B->mode_req == PRCG_BATCH_PERSISTENT) {
+            B->mode[kind] = PRCG_BATCH_PERSISTENT;
+        } else if (B->mode_req == PRCG_BATCH_LOCKSTEP) {
+            B->mode[kind] = PRCG_BATCH_LOCKSTEP;
+        } else {
+            hipEvent_t e0, e1;
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            float ms[2] = {0.f, 0.f};
+            for (int m = 0; m < 2; ++m) {
+                HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipEventRecord(e0, st));
+                if (m == 0)
+                    HIP_TRY(launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
+                                         B->tuned_grid[kind], B->queue, B->iters, B->status, st));
+                else
+                    HIP_TRY(run_lockstep());
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                HIP_TRY(hipEventElapsedTime(&ms[m], e0, e1));
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            B->mode[kind] = ms[1] < ms[0] ? PRCG_BATCH_LOCKSTEP : PRCG_BATCH_PERSISTENT;
         }
-        hipError_t e3 = hipGraphInstantiate(&B->graph[v], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIP_TRY(e3);
-        B->graph_tol[v] = tol;
-        B->graph_maxit[v] = maxit;
     }
-    HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipGraphLaunch(B->graph[v], st));
+    if (B->mode[kind] == PRCG_BATCH_LOCKSTEP) {
+        HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(run_lockstep());
+    } else {
+        // one graph per (kind, variant, tol, maxit): reset the queue + persistent kernel
+        if (!B->graph[v] || B->graph_tol[v] != tol || B->graph_maxit[v] != maxit) {
+            if (B->graph[v]) (void)hipGraphExecDestroy(B->graph[v]);
+            B->graph[v] = nullptr;
+            HIP_TRY(hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal));
+            hipError_t err = launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
+                                          B->tuned_grid[kind], B->queue, B->iters, B->status, A->capture);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(A->capture, &g);
+            if (err != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(PRCG_EDEVICE, "batched graph capture failed");
+            }
+            hipError_t e3 = hipGraphInstantiate(&B->graph[v], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(e3);
+            B->graph_tol[v] = tol;
+            B->graph_maxit[v] = maxit;
+        }
+        HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipGraphLaunch(B->graph[v], st));
+    }
     HIP_TRY(hipMemcpyAsync(x, vv.x, nb, hipMemcpyDeviceToDevice, st));
     std::vector<int32_t> hst((size_t)B->nsys);
     HIP_TRY(hipMemcpyAsync(hst.data(), B->status, sizeof(int32_t) * B->nsys, hipMemcpyDeviceToHost, st));
@@ -1018,6 +1145,23 @@ prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, in
     const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
     *threads = B->tuned_nt[kind];
     *grid = B->tuned_grid[kind];
+    return PRCG_OK;
+}
+
+prcg_status prcg_batch_set_mode(prcg_batch B, int32_t mode)
+{
+    if (!B) return fail(PRCG_EINVAL, "null batch");
+    if (mode < PRCG_BATCH_AUTO || mode > PRCG_BATCH_LOCKSTEP) return fail(PRCG_EINVAL, "unknown batch mode");
+    B->mode_req = mode;
+    for (auto& m : B->mode) m = 0;
+    return PRCG_OK;
+}
+
+prcg_status prcg_batch_mode(prcg_batch B, prcg_variant v, int32_t* mode)
+{
+    if (!B || !mode) return fail(PRCG_EINVAL, "null argument");
+    if (check_batch_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    *mode = B->mode[v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2];
     return PRCG_OK;
 }
 

@@ -30,10 +30,12 @@ STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "enomem
 KERNELS = {"fused": 0, "two_pass": 1, "two_pass_stage2": 2, "textbook": 3, "two_pass_last": 4,
            "two_pass_redundant": 5, "auto": 6}
 OPT_KERNELS, OPT_GRID = 0, 1
+BATCH_MODES = {"auto": 0, "persistent": 1, "lockstep": 2}
 
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
             "prcg_time_kernels", "prcg_get_props", "prcg_create_batch", "prcg_solve_batched",
-            "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config")
+            "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config",
+            "prcg_batch_set_mode", "prcg_batch_mode")
 
 
 class PrcgError(RuntimeError):
@@ -90,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "prcg_batch_destroy": (None, [_VP]),
         "prcg_last_error": (ctypes.c_char_p, []),
         "prcg_batch_config": (i32, [_VP, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "prcg_batch_set_mode": (i32, [_VP, i32]),
+        "prcg_batch_mode": (i32, [_VP, i32, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -167,6 +171,16 @@ def prcg_batch_config(B, variant):
     t, g = ctypes.c_int32(0), ctypes.c_int32(0)
     _check(load_library().prcg_batch_config(B, variant, ctypes.byref(t), ctypes.byref(g)))
     return t.value, g.value
+
+
+def prcg_batch_set_mode(B, mode):
+    _check(load_library().prcg_batch_set_mode(B, mode))
+
+
+def prcg_batch_mode(B, variant) -> int:
+    m = ctypes.c_int32(0)
+    _check(load_library().prcg_batch_mode(B, variant, ctypes.byref(m)))
+    return m.value
 
 
 def prcg_adjoint(A, variant, x, gx, gb, gvals, tol, maxit, info=None) -> int:
@@ -343,3 +357,12 @@ class Batch:
 
     def config(self, variant: str = "pr"):
         return prcg_batch_config(self.handle, VARIANTS[variant])
+
+    def set_mode(self, mode: str):
+        """'auto' (the faster on the first solve), 'persistent' or 'lockstep'."""
+        prcg_batch_set_mode(self.handle, BATCH_MODES[mode])
+
+    def mode(self, variant: str = "pr"):
+        """The mode in use for a variant, or None before its first solve."""
+        m = prcg_batch_mode(self.handle, VARIANTS[variant])
+        return {v: k for k, v in BATCH_MODES.items()}.get(m) if m else None

@@ -63,3 +63,4 @@ def test_binding_constants_match_the_header():
     for key, code in prcg.VARIANTS.items():
         assert variants["PRCG_" + key.upper()] == code, key
     assert header_enum("prcg_precond") == {"PRCG_PRECOND_" + k.upper(): v for k, v in prcg.PRECONDS.items()}
+    assert header_enum("prcg_batch_mode_t") == {"PRCG_BATCH_" + k.upper(): v for k, v in prcg.BATCH_MODES.items()}

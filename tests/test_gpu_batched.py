@@ -1,6 +1,7 @@
-"""GPU parity of the batched persistent solver against the oracle, system by
-system: at the GPU's iteration count the solution matches the oracle to
-1e-10 relative, the stopping iteration agrees to +-1 and the status agrees."""
+"""GPU parity of the batched solver (persistent and lockstep modes) against
+the oracle, system by system: at the GPU's iteration count the solution
+matches the oracle to 1e-10 relative, the stopping iteration agrees to +-1
+and the status agrees."""
 import numpy as np
 import pytest
 
@@ -112,6 +113,71 @@ def test_zero_block_and_maxit(prcg, monkeypatch):
     assert all(st == "not_converged" for s, st in enumerate(status) if s != 2)
 
 
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+@pytest.mark.parametrize("variant", ["pr", "m"])
+def test_lockstep_matches_oracle(prcg, variant, precond):
+    A, offs, b, mats, bs = small_batch()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
+    B = prcg.Batch(M, offs)
+    B.set_mode("lockstep")
+    x, iters, status = B.solve(b, variant, 1e-10, 5000)
+    assert B.mode(variant) == "lockstep"
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, variant, precond, 1e-10)
+
+
+def test_lockstep_packed_tiny_and_ragged_groups(prcg):
+    """Packed slices next to offset-aligned ones, systems of one to five
+    slices (row groups of one to four slices, partial last slices) in
+    lockstep: each system against the oracle."""
+    mats = [P.random_spd(700 + 173 * s, 5.0, 20 + s) for s in range(3)]
+    mats += [P.batch_system(s, 64, 3000)[0] for s in range(3)]
+    mats += [P.poisson2d(3), P.random_spd(40, 3.0, 9), P.poisson2d(16, 20)]
+    bs = [P.uniform_vector(A.n, 30 + s) for s, A in enumerate(mats)]
+    A, offs = P.block_diag(mats)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    B = prcg.Batch(M, offs)
+    B.set_mode("lockstep")
+    x, iters, status = B.solve(np.concatenate(bs), "pr", 1e-10, 5000)
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", "jacobi", 1e-10)
+
+
+def test_lockstep_zero_block_maxit_x0_and_repeatability(prcg):
+    A, offs, b, mats, bs = small_batch(5)
+    b = b.copy()
+    b[offs[2]:offs[3]] = 0.0
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    B.set_mode("lockstep")
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000, x0=np.ones(A.n))
+    x = x.cpu().numpy()
+    assert iters[2] == 0 and status[2] == "ok" and np.all(x[offs[2]:offs[3]] == 0.0)
+    x2, iters2, _ = B.solve(b, "pr", 1e-10, 5000, x0=np.ones(A.n))
+    assert np.array_equal(x, x2.cpu().numpy()) and np.array_equal(iters, iters2)
+    x, iters, status = B.solve(b, "pr", 0.0, 7)  # not a multiple of the 16-iteration chunk
+    assert all(int(k) == 7 for s, k in enumerate(iters) if s != 2)
+    assert all(st == "not_converged" for s, st in enumerate(status) if s != 2)
+    x, iters, status = B.solve(b, "pr", 0.0, 0)
+    assert np.all(iters == 0)
+    xs, _, _ = B.solve(b, "pr", 1e-10, 5000)
+    x, iters, status = B.solve(b, "pr", 1e-6, 5000, x0=xs)
+    assert np.all(iters == 0) and all(st == "ok" for st in status)
+
+
+def test_mode_selection(prcg):
+    A, offs, b, mats, bs = small_batch(4)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    assert B.mode("pr") is None
+    B.solve(b, "pr", 1e-10, 5000)
+    assert B.mode("pr") in ("persistent", "lockstep") and B.mode("m") == B.mode("pr")
+    B.set_mode("lockstep")
+    assert B.mode("pr") is None
+    B.solve(b, "hs", 1e-10, 5000)
+    assert B.mode("hs") == "persistent"  # HS-CG has no lockstep mode
+    with pytest.raises(prcg.PrcgError):
+        prcg.prcg_batch_set_mode(B.handle, 3)
+
+
 def test_block_structure_is_checked(prcg):
     A, offs, b, mats, bs = small_batch(3)
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
@@ -123,14 +189,22 @@ def test_block_structure_is_checked(prcg):
         prcg.Batch(M, offs[::-1].copy())
 
 
-def test_full_batched_workload_sampled(prcg):
-    """All 512 systems (n from 1k to 64k) in one launch; the oracle checks the
+@pytest.fixture(scope="module")
+def batch512():
+    return P.config4()
+
+
+@pytest.mark.parametrize("mode", ["persistent", "lockstep"])
+def test_full_batched_workload_sampled(prcg, batch512, mode):
+    """All 512 systems (n from 1k to 64k) in one solve; the oracle checks the
     largest, the smallest and two more systems; every system's true residual
     is checked on the host."""
-    A, offs, b, xstar, eps = P.config4()
+    A, offs, b, xstar, eps = batch512
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
+    B.set_mode(mode)
     x, iters, status = B.solve(b, "pr", 1e-10, 20000)
+    assert B.mode("pr") == mode
     x = x.cpu().numpy()
     assert all(st == "ok" for st in status)
     sizes = np.diff(offs)
