@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libprcg.so")
-SOURCES = ["kernels_setup.hip", "kernels_iter.hip", "kernels_fused.hip", "kernels_textbook.hip", "batched.hip", "batched_lockstep.hip", "prcg_api.hip"]
+SOURCES = ["kernels_setup.hip", "kernels_iter.hip", "kernels_fused.hip", "kernels_textbook.hip", "batched.hip", "prcg_api.hip"]
 ARCH = os.environ.get("PRCG_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -18,13 +18,23 @@ struct BatchView {
     int32_t nsys;
 };
 
-// Row groups of the lockstep solver: group g is up to four consecutive
-// slices of system grp_sys[g] from slice grp_slice0[g]; system s owns groups
-// [sys_grp0[s], sys_grp0[s+1]).
+// Row groups of the lockstep solver: up to kLockstepSlices consecutive
+// slices (rows row0 .. row0 + nrows - 1) of one system; system s owns groups
+// [sys_grp0[s], sys_grp0[s+1]).  One 32-byte record per group, so a
+// workgroup learns everything about its group in one round trip.
+constexpr int kLockstepSlices = 16;
+struct Group {
+    int64_t slice0;
+    int64_t row0;
+    int32_t sys;
+    int32_t nsl;
+    int32_t nrows;
+    int32_t spare;
+};
+static_assert(sizeof(Group) == 32, "two 16-byte loads per group");
 struct GroupView {
-    const int32_t* grp_sys;     // [ngroups]
-    const int64_t* grp_slice0;  // [ngroups]
-    const int64_t* sys_grp0;    // [nsys + 1]
+    const Group* grp;          // [ngroups]
+    const int64_t* sys_grp0;   // [nsys + 1]
     int64_t ngroups;
 };
 

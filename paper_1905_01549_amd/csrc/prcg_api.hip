@@ -191,8 +191,7 @@ struct prcg_batch_s {
     int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
     // lockstep solver (PR-CG, M-CG): row groups, per-system states, partials
     int64_t ngroups = 0;
-    int32_t* grp_sys = nullptr;
-    int64_t* grp_slice0 = nullptr;
+    Group* grp = nullptr;
     int64_t* sys_grp0 = nullptr;
     State* lstate = nullptr;
     double* lpart = nullptr;   // 6 * ngroups
@@ -203,7 +202,7 @@ struct prcg_batch_s {
     int32_t mode_req = PRCG_BATCH_AUTO;
     int32_t mode[3] = {0, 0, 0};  // per kind: 0 undecided, else PRCG_BATCH_PERSISTENT / _LOCKSTEP
 
-    GroupView groups() const { return GroupView{grp_sys, grp_slice0, sys_grp0, ngroups}; }
+    GroupView groups() const { return GroupView{grp, sys_grp0, ngroups}; }
 
     Vecs vecs_view() const
     {
@@ -254,7 +253,7 @@ void free_batch(prcg_batch B)
     if (B->hactive) (void)hipHostFree(B->hactive);
     void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
                    B->slice_meta, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
-                   B->grp_sys, B->grp_slice0, B->sys_grp0, B->lstate, B->lpart, B->lactive};
+                   B->grp, B->sys_grp0, B->lstate, B->lpart, B->lactive};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     delete B;
@@ -925,20 +924,25 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
             B->stream_from = q + 1;
             break;
         }
-    // row groups of the lockstep solver: up to four slices of one system
-    std::vector<int32_t> grp_sys;
-    std::vector<int64_t> grp_slice0, sys_grp0((size_t)nsys + 1);
+    // row groups of the lockstep solver: up to kLockstepSlices slices of one system
+    std::vector<Group> grp;
+    std::vector<int64_t> sys_grp0((size_t)nsys + 1);
     for (int32_t q = 0; q < nsys; ++q) {
-        sys_grp0[q] = (int64_t)grp_sys.size();
-        for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1]; s0 += kWaves) {
-            grp_sys.push_back(q);
-            grp_slice0.push_back(s0);
+        sys_grp0[q] = (int64_t)grp.size();
+        for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1]; s0 += kLockstepSlices) {
+            Group G{};
+            G.slice0 = s0;
+            G.nsl = (int32_t)std::min<int64_t>(kLockstepSlices, sys_slice0[q + 1] - s0);
+            G.row0 = slice_row0[(size_t)s0];
+            const int64_t last = s0 + G.nsl - 1;
+            G.nrows = (int32_t)(slice_row0[(size_t)last] + slice_nrows[(size_t)last] - G.row0);
+            G.sys = q;
+            grp.push_back(G);
         }
     }
-    sys_grp0[nsys] = (int64_t)grp_sys.size();
+    sys_grp0[nsys] = (int64_t)grp.size();
     B->ngroups = sys_grp0[nsys];
-    BTRY(hipMalloc(&B->grp_sys, sizeof(int32_t) * B->ngroups));
-    BTRY(hipMalloc(&B->grp_slice0, sizeof(int64_t) * B->ngroups));
+    BTRY(hipMalloc(&B->grp, sizeof(Group) * B->ngroups));
     BTRY(hipMalloc(&B->sys_grp0, sizeof(int64_t) * (nsys + 1)));
     BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
     BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * B->ngroups));
@@ -946,8 +950,7 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     BTRY(hipHostMalloc(&B->hactive, sizeof(int32_t) * 2, hipHostMallocDefault));
     BTRY(hipEventCreateWithFlags(&B->lev[0], hipEventDisableTiming));
     BTRY(hipEventCreateWithFlags(&B->lev[1], hipEventDisableTiming));
-    BTRY(hipMemcpyAsync(B->grp_sys, grp_sys.data(), sizeof(int32_t) * B->ngroups, hipMemcpyHostToDevice, st));
-    BTRY(hipMemcpyAsync(B->grp_slice0, grp_slice0.data(), sizeof(int64_t) * B->ngroups, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->grp, grp.data(), sizeof(Group) * B->ngroups, hipMemcpyHostToDevice, st));
     BTRY(hipMemcpyAsync(B->sys_grp0, sys_grp0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
     BTRY(hipMalloc(&B->slice_ptr, sizeof(int64_t) * (ns + 1)));
     BTRY(hipMalloc(&B->slice_meta, sizeof(int32_t) * ns));
