@@ -128,6 +128,17 @@ def stream_triad(torch, n=64 * 1024 * 1024, reps=20):
     return 3 * 8 * n / sec / 1e9
 
 
+def device_facts(torch):
+    """The properties the design assumes, as the runtime reports them."""
+    pr = torch.cuda.get_device_properties(0)
+    facts = {"name": pr.name, "arch": getattr(pr, "gcnArchName", None),
+             "compute_units": pr.multi_processor_count, "memory_GiB": round(pr.total_memory / 2 ** 30, 1)}
+    l2 = getattr(pr, "L2_cache_size", None)
+    if l2:
+        facts["l2_MiB"] = round(l2 / 2 ** 20, 2)
+    return facts
+
+
 def batched_section(torch, prcg, problems, traffic):
     """512 anisotropic systems in one batched solve (the mode the solver picks;
     both modes are timed) vs one prcg_solve per system."""
@@ -463,6 +474,7 @@ def main():
         "hbm_GBps_algorithmic": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"],
         "hbm_frac": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"] / HBM_PEAK_GBS,
         "stream_triad_GBps": triad,
+        "device": device_facts(torch),
         "frac_of_stream_triad": {"iteration": variants[f"{args.variant}/{args.kernels}"]["algorithmic_GBps"] / triad,
                                  roofline["kernel"]: roofline["achieved"] / triad},
         "variants": variants,
