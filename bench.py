@@ -48,6 +48,8 @@ def parse():
                     help="only time the flagship variant's kernels (the launches the roofline uses)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched workload (both modes; one JSON line)")
     ap.add_argument("--suite", action="store_true",
                     help="per-iteration times of every variant on every workload (one JSON line each)")
     return ap.parse_args()
@@ -330,6 +332,9 @@ def main():
     torch.cuda.set_device(0)
     if args.suite:
         suite(torch, prcg, problems)
+        return
+    if args.batched_only:
+        print(json.dumps(batched_section(torch, prcg, problems, traffic)), flush=True)
         return
     pr = problems.config2(m=args.m)
     A = pr.A
