@@ -76,15 +76,15 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
     // the metadata of the next group of slices is loaded while the current
     // group is multiplied
     struct Meta {
-        int64_t base[Q], end[Q], row0[Q];
-        int meta[Q], nrows[Q];
+        int64_t base[Q], row0[Q];
+        int meta[Q], nrows[Q], shape[Q];
     };
     auto load_meta = [&](int64_t s0, Meta& m) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int64_t sq = s0 + (int64_t)q * NW;
             m.base[q] = A.slice_ptr[sq];
-            m.end[q] = A.slice_ptr[sq + 1];
+            m.shape[q] = A.slice_shape[sq];
             m.meta[q] = A.slice_meta[sq];
             m.row0[q] = B.slice_row0[sq];
             m.nrows[q] = B.slice_nrows[sq];
@@ -104,10 +104,11 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             sq[q] = sl + (int64_t)q * NW;
-            width[q] = (int)((cur.end[q] - cur.base[q]) >> 6);
+            width[q] = shape_width(cur.shape[q]);
             row[q] = cur.row0[q] + lane;
             valid[q] = lane < cur.nrows[q];
-            group = group && cur.meta[q] >= 0 && width[q] == width[0];
+            // (slices stored singly: slot stride 64, as aligned_group reads them)
+            group = group && cur.meta[q] >= 0 && width[q] == width[0] && shape_stride(cur.shape[q]) == kSlice;
         }
         group = group && width[0] >= 1 && width[0] <= kWMax;
         double y0[Q], y1[Q];

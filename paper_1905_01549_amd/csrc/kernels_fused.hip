@@ -50,15 +50,17 @@ struct SlotIter {
     const int32_t* col;   // packed: column of the first slot of this lane
     const double* val;
     int row, last;
-    __device__ __forceinline__ double value(int j) const { return val[(int64_t)j * 64]; }
+    int stride;  // elements between consecutive slots of a row
 };
 
 __device__ __forceinline__ SlotIter slots_of(const SellView& A, int64_t slice, int lane, int64_t row, int& width)
 {
     const int64_t base = A.slice_ptr[slice];
-    width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
+    const int32_t shape = A.slice_shape[slice];
+    width = shape_width(shape);
     const int meta = A.slice_meta[slice];
     SlotIter it;
+    it.stride = shape_stride(shape);
     it.off = meta >= 0 ? A.soff + meta : nullptr;
     it.col = A.col + base + lane;
     it.val = A.val + base + lane;
@@ -75,9 +77,15 @@ __device__ __forceinline__ SlotIter slots_of(const SellView& A, int64_t slice, i
 // in flight together.
 constexpr int kFusedPiece = 4;
 
-template <int K, bool ALIGNED, class F>
+// UNIT: every slice is stored singly (slot stride 64, a constant the loads
+// fold into their offsets), as in the matrices the fused structure is chosen
+// for by default; the kernels are built both ways and the launcher picks
+// (measured: a runtime stride made the fused PR-CG iteration of the
+// 884,736-row problem 7% slower).
+template <int K, bool ALIGNED, bool UNIT, class F>
 __device__ __forceinline__ void fused_piece(const SlotIter& it, int j0, F&& f)
 {
+    const int64_t stride = UNIT ? kSlice : it.stride;
     int c[K];
     double a[K];
     if constexpr (ALIGNED) {
@@ -88,34 +96,34 @@ __device__ __forceinline__ void fused_piece(const SlotIter& it, int j0, F&& f)
         for (int u = 0; u < K; ++u) c[u] = min(max(it.row + o[u], 0), it.last);
     } else {
 #pragma unroll
-        for (int u = 0; u < K; ++u) c[u] = it.col[(int64_t)(j0 + u) * 64];
+        for (int u = 0; u < K; ++u) c[u] = it.col[(j0 + u) * stride];
     }
 #pragma unroll
-    for (int u = 0; u < K; ++u) a[u] = it.value(j0 + u);
+    for (int u = 0; u < K; ++u) a[u] = it.val[(j0 + u) * stride];
 #pragma unroll
     for (int u = 0; u < K; ++u) f(c[u], a[u]);
 }
 
-template <bool ALIGNED, class F>
+template <bool ALIGNED, bool UNIT, class F>
 __device__ __forceinline__ void fused_slots_of(const SlotIter& it, int width, F&& f)
 {
     int j0 = 0;
-    for (; j0 + kFusedPiece <= width; j0 += kFusedPiece) fused_piece<kFusedPiece, ALIGNED>(it, j0, f);
+    for (; j0 + kFusedPiece <= width; j0 += kFusedPiece) fused_piece<kFusedPiece, ALIGNED, UNIT>(it, j0, f);
     switch (width - j0) {
-    case 1: fused_piece<1, ALIGNED>(it, j0, f); break;
-    case 2: fused_piece<2, ALIGNED>(it, j0, f); break;
-    case 3: fused_piece<3, ALIGNED>(it, j0, f); break;
+    case 1: fused_piece<1, ALIGNED, UNIT>(it, j0, f); break;
+    case 2: fused_piece<2, ALIGNED, UNIT>(it, j0, f); break;
+    case 3: fused_piece<3, ALIGNED, UNIT>(it, j0, f); break;
     default: break;
     }
 }
 
-template <class F>
+template <bool UNIT, class F>
 __device__ __forceinline__ void fused_slots(const SlotIter& it, int width, F&& f)
 {
     if (it.off)
-        fused_slots_of<true>(it, width, f);
+        fused_slots_of<true, UNIT>(it, width, f);
     else
-        fused_slots_of<false>(it, width, f);
+        fused_slots_of<false, UNIT>(it, width, f);
 }
 
 // PR-CG, one kernel per iteration (Alg. 2):
@@ -123,7 +131,7 @@ __device__ __forceinline__ void fused_slots(const SlotIter& it, int width, F&& f
 //   s' = A p' with p' at neighbour j recomputed from p, s, r~ (and d);
 //   partials of mu, sigma, gamma, nu (+ <r, r>) for the next kernel.
 // Double-buffered: p, s, r~ (r~ is r without a preconditioner).
-template <bool PRE>
+template <bool PRE, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const State* __restrict__ in,
                                                      State* __restrict__ out, double* __restrict__ hist,
                                                      const double* __restrict__ Pin, double* __restrict__ Pout,
@@ -174,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const
         int width;
         const SlotIter it = slots_of(S, slice, lane, i, width);
         double sn = 0.0;
-        fused_slots(it, width, [&](int c, double a) {
+        fused_slots<UNIT>(it, width, [&](int c, double a) {
             const double sc = s_o[c];
             const double tc = t_o[c];
             const double pc = p_o[c];
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_fused(SellView S, Split sp, const
 // own row, the inner products, then u' = A s~' and w' = A r~' with s~' and
 // r~' at neighbour j recomputed from r~, s~, w, u (and d).  Double-buffered:
 // r~, s~, w, u (r~ = r and s~ = s without a preconditioner).
-template <bool PRE>
+template <bool PRE, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, const State* __restrict__ in,
                                                        State* __restrict__ out, double* __restrict__ hist,
                                                        const double* __restrict__ Pin, double* __restrict__ Pout,
@@ -262,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, con
         int width;
         const SlotIter it = slots_of(S, slice, lane, i, width);
         double un = 0.0, wn = 0.0;
-        fused_slots(it, width, [&](int c, double a) {
+        fused_slots<UNIT>(it, width, [&](int c, double a) {
             const double tc = t_o[c], zc = z_o[c], wc = w_o[c], uc = u_o[c];
             double tnc, znc;
             if (PRE) {
@@ -287,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_fused(SellView S, Split sp, con
 // HS-CG, second kernel of an iteration: stage 2 of nu (beta, tests), then
 // s = A p' with p' = r~ + beta p at neighbours from r (final in this kernel)
 // and the previous p; writes p' (double-buffered) and s; partials of mu.
-template <bool PRE>
+template <bool PRE, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_hs_fused(SellView S, Split sp, const State* __restrict__ in,
                                                      State* __restrict__ out, double* __restrict__ hist,
                                                      const double* __restrict__ PU, double* __restrict__ PS,
@@ -329,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_fused(SellView S, Split sp, const
         int width;
         const SlotIter it = slots_of(S, slice, lane, i, width);
         double sn = 0.0;
-        fused_slots(it, width, [&](int c, double a) {
+        fused_slots<UNIT>(it, width, [&](int c, double a) {
             const double rc = r[c];
             sn = fma(a, fma(beta, p_o[c], PRE ? d[c] * rc : rc), sn);
         });
@@ -360,27 +368,24 @@ hipError_t launch_fused_kernel(int variant, int pre, int j, int it, int& cur, co
         return hipGetLastError();
     };
     hipError_t e = hipSuccess;
-    if (is_pr_family(variant)) {
-        e = pre ? go(k_pr_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], form, f, q)
-                : go(k_pr_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], form, f, q);
-        cur = nxt;
-    } else if (variant == kPipePR || variant == kPipeM) {
-        e = pre ? go(k_pipe_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], form, f, q)
-                : go(k_pipe_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
-                     Pq[1 - q], form, f, q);
-        cur = nxt;
-    } else {
+    const bool unit = S.runs == 0;
+    auto pick = [&](auto P, auto U) -> hipError_t {
+        constexpr bool PR = decltype(P)::value, UN = decltype(U)::value;
+        if (is_pr_family(variant))
+            return go(k_pr_fused<PR, UN>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
+                      Pq[1 - q], form, f, q);
+        if (variant == kPipePR || variant == kPipeM)
+            return go(k_pipe_fused<PR, UN>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)Pq[q],
+                      Pq[1 - q], form, f, q);
         // HS: the first kernel is the two-pass k_hs_xr on the current buffers
-        if (j == 0) return hipErrorInvalidValue;
-        e = pre ? go(k_hs_fused<true>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)B.PU, B.PS,
-                     f, q)
-                : go(k_hs_fused<false>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)B.PU, B.PS,
-                     f, q);
-        cur = nxt;
-    }
+        return go(k_hs_fused<PR, UN>, S, sp, (const State*)B.S[cur], B.S[nxt], B.hist, (const double*)B.PU, B.PS,
+                  f, q);
+    };
+    if (!is_pr_family(variant) && variant != kPipePR && variant != kPipeM && j == 0) return hipErrorInvalidValue;
+    using T = std::true_type;
+    using F = std::false_type;
+    e = pre ? (unit ? pick(T{}, T{}) : pick(T{}, F{})) : (unit ? pick(F{}, T{}) : pick(F{}, F{}));
+    cur = nxt;
     return e;
 }
 

@@ -931,7 +931,7 @@ hipError_t with_pre(int pre, F&& f)
 
 SellView sell_or_empty(const SellView* s)
 {
-    return s ? *s : SellView{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+    return s ? *s : SellView{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
 }
 CsrView csr_or_empty(const CsrView* c) { return c ? *c : CsrView{nullptr, nullptr, nullptr, 0}; }
 

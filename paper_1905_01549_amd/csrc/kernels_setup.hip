@@ -134,15 +134,16 @@ __global__ void k_slice_plan(int64_t n, int64_t nslices, const int32_t* __restri
 }
 
 // Fill the SELL-64 storage planned above.  slice_ptr: value offsets;
-// slice_meta[s] = start of the slice's offsets in soff (aligned) or -1.
+// slice_meta[s] = start of the slice's offsets in soff (aligned) or -1;
+// slice_shape[s]: width and slot stride.
 // Packed padding has value 0 and the row's own index (n-1 past the last
 // row) as column.
 __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restrict__ row_ptr,
                             const int32_t* __restrict__ col, const double* __restrict__ val,
                             const int64_t* __restrict__ row0, const int32_t* __restrict__ nrows,
                             const int64_t* __restrict__ slice_ptr, const int32_t* __restrict__ slice_meta,
-                            int32_t* __restrict__ soff, int32_t* __restrict__ scol, double* __restrict__ sval,
-                            int write_cols)
+                            const int32_t* __restrict__ slice_shape, int32_t* __restrict__ soff,
+                            int32_t* __restrict__ scol, double* __restrict__ sval, int write_cols)
 {
     const int64_t t = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
     const int64_t s = t / kSlice;
@@ -150,7 +151,8 @@ __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restric
     const int lane = (int)(t % kSlice);
     const int64_t i = slice_lane_row(s, lane, n, row0, nrows);
     const int64_t base = slice_ptr[s];
-    const int width = (int)((slice_ptr[s + 1] - base) / kSlice);
+    const int width = shape_width(slice_shape[s]);
+    const int64_t stride = shape_stride(slice_shape[s]);
     const int32_t a = i >= 0 ? row_ptr[i] : 0;
     const int32_t e = i >= 0 ? row_ptr[i + 1] : 0;
     const int meta = slice_meta[s];
@@ -159,7 +161,7 @@ __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restric
         for (int j = 0; j < width; ++j) {
             const int head = q < e ? (int)(col[q] - i) : INT_MAX;
             const int m = wave_min_i32(head);
-            const int64_t pos = base + (int64_t)j * kSlice + lane;
+            const int64_t pos = base + (int64_t)j * stride + lane;
             if (head == m) {
                 sval[pos] = val[q];
                 ++q;
@@ -172,7 +174,7 @@ __global__ void k_fill_sell(int64_t n, int64_t nslices, const int32_t* __restric
         const int len = e - a;
         const int32_t pad_col = (int32_t)(i >= 0 ? i : n - 1);
         for (int j = 0; j < width; ++j) {
-            const int64_t pos = base + (int64_t)j * kSlice + lane;
+            const int64_t pos = base + (int64_t)j * stride + lane;
             if (j < len) {
                 if (write_cols) scol[pos] = col[a + j];
                 sval[pos] = val[a + j];
@@ -240,11 +242,11 @@ hipError_t launch_slice_plan(int64_t n, int64_t nslices, const int32_t* row_ptr,
 
 hipError_t launch_fill_sell(int64_t n, int64_t nslices, const int32_t* row_ptr, const int32_t* col, const double* val,
                             const int64_t* row0, const int32_t* nrows, const int64_t* slice_ptr,
-                            const int32_t* slice_meta, int32_t* soff, int32_t* scol, double* sval, int write_cols,
-                            hipStream_t st)
+                            const int32_t* slice_meta, const int32_t* slice_shape, int32_t* soff, int32_t* scol,
+                            double* sval, int write_cols, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fill_sell, rows_grid(nslices * kSlice), dim3(kSetupBlock), 0, st, n, nslices, row_ptr, col,
-                       val, row0, nrows, slice_ptr, slice_meta, soff, scol, sval, write_cols);
+                       val, row0, nrows, slice_ptr, slice_meta, slice_shape, soff, scol, sval, write_cols);
     return hipGetLastError();
 }
 

@@ -142,7 +142,7 @@ hipError_t launch_textbook_kernel(int pre, int j, int& cur, const SellView* sell
     const int nxt = 1 - cur;
     const State* S = B.S[cur];
     double* rt = pre ? v.rt : v.r;
-    const SellView SV = sell ? *sell : SellView{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+    const SellView SV = sell ? *sell : SellView{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
     const CsrView CV = csr ? *csr : CsrView{nullptr, nullptr, nullptr, 0};
     hipError_t e = hipSuccess;
     switch (k) {

@@ -72,11 +72,13 @@ struct prcg_matrix_s {
     // SELL-64 layout (when lanes == 1)
     int64_t* slice_ptr = nullptr;
     int32_t* slice_meta = nullptr;
+    int32_t* slice_shape = nullptr;
     int32_t* soff = nullptr;
     int32_t* scol = nullptr;
     double* sval = nullptr;
     int64_t nslices = 0;
     int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
+    int32_t runs = 0;            // 1 when some slice is stored in a run of more than one
     int64_t stored = 0;          // value slots, padding included
     int64_t stored_packed = 0;   // slots of packed slices (they also read a column index)
     int64_t stored_streamed = 0; // slots read with nontemporal loads
@@ -99,8 +101,9 @@ struct prcg_matrix_s {
 
     SellView sell() const
     {
-        SellView s{slice_ptr, slice_meta, soff, scol, sval, n, nslices};
+        SellView s{slice_ptr, slice_meta, slice_shape, soff, scol, sval, n, nslices};
         s.stream_from = stream_from;
+        s.runs = runs;
         return s;
     }
     CsrView csr() const { return CsrView{row_ptr, col, val, n}; }
@@ -176,6 +179,7 @@ struct prcg_batch_s {
     int32_t* order = nullptr;
     int64_t* slice_ptr = nullptr;
     int32_t* slice_meta = nullptr;
+    int32_t* slice_shape = nullptr;
     int32_t* soff = nullptr;
     int32_t* scol = nullptr;
     double* sval = nullptr;
@@ -226,7 +230,7 @@ struct prcg_batch_s {
     BatchView view() const
     {
         BatchView b;
-        b.A = SellView{slice_ptr, slice_meta, soff, scol, sval, A->n, nslices};
+        b.A = SellView{slice_ptr, slice_meta, slice_shape, soff, scol, sval, A->n, nslices};
         b.A.stream_from = stream_from;
         b.slice_row0 = slice_row0;
         b.slice_nrows = slice_nrows;
@@ -252,7 +256,7 @@ void free_batch(prcg_batch B)
         if (e) (void)hipEventDestroy(e);
     if (B->hactive) (void)hipHostFree(B->hactive);
     void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
-                   B->slice_meta, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
+                   B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
                    B->grp, B->sys_grp0, B->lstate, B->lpart, B->lactive};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -267,7 +271,7 @@ void free_matrix(prcg_matrix A)
         if (g) (void)hipGraphExecDestroy(g);
     for (auto& e : A->ev)
         if (e) (void)hipEventDestroy(e);
-    void* dev[] = {A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->soff, A->scol, A->sval, A->d,
+    void* dev[] = {A->row_ptr, A->col, A->val, A->slice_ptr, A->slice_meta, A->slice_shape, A->soff, A->scol, A->sval, A->d,
                    A->vecs, A->pairs, A->S, A->hist, A->partials, A->dflags};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -560,11 +564,33 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         (void)hipFree(dplan);
         HTRY(e1);
     }
+    // runs of up to kRunSlices consecutive slices of one width and kind,
+    // each stored slot-major, for matrices whose default grid gives every
+    // workgroup at least one 256-row group (from kMaxGrid groups up);
+    // smaller ones keep single slices (measured on MI355X: runs take 6% off
+    // the 27-point 160^3 product at 8192 workgroups, but slow the fused
+    // PR-CG iteration of an 884,736-row problem at 1024 workgroups by 7%)
+    const int64_t run_max = (n + kGroupRows - 1) / kGroupRows >= kMaxGrid ? kRunSlices : 1;
     std::vector<int64_t> hptr((size_t)A->nslices + 1);
-    std::vector<int32_t> hmeta((size_t)A->nslices);
-    hptr[0] = 0;
+    std::vector<int32_t> hmeta((size_t)A->nslices), hshape((size_t)A->nslices);
+    int64_t pos = 0;
+    for (int64_t q0 = 0; q0 < A->nslices;) {
+        int64_t len = 1;
+        while (len < run_max && q0 + len < A->nslices && width[q0 + len] == width[q0] &&
+               aligned[q0 + len] == aligned[q0])
+            ++len;
+        for (int64_t i = 0; i < len; ++i) {
+            hptr[q0 + i] = pos + (int64_t)kSlice * i;
+            hshape[q0 + i] = width[q0] | (int32_t)(len << 16);
+        }
+        if (len > 1) A->runs = 1;
+        pos += (int64_t)kSlice * len * width[q0];
+        if (A->stream_from == INT64_MAX && pos * (int64_t)sizeof(double) > kCachedValueBytes)
+            A->stream_from = q0 + len;  // the next run
+        q0 += len;
+    }
+    hptr[A->nslices] = pos;
     for (int64_t q = 0; q < A->nslices; ++q) {
-        hptr[q + 1] = hptr[q] + (int64_t)kSlice * width[q];
         if (aligned[q]) {
             hmeta[q] = (int32_t)A->noffsets;
             A->noffsets += width[q];
@@ -572,15 +598,13 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
             hmeta[q] = -1;
             A->stored_packed += (int64_t)kSlice * width[q];
         }
+        if (aligned[q] && q >= A->stream_from) A->stored_streamed += (int64_t)kSlice * width[q];
+        // every slot of every slice lies inside the storage
+        if (width[q] > 0 &&
+            hptr[q] + (int64_t)(width[q] - 1) * shape_stride(hshape[q]) + kSlice > pos)
+            return bail(fail(PRCG_EDEVICE, "internal error: SELL layout out of bounds"));
     }
-    A->stored = hptr[A->nslices];
-    for (int64_t q = 0; q < A->nslices; ++q)
-        if (hptr[q + 1] * (int64_t)sizeof(double) > kCachedValueBytes) {
-            A->stream_from = q + 1;
-            break;
-        }
-    for (int64_t q = A->stream_from; q < A->nslices; ++q)
-        if (aligned[q]) A->stored_streamed += hptr[q + 1] - hptr[q];
+    A->stored = pos;
     int lanes = 1;
     const char* fmt = std::getenv("PRCG_FORMAT");
     const double mean = (double)nnz / (double)n;
@@ -595,6 +619,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     if (lanes == 1) {
         HTRY(hipMalloc(&A->slice_ptr, sizeof(int64_t) * (A->nslices + 1)));
         HTRY(hipMalloc(&A->slice_meta, sizeof(int32_t) * A->nslices));
+        HTRY(hipMalloc(&A->slice_shape, sizeof(int32_t) * A->nslices));
         HTRY(hipMalloc(&A->soff, sizeof(int32_t) * std::max<int64_t>(A->noffsets, 1)));
         HTRY(hipMalloc(&A->scol, sizeof(int32_t) * std::max<int64_t>(A->stored, 1)));
         HTRY(hipMalloc(&A->sval, sizeof(double) * std::max<int64_t>(A->stored, 1)));
@@ -602,8 +627,10 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
                             A->stream));
         HTRY(hipMemcpyAsync(A->slice_meta, hmeta.data(), sizeof(int32_t) * A->nslices, hipMemcpyHostToDevice,
                             A->stream));
+        HTRY(hipMemcpyAsync(A->slice_shape, hshape.data(), sizeof(int32_t) * A->nslices, hipMemcpyHostToDevice,
+                            A->stream));
         HTRY(launch_fill_sell(n, A->nslices, A->row_ptr, A->col, A->val, nullptr, nullptr, A->slice_ptr,
-                              A->slice_meta, A->soff, A->scol, A->sval, 1, A->stream));
+                              A->slice_meta, A->slice_shape, A->soff, A->scol, A->sval, 1, A->stream));
         HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
     }
     A->kernels_mode = PRCG_KERNELS_AUTO;
@@ -666,7 +693,7 @@ prcg_status prcg_set_values(prcg_matrix A, const double* values)
         HIP_TRY(hipMemcpyAsync(A->val, values, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, A->stream));
     if (A->sp.lanes == 1)
         HIP_TRY(launch_fill_sell(A->n, A->nslices, A->row_ptr, A->col, A->val, nullptr, nullptr, A->slice_ptr,
-                                 A->slice_meta, A->soff, A->scol, A->sval, 0, A->stream));
+                                 A->slice_meta, A->slice_shape, A->soff, A->scol, A->sval, 0, A->stream));
     if (A->precond == PRCG_PRECOND_JACOBI) {
         HIP_TRY(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), A->stream));
         HIP_TRY(launch_jacobi(A->n, A->row_ptr, A->col, A->val, A->d, A->dflags, A->stream));
@@ -726,7 +753,7 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
     // bytes one product reads: values, the column indices of packed slices,
     // the offsets of aligned slices and the per-slice metadata
     props->matrix_bytes = A->sp.lanes == 1
-                              ? 8 * A->stored + 4 * A->stored_packed + 4 * A->noffsets + 12 * A->nslices + 8
+                              ? 8 * A->stored + 4 * A->stored_packed + 4 * A->noffsets + 16 * A->nslices
                               : 12 * A->nnz + 4 * (A->n + 1);
     props->aligned_slices_frac = 0.0;
     if (A->sp.lanes == 1 && A->nslices > 0)
@@ -909,13 +936,16 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         (void)hipFree(dplan);
         BTRY(e);
     }
+    // slices of a batch are stored singly (run length 1, slot stride 64),
+    // as the persistent kernel's paired product reads them
     std::vector<int64_t> hptr((size_t)ns + 1);
-    std::vector<int32_t> hmeta((size_t)ns);
+    std::vector<int32_t> hmeta((size_t)ns), hshape((size_t)ns);
     int64_t noff = 0;
     hptr[0] = 0;
     for (int64_t q = 0; q < ns; ++q) {
         hptr[q + 1] = hptr[q] + (int64_t)kSlice * width[q];
         hmeta[q] = aligned[q] ? (int32_t)noff : -1;
+        hshape[q] = width[q] | (1 << 16);
         if (aligned[q]) noff += width[q];
     }
     B->stored = hptr[ns];
@@ -954,13 +984,15 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     BTRY(hipMemcpyAsync(B->sys_grp0, sys_grp0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
     BTRY(hipMalloc(&B->slice_ptr, sizeof(int64_t) * (ns + 1)));
     BTRY(hipMalloc(&B->slice_meta, sizeof(int32_t) * ns));
+    BTRY(hipMalloc(&B->slice_shape, sizeof(int32_t) * ns));
     BTRY(hipMalloc(&B->soff, sizeof(int32_t) * std::max<int64_t>(noff, 1)));
     BTRY(hipMalloc(&B->scol, sizeof(int32_t) * std::max<int64_t>(B->stored, 1)));
     BTRY(hipMalloc(&B->sval, sizeof(double) * std::max<int64_t>(B->stored, 1)));
     BTRY(hipMemcpyAsync(B->slice_ptr, hptr.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
     BTRY(hipMemcpyAsync(B->slice_meta, hmeta.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->slice_shape, hshape.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
     BTRY(launch_fill_sell(n, ns, A->row_ptr, A->col, A->val, B->slice_row0, B->slice_nrows, B->slice_ptr,
-                          B->slice_meta, B->soff, B->scol, B->sval, 1, st));
+                          B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, 1, st));
     // largest systems first
     std::vector<int32_t> order((size_t)nsys);
     for (int32_t q = 0; q < nsys; ++q) order[q] = q;

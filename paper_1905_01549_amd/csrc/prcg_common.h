@@ -78,15 +78,20 @@ struct alignas(128) State {
 static_assert(sizeof(State) == 128, "State fills its 128-byte alignment");
 
 // SELL-64 matrix: rows are cut into slices of 64 (one wavefront, one row
-// per lane); slice s stores its slots column-major, slot j of row 64 s + l
-// at slice_ptr[s] + 64 j + l.  An offset-aligned slice (slice_meta[s] >= 0)
+// per lane); slot j of row 64 s + l is at slice_ptr[s] + j stride_s + l.
+// Consecutive slices of one width and kind are stored as runs of up to
+// kRunSlices slices, slot-major: slot j of every slice of the run side by
+// side, so the slices that run at the same time read neighbouring memory;
+// slice_shape[s] = width | (run length << 16), stride_s = 64 x run length.
+// An offset-aligned slice (slice_meta[s] >= 0)
 // stores no column indices: slot j of row r holds the entry at column
 // r + soff[slice_meta[s] + j] or a zero.  A packed slice (slice_meta[s] < 0)
 // holds each row's j-th entry in slot j with its column in col; short rows
 // are padded with zeros whose column is the row itself.
 struct SellView {
-    const int64_t* slice_ptr;   // [nslices + 1]
-    const int32_t* slice_meta;  // [nslices]
+    const int64_t* slice_ptr;    // [nslices + 1]
+    const int32_t* slice_meta;   // [nslices]
+    const int32_t* slice_shape;  // [nslices]
     const int32_t* soff;
     const int32_t* col;
     const double* val;
@@ -97,6 +102,7 @@ struct SellView {
     // past it and the first kCachedValueBytes of values stay resident from
     // one product to the next (nslices or more: every slice is cached).
     int64_t stream_from = INT64_MAX;
+    int32_t runs = 0;  // 1 when some slice is stored in a run of more than one
 };
 
 // Matrix values kept cacheable before loads turn nontemporal: half of the
@@ -105,6 +111,14 @@ struct SellView {
 // and 192 MB gave products of 205, 199 and 217 us against 230 us with every
 // load cached and 213 us with none).
 constexpr int64_t kCachedValueBytes = (int64_t)128 << 20;
+
+// Slices per run of the SELL-64 layout (measured on MI355X, streaming the
+// 885 MB of a 27-point matrix: runs of 64 slices 6% faster than single
+// slices, runs of 640 or more slower than single slices).  Matrices of
+// fewer than kMaxGrid row groups keep single slices.
+constexpr int kRunSlices = 64;
+__host__ __device__ inline int shape_width(int32_t sh) { return sh & 0xffff; }
+__host__ __device__ inline int shape_stride(int32_t sh) { return (sh >> 16) * kSlice; }
 
 // Vector-CSR matrix for long rows: L lanes per row, CSR arrays as given.
 struct CsrView {
@@ -163,8 +177,8 @@ hipError_t launch_slice_plan(int64_t n, int64_t nslices, const int32_t* row_ptr,
                              hipStream_t st);
 hipError_t launch_fill_sell(int64_t n, int64_t nslices, const int32_t* row_ptr, const int32_t* col,
                             const double* val, const int64_t* row0, const int32_t* nrows,
-                            const int64_t* slice_ptr, const int32_t* slice_meta, int32_t* soff, int32_t* scol,
-                            double* sval, int write_cols, hipStream_t st);
+                            const int64_t* slice_ptr, const int32_t* slice_meta, const int32_t* slice_shape,
+                            int32_t* soff, int32_t* scol, double* sval, int write_cols, hipStream_t st);
 hipError_t launch_block_check(int64_t n, const int32_t* row_ptr, const int32_t* col,
                               const int32_t* row_sys, const int64_t* sys_off, int32_t* flags, hipStream_t st);
 hipError_t launch_outer_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* lam,

@@ -323,6 +323,7 @@ struct SlotCols {
     const int32_t* off;
     const int32_t* col;
     int row, last;
+    int stride;  // elements between consecutive slots of a row
 };
 
 // K slots starting at j0; G(c) returns the gathered entry (double or
@@ -340,16 +341,16 @@ __device__ __forceinline__ void slot_piece(const double* __restrict__ v, const S
         for (int u = 0; u < K; ++u) c[u] = min(max(cols.row + o[u], 0), cols.last);
     } else {
 #pragma unroll
-        for (int u = 0; u < K; ++u) c[u] = cols.col[(int64_t)(j0 + u) * 64];
+        for (int u = 0; u < K; ++u) c[u] = cols.col[(int64_t)(j0 + u) * cols.stride];
     }
     double a[K];
     T g[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         if constexpr (NT)
-            a[u] = __builtin_nontemporal_load(v + (int64_t)(j0 + u) * 64);
+            a[u] = __builtin_nontemporal_load(v + (int64_t)(j0 + u) * cols.stride);
         else
-            a[u] = v[(int64_t)(j0 + u) * 64];
+            a[u] = v[(int64_t)(j0 + u) * cols.stride];
         g[u] = gather(c[u]);
     }
 #pragma unroll
@@ -394,13 +395,15 @@ __device__ __forceinline__ SlotCols slot_cols(const SellView& A, int64_t slice, 
                                               int64_t& base, int& width)
 {
     base = A.slice_ptr[slice];
-    width = (int)((A.slice_ptr[slice + 1] - base) >> 6);
+    const int32_t shape = A.slice_shape[slice];
+    width = shape_width(shape);
     const int meta = A.slice_meta[slice];
     SlotCols c;
     c.off = meta >= 0 ? A.soff + meta : nullptr;
     c.col = A.col + base + lane;
     c.row = (int)row64;
     c.last = (int)A.n - 1;
+    c.stride = shape_stride(shape);
     return c;
 }
 

@@ -125,6 +125,28 @@ def test_spmv_every_layout(prcg, torch_cuda, fmt, monkeypatch):
     M.close()
 
 
+def test_spmv_runs_of_packed_slices(prcg, torch_cuda, monkeypatch):
+    """2,100,001 rows (8204 row groups: slices stored in slot-major runs)
+    of a random SPD matrix forced into SELL-64: packed slices of many
+    widths, so runs of every length from 1 to 64 and a partial last slice;
+    every row against the oracle's product, and a fused/two-pass solve."""
+    monkeypatch.setenv("PRCG_FORMAT", "sell")
+    A = P.random_spd(2_100_001, 5.0, 3)
+    x = np.random.default_rng(5).uniform(-1, 1, A.n)
+    M = gpu_matrix(prcg, A, "jacobi", "auto")
+    assert M.props.lanes_per_row == 1 and M.props.aligned_slices_frac < 0.5
+    y = M.spmv(x).cpu().numpy()
+    yo = oracle.spmv(A.row_ptr, A.col_idx, A.values, x)
+    scale = np.abs(A.scipy()) @ np.abs(x)
+    assert np.all(np.abs(y - yo) <= (np.diff(A.row_ptr) + 2) * EPS * scale)
+    b = P.uniform_vector(A.n, 6)
+    xs, info = M.solve(b, "pr", 0.0, 10, history=True)
+    ref = oracle_solve(A, b, "pr", "jacobi", 0.0, 10)
+    assert hist_close(info.history, ref["history"])
+    assert np.linalg.norm(xs.cpu().numpy() - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+    M.close()
+
+
 # ---------------------------------------------------------------- solver parity
 
 @pytest.mark.parametrize("kernels", STRUCTURES)
@@ -475,14 +497,16 @@ def varcoef27_160():
 
 def test_streamed_values_product_full_scale(prcg, torch_cuda, varcoef27_160):
     """The 27-point 160^3 matrix (885 MB of values) is read past its first
-    128 MiB with nontemporal loads: every row of the product, on both sides
-    of the first streamed slice, against the oracle's."""
+    128 MiB with nontemporal loads (from the first run of slices that starts
+    beyond them): every row of the product, on both sides of the first
+    streamed slice, against the oracle's."""
     pr = varcoef27_160
     M = gpu_matrix(prcg, pr.A, "none", "auto")
     props = M.props
     cached = (128 << 20) // 8
     assert 0 < props.streamed_entries < props.stored_entries
-    assert cached <= props.stored_entries - props.streamed_entries <= cached + 64 * 27
+    run = 64 * 64 * 27  # a run of 64 slices of 27 slots
+    assert cached <= props.stored_entries - props.streamed_entries <= cached + run
     x = P.uniform_vector(pr.A.n, 31)
     y = M.spmv(x).cpu().numpy()
     yo = oracle.spmv(pr.A.row_ptr, pr.A.col_idx, pr.A.values, x)
