@@ -599,8 +599,9 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
             A->stored_packed += (int64_t)kSlice * width[q];
         }
         if (aligned[q] && q >= A->stream_from) A->stored_streamed += (int64_t)kSlice * width[q];
-        // every slot of every slice lies inside the storage
-        if (width[q] > 0 &&
+        // every slot of every slice lies inside the storage (widths of 2^16
+        // and more do not fit the shape word: SELL-64 is refused for them below)
+        if (width[q] > 0 && width[q] <= 0xffff &&
             hptr[q] + (int64_t)(width[q] - 1) * shape_stride(hshape[q]) + kSlice > pos)
             return bail(fail(PRCG_EDEVICE, "internal error: SELL layout out of bounds"));
     }
@@ -617,6 +618,9 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         if (!sell_ok) lanes = mean >= 96 ? 64 : mean >= 48 ? 32 : mean >= 24 ? 16 : 8;
     }
     if (lanes == 1) {
+        // the slice shape word holds widths below 2^16
+        if (maxlen > 0xffff)
+            return bail(fail(PRCG_EINVAL, "SELL-64 holds rows of at most 65535 entries; use vector CSR"));
         HTRY(hipMalloc(&A->slice_ptr, sizeof(int64_t) * (A->nslices + 1)));
         HTRY(hipMalloc(&A->slice_meta, sizeof(int32_t) * A->nslices));
         HTRY(hipMalloc(&A->slice_shape, sizeof(int32_t) * A->nslices));
@@ -936,6 +940,8 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         (void)hipFree(dplan);
         BTRY(e);
     }
+    for (int64_t q = 0; q < ns; ++q)
+        if (width[q] > 0xffff) return bail(fail(PRCG_EINVAL, "a batched system has a row of more than 65535 entries"));
     // slices of a batch are stored singly (run length 1, slot stride 64),
     // as the persistent kernel's paired product reads them
     std::vector<int64_t> hptr((size_t)ns + 1);

@@ -125,6 +125,23 @@ def test_spmv_every_layout(prcg, torch_cuda, fmt, monkeypatch):
     M.close()
 
 
+def test_sell_refuses_rows_beyond_its_shape_word(prcg, torch_cuda, monkeypatch):
+    """A row of 70,000 entries: vector CSR by default (product against the
+    oracle); SELL-64 forced is refused (its slice shape holds widths below
+    2^16) instead of mis-reading the row."""
+    A = P.arrowhead(70_000, 2)
+    M = gpu_matrix(prcg, A)
+    assert M.props.lanes_per_row > 1
+    x = np.random.default_rng(3).uniform(-1, 1, A.n)
+    yo = oracle.spmv(A.row_ptr, A.col_idx, A.values, x)
+    scale = np.abs(A.scipy()) @ np.abs(x)
+    assert np.all(np.abs(M.spmv(x).cpu().numpy() - yo) <= (np.diff(A.row_ptr) + 2) * EPS * scale)
+    M.close()
+    monkeypatch.setenv("PRCG_FORMAT", "sell")
+    with pytest.raises(prcg.PrcgError):
+        prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+
+
 def test_spmv_runs_of_packed_slices(prcg, torch_cuda, monkeypatch):
     """2,100,001 rows (8204 row groups: slices stored in slot-major runs)
     of a random SPD matrix forced into SELL-64: packed slices of many
