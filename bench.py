@@ -285,7 +285,8 @@ def adjoint_section(torch, prcg, problems):
 
 def suite(torch, prcg, problems):
     """Per-iteration time of every variant on every workload (printed, one
-    JSON line per workload and kernel structure)."""
+    JSON line per workload and kernel structure; the default structure's
+    lines also give each kernel's time per launch)."""
     def shard():
         # one GPU's rows of the 128^3 problem split into 8 z-slabs (no halo)
         A = problems.poisson3d(128, 128, 16)
@@ -316,6 +317,9 @@ def suite(torch, prcg, problems):
                     best = min(best, time.perf_counter() - t)
                 out[v] = {"iters": info.iters, "status": info.status, "relres_true": info.relres_true,
                           "us_per_iter": best / max(info.iters, 1) * 1e6, "solve_ms": best * 1e3}
+                if kern == "auto":
+                    # each kernel of the default structure, 20 launches timed with HIP events
+                    out[v]["kernels_us"] = {k: ms * 1e3 for k, ms in M.time_kernels(v, 20)}
             print(json.dumps(out), flush=True)
         M.close()
 
