@@ -64,3 +64,19 @@ def test_binding_constants_match_the_header():
         assert variants["PRCG_" + key.upper()] == code, key
     assert header_enum("prcg_precond") == {"PRCG_PRECOND_" + k.upper(): v for k, v in prcg.PRECONDS.items()}
     assert header_enum("prcg_batch_mode_t") == {"PRCG_BATCH_" + k.upper(): v for k, v in prcg.BATCH_MODES.items()}
+
+
+def header_struct(name):
+    """[(field, C type)] of a typedef'd struct of include/prcg.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    return re.findall(r"(int32_t|int64_t|double)\s+(\w+)\s*;", body)
+
+
+@pytest.mark.parametrize("name", ["prcg_matrix_props", "prcg_info"])
+def test_binding_structs_match_the_header(name):
+    """Field order, names and widths of the structs passed across the ABI."""
+    from paper_1905_01549_amd import prcg
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    fields = getattr(prcg, name)._fields_
+    assert [(f, ctype[t]) for t, f in header_struct(name)] == [(f, t) for f, t in fields]
