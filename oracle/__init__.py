@@ -44,7 +44,7 @@ _I32 = ctypes.POINTER(ctypes.c_int32)
 
 class _Diag(ctypes.Structure):
     _fields_ = [(name, _DBL) for name in
-                ("nu", "nup", "rr", "mu", "alpha", "beta", "true_res", "err_a", "orth", "xstar")]
+                ("nu", "nup", "rr", "mu", "alpha", "beta", "true_res", "err_a", "orth", "gap", "xstar")]
 
 
 def _compile(src: str, out: str) -> str:
@@ -151,7 +151,7 @@ def set_threads(n: int) -> None:
     _lib().orc_set_threads(int(n))
 
 
-_DIAG_KEYS = ("nu", "nup", "rr", "mu", "alpha", "beta", "true_res", "err_a", "orth")
+_DIAG_KEYS = ("nu", "nup", "rr", "mu", "alpha", "beta", "true_res", "err_a", "orth", "gap")
 
 
 def solve(row_ptr, col_idx, values, b, variant: str = "pr", precond: str = "none",
@@ -159,7 +159,7 @@ def solve(row_ptr, col_idx, values, b, variant: str = "pr", precond: str = "none
     """Run one variant of the oracle.
 
     ``diagnostics`` is an iterable of names from ``nu, nup, rr, mu, alpha,
-    beta, true_res, err_a, orth``; each becomes a float64[iters+1] array in
+    beta, true_res, err_a, orth, gap``; each becomes a float64[iters+1] array in
     the result (NaN where the quantity is undefined).  Returns a dict with
     ``x``, ``iters``, ``status`` (string), ``code`` and ``history``
     (||r_k||/||b|| for k = 0..iters).

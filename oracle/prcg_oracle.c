@@ -6,8 +6,8 @@
  * calls this file: only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark use it.  It shares no code with the GPU path.
  *
- * What it is: a plain, slow, step-by-step FP64 transcription of the
- * algorithms, written for checking by eye against the paper:
+ * What it is: a plain, slow FP64 implementation of the algorithms in the
+ * paper's notation, written for checking by eye against the paper:
  *   - initialize (Appendix D, Alg. "Initializations"),
  *   - HS-CG      (Alg. 1, Hestenes-Stiefel, preconditioned),
  *   - PR-CG      (Alg. 2, predict nu' with eq. nuk_simplified, recompute nu),
@@ -54,7 +54,8 @@
  * Every exported function is pinned by the CPU tests against something other
  * than itself: dense solves, Krylov-subspace optimality of the iterates,
  * exact rational arithmetic, finite termination, closed forms, the paper's
- * nu'-gap bound and the paper's printed table for its model problem.
+ * nu'-gap and residual-gap analysis, its statements about the two
+ * ablations and its printed table for its model problem.
  */
 #include <math.h>
 #include <stdint.h>
@@ -89,6 +90,7 @@ typedef struct {
     double* true_res;  /* ||b - A x_k|| / ||b||                               */
     double* err_a;     /* ||x* - x_k||_A (needs xstar)                        */
     double* orth;      /* |<p_{k-1}, s_k>| / (||p_{k-1}|| ||s_k||)  (k >= 1)  */
+    double* gap;       /* ||b - A x_k - r_k|| / ||b||, the residual gap       */
     const double* xstar;
 } orc_diag;
 
@@ -141,13 +143,6 @@ static void orc_prec(int64_t n, const double* d, const double* v, double* out)
     for (int64_t i = 0; i < n; ++i) out[i] = d[i] * v[i];
 }
 
-/* y = y + a x  (a plain AXPY; Section 3 eq. axpy) */
-static void orc_axpy(int64_t n, double a, const double* x, double* y)
-{
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) y[i] = y[i] + a * x[i];
-}
-
 /* y = x + a y  (the direction updates p = r~ + beta p, s = w + beta s) */
 static void orc_xpay(int64_t n, const double* x, double a, double* y)
 {
@@ -157,16 +152,21 @@ static void orc_xpay(int64_t n, const double* x, double a, double* y)
 
 static int orc_finite(double v) { return isfinite(v) ? 1 : 0; }
 
-/* ||b - A x|| / ||b|| and ||x* - x||_A, recorded in diagnostics mode only. */
-static void orc_record_truth(const orc_csr* A, const double* b, const double* x, double bnorm,
+/* ||b - A x|| / ||b||, the residual gap ||b - A x - r|| / ||b|| (Section
+ * 3.1.1, Delta_r) and ||x* - x||_A, recorded in diagnostics mode only. */
+static void orc_record_truth(const orc_csr* A, const double* b, const double* x, const double* r, double bnorm,
                              orc_diag* dg, int64_t k, double* tmp1, double* tmp2)
 {
     if (!dg) return;
     int64_t n = A->n;
-    if (dg->true_res) {
+    if (dg->true_res || dg->gap) {
         orc_spmv(A, x, tmp1);
         for (int64_t i = 0; i < n; ++i) tmp1[i] = b[i] - tmp1[i];
-        dg->true_res[k] = sqrt(orc_dot(n, tmp1, tmp1)) / bnorm;
+        if (dg->true_res) dg->true_res[k] = sqrt(orc_dot(n, tmp1, tmp1)) / bnorm;
+        if (dg->gap) {
+            for (int64_t i = 0; i < n; ++i) tmp1[i] = tmp1[i] - r[i];
+            dg->gap[k] = sqrt(orc_dot(n, tmp1, tmp1)) / bnorm;
+        }
     }
     if (dg->err_a && dg->xstar) {
         for (int64_t i = 0; i < n; ++i) tmp1[i] = dg->xstar[i] - x[i];
@@ -249,7 +249,7 @@ static int orc_observe(orc_ctx* C, int64_t k, double rr, double nu, const double
     if (C->dg) {
         if (C->dg->nu) C->dg->nu[k] = nu;
         if (C->dg->rr) C->dg->rr[k] = orc_dot(C->A.n, r, r);
-        orc_record_truth(&C->A, C->b, C->x, C->bnorm, C->dg, k, C->W.tmp1, C->W.tmp2);
+        orc_record_truth(&C->A, C->b, C->x, r, C->bnorm, C->dg, k, C->W.tmp1, C->W.tmp2);
     }
     return orc_finite(rr) && rnorm <= C->tol * C->bnorm;
 }
@@ -262,60 +262,214 @@ static void orc_record_orth(orc_ctx* C, int64_t k, const double* pold, const dou
     C->dg->orth[k] = fabs(orc_dot(n, pold, s)) / (np * ns);
 }
 
-/* Alg. 1: HS-CG.  Two reductions per iteration: nu_k, then mu_k. */
+/* The vectors of an iteration.  Without a preconditioner the tilde vectors
+ * are the plain arrays themselves (r~ = r, s~ = s, w~ = w, u~ = u). */
+typedef struct {
+    int64_t n;
+    int pre;
+    const double* d;
+    double *x, *r, *rt, *p, *s, *st, *w, *wt, *u, *ut, *t;
+} orc_vecs;
+
+static orc_vecs orc_vecs_of(orc_ctx* C)
+{
+    orc_vecs v;
+    v.n = C->A.n;
+    v.pre = C->pre;
+    v.d = C->dinv;
+    v.x = C->x;
+    v.r = C->W.r;
+    v.p = C->W.p;
+    v.s = C->W.s;
+    v.w = C->W.w;
+    v.u = C->W.u;
+    v.t = C->W.t;
+    v.rt = C->pre ? C->W.rt : C->W.r;
+    v.st = C->pre ? C->W.st : C->W.s;
+    v.wt = C->pre ? C->W.wt : C->W.w;
+    v.ut = C->pre ? C->W.ut : C->W.u;
+    return v;
+}
+
+/* ---- the parts of an iteration --------------------------------------------
+ * Section 2.2.1 splits an iteration of a predict-and-recompute method into a
+ * scalar step (alpha, nu', beta from the previous reduction), the vector
+ * recurrences, the matrix products and one global reduction of all inner
+ * products.  Each variant below is written as those parts.  The recurrences
+ * act row by row: row i of every vector depends only on row i of the others,
+ * so taking all of a row's updates together gives the same values as taking
+ * each vector update over all rows in turn. */
+
+/* The predicted nu'_{k+1} (Section 2.1).  PR-CG: eq. nuk_simplified,
+ * nu_k - 2 alpha_k sigma_k + alpha_k^2 gamma_k.  M-CG: the Meurant form
+ * -nu_k + alpha_k^2 gamma_k (Appendix D).  eq. nuk keeps <s~_k, r_k> = delta_k
+ * apart from sigma_k; its two middle terms are grouped as alpha (sigma +
+ * delta), which with delta = sigma (M = I) rounds exactly like 2 alpha sigma.
+ * The ablation of eq. nuk_norecomp starts from the previous prediction nu'_k
+ * instead of the recomputed nu_k. */
+enum { FORM_PR, FORM_MEURANT, FORM_NUK, FORM_NORECOMPUTE };
+
+static double orc_predict_nu(int form, double nu, double nup_prev, double alpha, double sigma, double gamma,
+                             double delta)
+{
+    switch (form) {
+    case FORM_MEURANT: return -nu + alpha * alpha * gamma;
+    case FORM_NUK: return nu - alpha * (sigma + delta) + alpha * alpha * gamma;
+    case FORM_NORECOMPUTE: return nup_prev - 2.0 * alpha * sigma + alpha * alpha * gamma;
+    default: return nu - 2.0 * alpha * sigma + alpha * alpha * gamma;
+    }
+}
+
+/* Solution and residual recurrences of every variant:
+ *   x_k = x_{k-1} + alpha_{k-1} p_{k-1},   r_k = r_{k-1} - alpha_{k-1} s_{k-1}. */
+static inline void orc_xr_row(const orc_vecs* v, int64_t i, double alpha)
+{
+    v->x[i] = v->x[i] + alpha * v->p[i];
+    v->r[i] = v->r[i] - alpha * v->s[i];
+}
+
+/* Alg. 2: x, r, the preconditioned residual by its own recurrence
+ * r~_k = r~_{k-1} - alpha s~_{k-1} (not recomputed as M^{-1} r_k), and the
+ * new direction p_k = r~_k + beta_k p_{k-1}. */
+static void orc_pr_recurrences(const orc_vecs* v, double alpha, double beta)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < v->n; ++i) {
+        orc_xr_row(v, i, alpha);
+        if (v->pre) v->rt[i] = v->rt[i] - alpha * v->st[i];
+        v->p[i] = v->rt[i] + beta * v->p[i];
+    }
+}
+
+/* Alg. 3: besides x, r and r~, the predictions w'_k = w_{k-1} - alpha u_{k-1}
+ * and w~'_k = w~_{k-1} - alpha u~_{k-1}, then the directions
+ * p_k = r~_k + beta p_{k-1}, s_k = w'_k + beta s_{k-1} and
+ * s~_k = w~'_k + beta s~_{k-1}.  w' and w~' overwrite w and w~: they are
+ * replaced by the recomputed A r~_k and M^{-1} A r~_k after the products
+ * (unless the ablation keeps them). */
+static void orc_pipe_recurrences(const orc_vecs* v, double alpha, double beta)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < v->n; ++i) {
+        orc_xr_row(v, i, alpha);
+        if (v->pre) v->rt[i] = v->rt[i] - alpha * v->st[i];
+        v->w[i] = v->w[i] - alpha * v->u[i];
+        if (v->pre) v->wt[i] = v->wt[i] - alpha * v->ut[i];
+        v->p[i] = v->rt[i] + beta * v->p[i];
+        v->s[i] = v->w[i] + beta * v->s[i];
+        if (v->pre) v->st[i] = v->wt[i] + beta * v->st[i];
+    }
+}
+
+/* Several inner products of one reduction, each summed exactly as orc_dot
+ * sums it (the same chunks in the same order), so forming them in one sweep
+ * changes no bit.  out[q] = <a[q], b[q]> for q < m (m <= 8). */
+static void orc_dots(int64_t n, int m, const double* const* a, const double* const* b, double* out)
+{
+    int64_t nc = (n + ORC_CHUNK - 1) / ORC_CHUNK;
+    double* part = (double*)malloc((size_t)(nc > 0 ? nc : 1) * (size_t)m * sizeof(double));
+    if (!part) abort();
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t lo = c * ORC_CHUNK, hi = lo + ORC_CHUNK < n ? lo + ORC_CHUNK : n;
+        double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = lo; i < hi; ++i)
+            for (int q = 0; q < m; ++q) s[q] = s[q] + a[q][i] * b[q][i];
+        for (int q = 0; q < m; ++q) part[(size_t)q * (size_t)nc + (size_t)c] = s[q];
+    }
+    for (int q = 0; q < m; ++q) {
+        double s = 0.0;
+        for (int64_t c = 0; c < nc; ++c) s = s + part[(size_t)q * (size_t)nc + (size_t)c];
+        out[q] = s;
+    }
+    free(part);
+}
+
+/* The reduction of PR-CG and pipe-PR-CG (Alg. 2, Alg. 3; Table 1): mu_k =
+ * <p_k, s_k>, sigma_k = <r~_k, s_k>, gamma_k = <s~_k, s_k>, nu_k = <r~_k, r_k>,
+ * and where needed <r_k, r_k> (stopping test with M != I) and delta_k =
+ * <s~_k, r_k> (eq. nuk).  Returns the values in that order in out[0..5]. */
+static void orc_pr_reduction(const orc_vecs* v, int want_rr, int want_delta, double* out)
+{
+    const double* a[6] = {v->p, v->rt, v->st, v->rt, v->r, v->st};
+    const double* b[6] = {v->s, v->s, v->s, v->r, v->r, v->r};
+    double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    orc_dots(v->n, 4, a, b, t);
+    if (want_rr) orc_dots(v->n, 1, a + 4, b + 4, t + 4);
+    if (want_delta) orc_dots(v->n, 1, a + 5, b + 5, t + 5);
+    for (int q = 0; q < 6; ++q) out[q] = t[q];
+}
+
+/* initialize (Appendix D): r_0 = b - A x_0, r~_0 = M^{-1} r_0, p_0 = r~_0,
+ * s_0 = A p_0, s~_0 = M^{-1} s_0, and for the pipelined methods w_0 = A r~_0
+ * (= A p_0 = s_0), w~_0 = M^{-1} w_0, u_0 = A s~_0, u~_0 = M^{-1} u_0. */
+static void orc_initialize(orc_ctx* C, const orc_vecs* v, int pipelined)
+{
+    const int64_t n = v->n;
+    orc_spmv(&C->A, v->x, v->r);
+    for (int64_t i = 0; i < n; ++i) v->r[i] = C->b[i] - v->r[i];
+    if (v->pre) orc_prec(n, v->d, v->r, v->rt);
+    memcpy(v->p, v->rt, (size_t)n * sizeof(double));
+    orc_spmv(&C->A, v->p, v->s);
+    if (v->pre) orc_prec(n, v->d, v->s, v->st);
+    if (pipelined) {
+        memcpy(v->w, v->s, (size_t)n * sizeof(double));
+        if (v->pre) orc_prec(n, v->d, v->w, v->wt);
+        orc_spmv(&C->A, v->st, v->u);
+        if (v->pre) orc_prec(n, v->d, v->u, v->ut);
+    }
+}
+
+/* Alg. 1: HS-CG.  Two reductions per iteration: nu_k after the x and r
+ * recurrences, mu_k after the product s_k = A p_k. */
 static int orc_hs(orc_ctx* C, int64_t* kout)
 {
-    const int64_t n = C->A.n;
-    const int pre = C->pre;
-    double* x = C->x;
-    double* r = C->W.r;
-    double* p = C->W.p;
-    double* s = C->W.s;
-    double* rt = pre ? C->W.rt : r;
+    const orc_vecs V = orc_vecs_of(C);
+    const orc_vecs* v = &V;
+    const int64_t n = v->n;
     orc_diag* dg = C->dg;
 
-    /* initialize (Appendix D): r0, r~0, nu0, p0, s0, alpha0 */
-    orc_spmv(&C->A, x, r);
-    for (int64_t i = 0; i < n; ++i) r[i] = C->b[i] - r[i];     /* r0 = b - A x0     */
-    if (pre) orc_prec(n, C->dinv, r, rt);                      /* r~0 = M^-1 r0     */
-    double nu = orc_dot(n, r, rt);                             /* nu0 = <r0, r~0>   */
-    memcpy(p, rt, (size_t)n * sizeof(double));                 /* p0 = r~0          */
-    orc_spmv(&C->A, p, s);                                     /* s0 = A p0         */
-    double mu = orc_dot(n, p, s);                              /* <p0, s0>          */
-    double rr = pre ? orc_dot(n, r, r) : nu;
+    orc_initialize(C, v, 0);
+    double nu = orc_dot(n, v->r, v->rt);
+    double mu = orc_dot(n, v->p, v->s);
+    double rr = v->pre ? orc_dot(n, v->r, v->r) : nu;
 
     int64_t k = 0;
     int status;
     if (dg && dg->mu) dg->mu[0] = mu;
     /* same order as in the loop: converged, nu breakdown, maxit, mu breakdown */
-    if (orc_observe(C, 0, rr, nu, r)) { status = ORC_OK; goto out; }
+    if (orc_observe(C, 0, rr, nu, v->r)) { status = ORC_OK; goto out; }
     if (!orc_finite(nu) || !orc_finite(rr) || !(nu > 0.0)) { status = ORC_BREAKDOWN; goto out; }
     if (k == C->maxit) { status = ORC_NOT_CONVERGED; goto out; }
     if (!orc_finite(mu) || !(mu > 0.0)) { status = ORC_BREAKDOWN; goto out; }
-    double alpha = nu / mu;                                    /* alpha0 = nu0 / <p0, s0> */
+    double alpha = nu / mu;
     if (dg && dg->alpha) dg->alpha[0] = alpha;
 
     for (;;) {
         ++k;
-        orc_axpy(n, alpha, p, x);                              /* x_k = x_{k-1} + alpha_{k-1} p_{k-1} */
-        orc_axpy(n, -alpha, s, r);                             /* r_k = r_{k-1} - alpha_{k-1} s_{k-1} */
-        if (pre) orc_prec(n, C->dinv, r, rt);                  /* r~_k = M^-1 r_k                     */
-        double nu_new = orc_dot(n, rt, r);                     /* nu_k = <r~_k, r_k>                  */
-        rr = pre ? orc_dot(n, r, r) : nu_new;
-        if (orc_observe(C, k, rr, nu_new, r)) { status = ORC_OK; goto out; }
+        /* x_k, r_k, then the preconditioned residual recomputed as M^{-1} r_k */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) orc_xr_row(v, i, alpha);
+        if (v->pre) orc_prec(n, v->d, v->r, v->rt);
+        /* first reduction: nu_k = <r~_k, r_k> (and <r_k, r_k>) */
+        double nu_new = orc_dot(n, v->rt, v->r);
+        rr = v->pre ? orc_dot(n, v->r, v->r) : nu_new;
+        if (orc_observe(C, k, rr, nu_new, v->r)) { status = ORC_OK; goto out; }
         if (!orc_finite(nu_new) || !orc_finite(rr) || !(nu_new > 0.0)) { status = ORC_BREAKDOWN; goto out; }
         if (k == C->maxit) { status = ORC_NOT_CONVERGED; goto out; }
-        double beta = nu_new / nu;                             /* beta_k = nu_k / nu_{k-1}            */
+        /* beta_k = nu_k / nu_{k-1}; p_k = r~_k + beta_k p_{k-1}; s_k = A p_k */
+        double beta = nu_new / nu;
         nu = nu_new;
         if (dg && dg->beta) dg->beta[k] = beta;
-        if (dg && dg->orth) memcpy(C->W.pold, p, (size_t)n * sizeof(double));
-        orc_xpay(n, rt, beta, p);                              /* p_k = r~_k + beta_k p_{k-1}         */
-        orc_spmv(&C->A, p, s);                                 /* s_k = A p_k                         */
-        mu = orc_dot(n, p, s);                                 /* mu_k = <p_k, s_k>                   */
+        if (dg && dg->orth) memcpy(C->W.pold, v->p, (size_t)n * sizeof(double));
+        orc_xpay(n, v->rt, beta, v->p);
+        orc_spmv(&C->A, v->p, v->s);
+        /* second reduction: mu_k = <p_k, s_k>; alpha_k = nu_k / mu_k */
+        mu = orc_dot(n, v->p, v->s);
         if (dg && dg->mu) dg->mu[k] = mu;
-        orc_record_orth(C, k, C->W.pold, s);
+        orc_record_orth(C, k, C->W.pold, v->s);
         if (!orc_finite(mu) || !(mu > 0.0)) { status = ORC_BREAKDOWN; goto out; }
-        alpha = nu / mu;                                       /* alpha_k = nu_k / mu_k               */
+        alpha = nu / mu;
         if (dg && dg->alpha) dg->alpha[k] = alpha;
     }
 out:
@@ -323,172 +477,141 @@ out:
     return status;
 }
 
-/* Alg. 2 (PR-CG), Alg. 3 (pipe-PR-CG), their Meurant forms, GV-CG and the
- * two no-recompute ablations.  One reduction per iteration; after it the
- * loop head runs the checks and the scalar step for the next iteration. */
+/* The one-reduction variants: PR-CG (Alg. 2) with its nu' forms and the
+ * ablation without the recompute of nu, pipe-PR-CG (Alg. 3), pipe-PR-M-CG and
+ * the ablation without the recompute of w, GV-CG and CG-CG (Appendix D).  The
+ * loop head takes the tests after the reduction of iteration k, then the
+ * scalar step of iteration k+1; the body runs that iteration's recurrences,
+ * products and reduction. */
 static int orc_one_sync(int variant, orc_ctx* C, int64_t* kout)
 {
-    const int64_t n = C->A.n;
-    const int pre = C->pre;
-    const double* dinv = C->dinv;
-    double* x = C->x;
-    double* r = C->W.r;
-    double* p = C->W.p;
-    double* s = C->W.s;
-    double* w = C->W.w;
-    double* u = C->W.u;
-    double* t = C->W.t;
-    double* rt = pre ? C->W.rt : C->W.r;
-    double* st = pre ? C->W.st : C->W.s;
-    double* wt = pre ? C->W.wt : C->W.w;
-    double* ut = pre ? C->W.ut : C->W.u;
+    const orc_vecs V = orc_vecs_of(C);
+    const orc_vecs* v = &V;
+    const int64_t n = v->n;
+    const int pre = v->pre;
     orc_diag* dg = C->dg;
 
     const int is_pr = variant == ORC_PR || variant == ORC_M || variant == ORC_PR_NO_RECOMPUTE ||
                       variant == ORC_PR_UNSIMPLIFIED;
-    const int unsimplified = variant == ORC_PR_UNSIMPLIFIED;
     const int is_pipe = variant == ORC_PIPE_PR || variant == ORC_PIPE_M || variant == ORC_PIPE_PR_NO_W_RECOMPUTE;
     const int is_gv = variant == ORC_GV;
     const int is_cg = variant == ORC_CG;
-    const int meurant = variant == ORC_M || variant == ORC_PIPE_M;
+    const int form = (variant == ORC_M || variant == ORC_PIPE_M) ? FORM_MEURANT
+                     : variant == ORC_PR_UNSIMPLIFIED          ? FORM_NUK
+                     : variant == ORC_PR_NO_RECOMPUTE          ? FORM_NORECOMPUTE
+                                                               : FORM_PR;
+    const int recompute_nu = variant != ORC_PR_NO_RECOMPUTE;
+    const int recompute_w = variant != ORC_PIPE_PR_NO_W_RECOMPUTE;
 
-    /* initialize (Appendix D) */
-    orc_spmv(&C->A, x, r);
-    for (int64_t i = 0; i < n; ++i) r[i] = C->b[i] - r[i];     /* r0 = b - A x0        */
-    if (pre) orc_prec(n, dinv, r, rt);                         /* r~0 = M^-1 r0        */
-    double nu = orc_dot(n, r, rt);                             /* nu0 = <r0, r~0>      */
-    memcpy(p, rt, (size_t)n * sizeof(double));                 /* p0 = r~0             */
-    orc_spmv(&C->A, p, s);                                     /* s0 = A p0            */
-    double mu = orc_dot(n, p, s);                              /* <p0, s0>             */
-    if (pre) orc_prec(n, dinv, s, st);                         /* s~0 = M^-1 s0        */
-    double sigma = orc_dot(n, rt, s);                          /* sigma0 = <r~0, s0>   */
-    double gamma = orc_dot(n, st, s);                          /* gamma0 = <s~0, s0>   */
-    double delta = unsimplified ? orc_dot(n, st, r) : 0.0;     /* delta0 = <s~0, r0>   */
-    double eta = 0.0;
-    if (is_pipe || is_gv) {
-        memcpy(w, s, (size_t)n * sizeof(double));             /* w0 = A r~0 = A p0 = s0 */
-        if (pre) orc_prec(n, dinv, w, wt);                     /* w~0 = M^-1 w0        */
-        orc_spmv(&C->A, st, u);                                /* u0 = A s~0           */
-        if (pre) orc_prec(n, dinv, u, ut);                     /* u~0 = M^-1 u0        */
-    }
-    double rr = pre ? orc_dot(n, r, r) : nu;
+    orc_initialize(C, v, is_pipe || is_gv);
+    /* the reduction of initialize: mu_0, sigma_0, gamma_0, nu_0, <r_0, r_0>,
+     * delta_0 (eq. nuk) */
+    double red[6];
+    orc_pr_reduction(v, pre, form == FORM_NUK, red);
+    double mu = red[0], sigma = red[1], gamma = red[2], nu = red[3], delta = red[5];
+    double rr = pre ? red[4] : nu;
     double nup = nu;      /* nu'_0 := nu_0 (only the no-recompute ablation reads it) */
-    double alpha = 0.0, beta = 0.0;
+    double alpha = 0.0, beta = 0.0, eta = 0.0;
     int64_t k = 0;
     int status;
     int last = 0;         /* set when nu' <= 0: the current iteration is the final one */
 
     for (;;) {
-        /* the reduction of iteration k has produced nu_k, mu_k, sigma_k, gamma_k */
+        /* ---- tests after the reduction of iteration k */
         if (dg && dg->mu) dg->mu[k] = mu;
-        if (orc_observe(C, k, rr, nu, r)) { status = ORC_OK; break; }
+        if (orc_observe(C, k, rr, nu, v->r)) { status = ORC_OK; break; }
         if (last || !orc_finite(nu) || !orc_finite(mu) || !orc_finite(rr) || !(nu > 0.0) || !(mu > 0.0)) {
             status = ORC_BREAKDOWN;
             break;
         }
         if (k == C->maxit) { status = ORC_NOT_CONVERGED; break; }
 
-        /* scalar step for iteration k+1 (Section 2.2.1) */
-        alpha = nu / mu;                                       /* alpha_k = nu_k / mu_k */
+        /* ---- scalar step for iteration k+1 (Section 2.2.1): alpha_k, and for
+         * the predict-and-recompute methods nu'_{k+1} and beta_{k+1} */
+        alpha = nu / mu;
         if (dg && dg->alpha) dg->alpha[k] = alpha;
         if (is_pr || is_pipe) {
-            if (variant == ORC_PR_NO_RECOMPUTE)
-                nup = nup - 2.0 * alpha * sigma + alpha * alpha * gamma;  /* eq. nuk_norecomp   */
-            else if (meurant)
-                nup = -nu + alpha * alpha * gamma;                        /* M-CG form           */
-            else if (unsimplified)
-                nup = nu - alpha * (sigma + delta) + alpha * alpha * gamma; /* eq. nuk            */
-            else
-                nup = nu - 2.0 * alpha * sigma + alpha * alpha * gamma;   /* eq. nuk_simplified  */
+            nup = orc_predict_nu(form, nu, nup, alpha, sigma, gamma, delta);
             if (!orc_finite(nup) || !(nup > 0.0)) {
                 last = 1;                                      /* take x, r of iteration k+1, then stop */
                 beta = 0.0;
             } else {
-                beta = nup / nu;                               /* beta_{k+1} = nu'_{k+1} / nu_k */
+                beta = nup / nu;
             }
         }
         ++k;
         if (dg && dg->nup && !is_gv && !is_cg) dg->nup[k] = nup;
         if (dg && dg->beta && !is_gv && !is_cg) dg->beta[k] = beta;
-        if (dg && dg->orth) memcpy(C->W.pold, p, (size_t)n * sizeof(double));
+        if (dg && dg->orth) memcpy(C->W.pold, v->p, (size_t)n * sizeof(double));
 
         if (is_pr) {
-            /* Alg. 2, iteration k */
-            orc_axpy(n, alpha, p, x);                          /* x_k = x_{k-1} + alpha p      */
-            orc_axpy(n, -alpha, s, r);                         /* r_k = r_{k-1} - alpha s      */
-            if (pre) orc_axpy(n, -alpha, st, rt);              /* r~_k = r~_{k-1} - alpha s~   */
-            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta_k p_{k-1}  */
-            orc_spmv(&C->A, p, s);                             /* s_k = A p_k                  */
-            if (pre) orc_prec(n, dinv, s, st);                 /* s~_k = M^-1 s_k              */
-            mu = orc_dot(n, p, s);                             /* mu_k    = <p_k, s_k>         */
-            sigma = orc_dot(n, rt, s);                         /* sigma_k = <r~_k, s_k>        */
-            gamma = orc_dot(n, st, s);                         /* gamma_k = <s~_k, s_k>        */
-            if (unsimplified) delta = orc_dot(n, st, r);       /* delta_k = <s~_k, r_k>        */
-            if (variant == ORC_PR_NO_RECOMPUTE) {
-                nu = nup;                                      /* nu_k is never recomputed     */
-                rr = orc_dot(n, r, r);
-            } else {
-                nu = orc_dot(n, rt, r);                        /* nu_k    = <r~_k, r_k>        */
-                rr = pre ? orc_dot(n, r, r) : nu;
-            }
+            /* ---- Alg. 2: recurrences; s_k = A p_k, s~_k = M^{-1} s_k; one
+             * reduction.  The ablation takes nu_k := nu'_k and uses the inner
+             * product of r with itself only for the stopping test. */
+            orc_pr_recurrences(v, alpha, beta);
+            orc_spmv(&C->A, v->p, v->s);
+            if (pre) orc_prec(n, v->d, v->s, v->st);
+            orc_pr_reduction(v, pre || !recompute_nu, form == FORM_NUK, red);
+            mu = red[0], sigma = red[1], gamma = red[2], delta = red[5];
+            nu = recompute_nu ? red[3] : nup;
+            rr = (pre || !recompute_nu) ? red[4] : nu;
         } else if (is_pipe) {
-            /* Alg. 3, iteration k; w and w' share one array, as do w~ and w~' */
-            orc_axpy(n, alpha, p, x);                          /* x_k = x_{k-1} + alpha p      */
-            orc_axpy(n, -alpha, s, r);                         /* r_k = r_{k-1} - alpha s      */
-            if (pre) orc_axpy(n, -alpha, st, rt);              /* r~_k = r~_{k-1} - alpha s~   */
-            orc_axpy(n, -alpha, u, w);                         /* w'_k = w_{k-1} - alpha u     */
-            if (pre) orc_axpy(n, -alpha, ut, wt);              /* w~'_k = w~_{k-1} - alpha u~  */
-            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta_k p_{k-1}  */
-            orc_xpay(n, w, beta, s);                           /* s_k = w'_k + beta_k s_{k-1}  */
-            if (pre) orc_xpay(n, wt, beta, st);                /* s~_k = w~'_k + beta_k s~_{k-1} */
-            orc_spmv(&C->A, st, u);                            /* u_k = A s~_k                 */
-            if (pre) orc_prec(n, dinv, u, ut);                 /* u~_k = M^-1 u_k              */
-            if (variant != ORC_PIPE_PR_NO_W_RECOMPUTE) {
-                orc_spmv(&C->A, rt, w);                        /* w_k = A r~_k  (recompute)    */
-                if (pre) orc_prec(n, dinv, w, wt);             /* w~_k = M^-1 w_k              */
+            /* ---- Alg. 3: recurrences; u_k = A s~_k and the recompute
+             * w_k = A r~_k (both read A: Section 2.2.1 takes them as one
+             * product with a block vector), their preconditioned forms; one
+             * reduction over the vectors of the recurrences */
+            orc_pipe_recurrences(v, alpha, beta);
+            orc_spmv(&C->A, v->st, v->u);
+            if (pre) orc_prec(n, v->d, v->u, v->ut);
+            if (recompute_w) {
+                orc_spmv(&C->A, v->rt, v->w);
+                if (pre) orc_prec(n, v->d, v->w, v->wt);
             }
-            mu = orc_dot(n, p, s);                             /* mu_k    = <p_k, s_k>         */
-            sigma = orc_dot(n, rt, s);                         /* sigma_k = <r~_k, s_k>        */
-            gamma = orc_dot(n, st, s);                         /* gamma_k = <s~_k, s_k>        */
-            nu = orc_dot(n, rt, r);                            /* nu_k    = <r~_k, r_k>        */
-            rr = pre ? orc_dot(n, r, r) : nu;
-        } else if (is_cg) {
-            /* CG-CG (Appendix D), iteration k */
-            orc_axpy(n, alpha, p, x);                          /* x_k = x_{k-1} + alpha p      */
-            orc_axpy(n, -alpha, s, r);                         /* r_k = r_{k-1} - alpha s      */
-            if (pre) orc_prec(n, dinv, r, rt);                 /* r~_k = M^-1 r_k              */
-            orc_spmv(&C->A, rt, w);                            /* w_k = A r~_k                 */
-            double nu_new = orc_dot(n, rt, r);                 /* nu_k  = <r~_k, r_k>          */
-            eta = orc_dot(n, rt, w);                           /* eta_k = <r~_k, w_k>          */
-            beta = nu_new / nu;                                /* beta_k = nu_k / nu_{k-1}     */
-            if (dg && dg->beta) dg->beta[k] = beta;
-            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta p_{k-1}    */
-            orc_xpay(n, w, beta, s);                           /* s_k = w_k + beta s_{k-1}     */
-            mu = eta - (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */
-            nu = nu_new;
-            rr = pre ? orc_dot(n, r, r) : nu;
+            orc_pr_reduction(v, pre, 0, red);
+            mu = red[0], sigma = red[1], gamma = red[2], nu = red[3];
+            rr = pre ? red[4] : nu;
         } else {
-            /* GV-CG (Appendix D), iteration k */
-            orc_axpy(n, alpha, p, x);                          /* x_k = x_{k-1} + alpha p      */
-            orc_axpy(n, -alpha, s, r);                         /* r_k = r_{k-1} - alpha s      */
-            if (pre) orc_axpy(n, -alpha, st, rt);              /* r~_k = r~_{k-1} - alpha s~   */
-            orc_axpy(n, -alpha, u, w);                         /* w_k = w_{k-1} - alpha u      */
-            if (pre) orc_prec(n, dinv, w, wt);                 /* w~_k = M^-1 w_k              */
-            double nu_new = orc_dot(n, rt, r);                 /* nu_k  = <r~_k, r_k>          */
-            eta = orc_dot(n, rt, w);                           /* eta_k = <r~_k, w_k>          */
-            orc_spmv(&C->A, wt, t);                            /* t_k = A w~_k                 */
-            beta = nu_new / nu;                                /* beta_k = nu_k / nu_{k-1}     */
+            /* ---- CG-CG and GV-CG (Appendix D): x, r, r~ first; the reduction
+             * of nu_k = <r~_k, r_k> and eta_k = <r~_k, w_k>; then
+             * beta_k = nu_k / nu_{k-1}, the direction recurrences and
+             * mu_k = eta_k - (beta_k / alpha_{k-1}) nu_k.
+             *   CG-CG: r~_k = M^{-1} r_k and w_k = A r~_k are recomputed.
+             *   GV-CG: r~_k and w_k by recurrence, w~_k = M^{-1} w_k, and the
+             *          product t_k = A w~_k feeds u_k = t_k + beta_k u_{k-1}. */
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                orc_xr_row(v, i, alpha);
+                if (is_gv) {
+                    if (pre) v->rt[i] = v->rt[i] - alpha * v->st[i];
+                    v->w[i] = v->w[i] - alpha * v->u[i];
+                }
+            }
+            if (pre) orc_prec(n, v->d, is_gv ? v->w : v->r, is_gv ? v->wt : v->rt);
+            if (is_cg) orc_spmv(&C->A, v->rt, v->w);
+            const double* a2[2] = {v->rt, v->rt};
+            const double* b2[2] = {v->r, v->w};
+            double ne[2];
+            orc_dots(n, 2, a2, b2, ne);
+            const double nu_new = ne[0];
+            eta = ne[1];
+            if (is_gv) orc_spmv(&C->A, v->wt, v->t);
+            beta = nu_new / nu;
             if (dg && dg->beta) dg->beta[k] = beta;
-            if (dg && dg->nup) dg->nup[k] = nu_new;
-            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta p_{k-1}    */
-            orc_xpay(n, w, beta, s);                           /* s_k = w_k + beta s_{k-1}     */
-            if (pre) orc_xpay(n, wt, beta, st);                /* s~_k = w~_k + beta s~_{k-1}  */
-            orc_xpay(n, t, beta, u);                           /* u_k = t_k + beta u_{k-1}     */
-            mu = eta - (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */
+            if (dg && dg->nup && is_gv) dg->nup[k] = nu_new;
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                v->p[i] = v->rt[i] + beta * v->p[i];
+                v->s[i] = v->w[i] + beta * v->s[i];
+                if (is_gv) {
+                    if (pre) v->st[i] = v->wt[i] + beta * v->st[i];
+                    v->u[i] = v->t[i] + beta * v->u[i];
+                }
+            }
+            mu = eta - (beta / alpha) * nu_new;
             nu = nu_new;
-            rr = pre ? orc_dot(n, r, r) : nu;
+            rr = pre ? orc_dot(n, v->r, v->r) : nu;
         }
-        orc_record_orth(C, k, C->W.pold, s);
+        orc_record_orth(C, k, C->W.pold, v->s);
     }
     *kout = k;
     return status;

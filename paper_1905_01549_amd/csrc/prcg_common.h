@@ -192,7 +192,7 @@ struct Vecs {
     const double* d;  // Jacobi reciprocal diagonal or nullptr
     // pipe-PR-CG block vectors (two-pass kernels): zr[i] = (s~_i, r~_i) and
     // uw[i] = (u_i, w_i), so that the pair of products [A s~, A r~] gathers
-    // one 16-byte entry per stored matrix entry (Section 6 reads A once for
+    // one 16-byte entry per stored matrix entry (Section 5 reads A once for
     // the block vector [s, r]).
     double2* zr;
     double2* uw;

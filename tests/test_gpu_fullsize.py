@@ -60,7 +60,7 @@ def test_varcoef27_160(prcg, varcoef27, variant):
 def test_model_diagonal_1e6(prcg, variant):
     """The eq. model spectrum as a 1e6 diagonal, solved to 1e-10: the first 12
     residual norms against the oracle; the iteration count (the rounding-
-    dependent delay of convergence, Section 5) within 10% of the oracle's;
+    dependent delay of convergence, Section 4) within 10% of the oracle's;
     the true residual of the returned x (the attainable accuracy: 7e-11 for
     PR-CG, 4e-8 for GV-CG in the oracle) within the paper's 10% log-scale
     criterion of the oracle's."""

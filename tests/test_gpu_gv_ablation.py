@@ -1,7 +1,7 @@
 """GPU parity of the comparator GV-CG (Appendix D) and of the two Section 2
 ablations (PR-CG keeping the predicted nu', eq. nuk_norecomp; pipe-PR-CG
 keeping w' instead of recomputing w = A r~), against the oracle, plus the
-paper's accuracy claim on its model problem (Section 5, Table 2): without the
+paper's accuracy claim on its model problem (Section 4, Table 2): without the
 recomputes the attainable accuracy is orders of magnitude worse."""
 import numpy as np
 import pytest

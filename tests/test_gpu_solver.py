@@ -271,7 +271,7 @@ def test_vector_csr_parity(prcg, torch_cuda, variant, fmt, monkeypatch):
 @pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
 def test_dense_model_problem_parity(prcg, torch_cuda, variant):
     """model_48_8_3 (eq. model, n=48, rho=0.8, kappa=1e3) is built to be
-    sensitive to rounding (Section 5): after a few iterations two correct
+    sensitive to rounding (Section 4): after a few iterations two correct
     rounding orders follow different paths.  Early histories must agree to
     1e-8; beyond that the GPU must match the oracle on the two statistics
     the paper reports (Table 2): iterations to reduce the A-norm error by

@@ -32,6 +32,9 @@ from paper_1905_01549_amd import problems as P
 HERE = os.path.dirname(os.path.abspath(__file__))
 EPS = 2.0 ** -53  # unit roundoff of IEEE double
 ALL = ["hs", "pr", "pipe_pr", "m", "pipe_m", "gv", "cg", "pr_unsimplified"]
+# the two ablations of Section 2: PR-CG keeping the predicted nu' (eq. nuk_norecomp)
+# and pipe-PR-CG keeping the predicted w'
+ABLATIONS = ["pr_norecompute", "pipe_pr_nowrecompute"]
 
 
 def run(A, b, variant, precond="none", tol=0.0, maxit=100, **kw):
@@ -63,8 +66,16 @@ def galerkin_iterates(Ad, dinv, b, x0, K):
     return xs
 
 
-def krylov_mismatch(variant, precond, lib=None, n=60, K=14, seed=7):
-    """Largest relative difference between the oracle's x_k and the Galerkin x_k."""
+def krylov_mismatch(variant, precond, lib=None, n=60, K=None, seed=7):
+    """Largest relative difference between the oracle's x_k and the Galerkin x_k.
+
+    In exact arithmetic every variant, the two ablations included, produces
+    HS-CG's iterates (Section 2).  The ablations are compared over a shorter
+    prefix (10 iterations instead of 14): without the recompute their
+    rounding errors accumulate (eq. nuk_norecomp), so their iterates leave
+    the exact ones sooner (1e-10 at k = 14 with Jacobi, 1e-12 at k = 10)."""
+    if K is None:
+        K = 10 if variant in ABLATIONS else 14
     A = P.random_spd(n, 4.0, seed)
     Ad = A.dense()
     rng = np.random.default_rng(seed + 1)
@@ -81,19 +92,23 @@ def krylov_mismatch(variant, precond, lib=None, n=60, K=14, seed=7):
 
 
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
-@pytest.mark.parametrize("variant", ALL)
+@pytest.mark.parametrize("variant", ALL + ABLATIONS)
 def test_iterates_are_krylov_galerkin_solutions(variant, precond):
     assert krylov_mismatch(variant, precond) < 1e-11
 
 
-@pytest.mark.parametrize("variant", ALL)
+@pytest.mark.parametrize("variant", ALL + ABLATIONS)
 def test_history_is_true_residual_of_galerkin_iterate(variant):
     A = P.random_spd(50, 5.0, 3)
     Ad = A.dense()
     b = np.random.default_rng(4).uniform(-1, 1, 50)
-    ref = galerkin_iterates(Ad, None, b, np.zeros(50), 12)
-    out = run(A, b, variant, maxit=12)
-    for k in range(1, 13):
+    # the ablations over 8 iterations: the nu' ablation's updated residual
+    # leaves the exact one by about 5x per iteration (1.7e-11 relative at
+    # k = 8, 4e-10 at k = 10), the accumulation eq. nuk_norecomp describes
+    K = 8 if variant in ABLATIONS else 12
+    ref = galerkin_iterates(Ad, None, b, np.zeros(50), K)
+    out = run(A, b, variant, maxit=K)
+    for k in range(1, K + 1):
         rk = np.linalg.norm(b - Ad @ ref[k - 1]) / np.linalg.norm(b)
         assert abs(out["history"][k] - rk) <= 1e-10 * rk + 1e-15
 
@@ -187,6 +202,38 @@ def test_dense_cholesky_on_poisson2d(variant):
     assert err <= kappa * true_res * (1 + 1e-6) + 1e-13
 
 
+def cholesky_pin(A, b, variant, precond, kappa, tol=1e-10):
+    """P1: the returned x is within kappa times its relative true residual of
+    the dense Cholesky solution (+1e-13 for the Cholesky solve's own error)."""
+    Ad = A.dense()
+    xc = sla.cho_solve(sla.cho_factor(Ad), b)
+    out = run(A, b, variant, precond, tol=tol, maxit=5000, diagnostics=["true_res"])
+    assert out["status"] == "ok", out["status"]
+    err = np.linalg.norm(out["x"] - xc) / np.linalg.norm(xc)
+    assert err <= kappa * out["true_res"][-1] * (1 + 1e-6) + 1e-13, (err, out["true_res"][-1])
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+@pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
+def test_dense_cholesky_on_varcoef7_12(variant, precond):
+    """P1 on the 12^3 variable-coefficient instance of the adjoint tests
+    (kappa from its eigenvalues)."""
+    A = P.varcoef7(12, 5)
+    b = P.uniform_vector(A.n, 5)
+    lam = np.linalg.eigvalsh(A.dense())
+    cholesky_pin(A, b, variant, precond, lam[-1] / lam[0])
+
+
+@pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr"])
+def test_dense_cholesky_on_model_48_8_3(variant):
+    """P1 on the eq. model problem of Table 2 (kappa = 1e3 by construction,
+    Section 4; checked against the eigenvalues)."""
+    mp = P.model_48_8_3(0)
+    lam = np.linalg.eigvalsh(mp.A.dense())
+    assert abs(lam[-1] / lam[0] - 1e3) <= 1e-6 * 1e3
+    cholesky_pin(mp.A, mp.b, variant, "none", 1e3)
+
+
 # ---------------------------------------------------------------- rounding-error analysis
 
 def nu_gap_ratio(A, b, variant, maxit):
@@ -255,7 +302,7 @@ def differs(a, b):
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
 @pytest.mark.parametrize("variant", TABLE2)
 def test_model_48_8_3_matches_table2(variant, precond):
-    """Section 5, Table 2 (model_48_8_3).  The minimum error is within 10%
+    """Section 4, Table 2 (model_48_8_3).  The minimum error is within 10%
     (log scale) of the printed value.  Iteration counts depend on the draw of
     the eigenvectors, which the paper does not give (HS-CG needs 46 here
     against the printed 43), so they are pinned by the table's own criterion:
@@ -278,6 +325,113 @@ def test_no_recompute_loses_accuracy_on_model_problem():
     bad = run(mp.A, mp.b, "pr_norecompute", maxit=200, diagnostics=["err_a"], xstar=mp.xstar)
     assert np.nanmin(good["err_a"]) / good["err_a"][0] < 1e-13
     assert np.nanmin(bad["err_a"]) / bad["err_a"][0] > 1e-9
+
+
+def test_no_recompute_keeps_the_predicted_nu():
+    """eq. nuk_norecomp: the ablation takes nu_k := nu'_k in every iteration,
+    so the nu it divides by is the prediction bit for bit; PR-CG replaces the
+    prediction by the recomputed <r~_k, r_k>, which differs in its last bits."""
+    pr = P.config1()
+    a = run(pr.A, pr.b, "pr_norecompute", maxit=60, diagnostics=["nu", "nup"])
+    assert np.array_equal(a["nu"][1:], a["nup"][1:])
+    p = run(pr.A, pr.b, "pr", maxit=60, diagnostics=["nu", "nup"])
+    assert not np.array_equal(p["nu"][1:], p["nup"][1:])
+
+
+def test_no_recompute_breaks_down_near_sqrt_eps():
+    """Section 3.1: without the recompute, nu' is no longer guaranteed to stay
+    positive once ||r_k|| is about sqrt(eps) (relative to early residuals of
+    norm about 1).  On the 64x64 Poisson problem, a 16^3 variable-coefficient
+    problem and the eq. model problem the ablation breaks down, its smallest
+    relative residual within one decade of sqrt(eps); PR-CG on the same
+    problems goes on to 1e-13."""
+    cases = [(P.config1().A, P.config1().b), (P.varcoef7(16, 5), P.uniform_vector(16 ** 3, 5))]
+    mp = P.model_48_8_3(2)
+    cases.append((mp.A, mp.b))
+    for A, b in cases:
+        a = run(A, b, "pr_norecompute", maxit=3000)
+        assert a["status"] == "breakdown"
+        assert abs(math.log10(np.nanmin(a["history"]) / math.sqrt(EPS))) <= 1.0, np.nanmin(a["history"])
+        good = run(A, b, "pr", tol=1e-13, maxit=3000)
+        assert good["status"] == "ok"
+
+
+def test_w_ablation_behaves_like_gv():
+    """Section 3.2.1: without the recompute of w the w'-gap accumulates like
+    GV-CG's, and the two methods behave alike.  On the model problem of
+    Table 2 (medians over 8 eigenvector draws) the ablation's minimum A-norm
+    error is within 10% (log scale) of GV-CG's and of the printed GV-CG value
+    (-10.23), while pipe-PR-CG reaches the printed -13.66; on the 64x64
+    Poisson problem its residual gap ||b - A x_k - r_k|| grows to a hundred
+    times pipe-PR-CG's, the level of GV-CG's."""
+    _, mn_w = table2_stats("pipe_pr_nowrecompute", "none")
+    _, mn_gv = table2_stats("gv", "none")
+    _, mn_p = table2_stats("pipe_pr", "none")
+    gold = GOLD["none"]["min_log10_error"]
+    assert abs(mn_w - mn_gv) <= 0.1 * abs(mn_gv)
+    assert abs(mn_w - gold["GV"]) <= 0.1 * abs(gold["GV"])
+    assert abs(mn_p - gold["PPR"]) <= 0.1 * abs(gold["PPR"])
+    pr = P.config1()
+    gaps = {v: np.nanmax(run(pr.A, pr.b, v, tol=1e-10, maxit=2000, diagnostics=["gap"])["gap"])
+            for v in ("pipe_pr", "pipe_pr_nowrecompute", "gv")}
+    assert gaps["pipe_pr_nowrecompute"] >= 100 * gaps["pipe_pr"], gaps
+    assert gaps["gv"] / 10 <= gaps["pipe_pr_nowrecompute"] <= 10 * gaps["gv"], gaps
+
+
+# ---------------------------------------------------------------- residual gap (maximum attainable accuracy)
+
+def residual_gap_bound(A, b, xstar, hist, pipelined):
+    """First-order bound on ||b - A x_k - r_k|| / ||b|| from the accumulation
+    of local rounding errors (Section 3.1.1; Section 3.2.1 for pipe-PR-CG),
+    for x_0 = 0 (then r_0 = b exactly and the gap starts at 0).
+
+    Iteration i adds alpha delta_s - A delta_x - delta_r, with (Section 3,
+    eq. fp, axpy, Ax; m = longest row, gamma_m = m eps / (1 - m eps)):
+      ||alpha delta_s|| <= gamma_m || |A| || ||alpha p||,
+      ||A delta_x|| <= eps ||A|| (||alpha p|| + ||x_i||),
+      ||delta_r|| <= eps (||alpha s|| + ||r_i||).
+    In exact arithmetic ||x_i|| grows monotonically to ||x*|| from x_0 = 0, so
+    ||alpha p|| = ||x_i - x_{i-1}|| <= 2 ||x*||, and
+    ||alpha s|| = ||r_{i-1} - r_i||.  ||A|| and || |A| || are bounded by the
+    largest absolute row sum (A symmetric).  A factor 2 covers the
+    second-order terms.  pipe-PR-CG's gap also carries alpha Delta_s, whose
+    local errors are amplified by products of beta, equal in exact
+    arithmetic to ||r_i||^2 / ||r_j||^2 (j <= i): its bound is multiplied by
+    1 + k max_{j <= i <= k} (||r_i|| / ||r_j||)^2."""
+    dense = A.dense()
+    absA = float(np.max(np.sum(np.abs(dense), axis=1)))
+    m = int(np.max(np.diff(A.row_ptr)))
+    gm = m * EPS / (1 - m * EPS)
+    X = float(np.linalg.norm(xstar))
+    bn = float(np.linalg.norm(b))
+    rn = hist * bn
+    k = np.arange(1, len(hist))
+    local = 2 * gm * absA * X + 3 * EPS * absA * X + EPS * (2 * rn[k] + rn[k - 1])
+    bound = np.concatenate([[0.0], 2 * np.cumsum(local) / bn])
+    if pipelined:
+        amp = np.ones(len(hist))
+        for kk in range(1, len(hist)):
+            h = hist[: kk + 1]
+            run_min = np.minimum.accumulate(h)  # smallest ||r_j|| with j <= i
+            amp[kk] = 1 + kk * float(np.max((h / run_min) ** 2))
+        bound = bound * amp
+    return bound
+
+
+@pytest.mark.parametrize("variant", ["hs", "pr", "m", "cg", "pr_unsimplified", "pipe_pr", "pipe_m"])
+def test_residual_gap_within_accumulated_rounding(variant):
+    """P6: the residual gap of a method that recomputes what its recurrences
+    predict stays within the accumulated local rounding errors at every
+    iteration on the 64x64 Poisson problem (Section 3.1.1, 3.2.1), about
+    1e-12 of ||b|| at the end here (measured: at most 2.5% of the bound; GV-CG
+    and the w ablation, whose gaps accumulate, reach 70% of the
+    non-pipelined bound)."""
+    pr = P.config1()
+    out = run(pr.A, pr.b, variant, tol=1e-10, maxit=2000, diagnostics=["gap"])
+    assert out["status"] == "ok"
+    bound = residual_gap_bound(pr.A, pr.b, pr.xstar, out["history"], variant.startswith("pipe"))
+    assert np.all(out["gap"] <= bound), np.max(out["gap"] / np.maximum(bound, 1e-300))
+    assert bound[-1] <= (1e-9 if variant.startswith("pipe") else 1e-11)
 
 
 # ---------------------------------------------------------------- eq. nuk against eq. nuk_simplified
@@ -320,6 +474,17 @@ def test_variants_agree_with_hs_early():
     ref = run(pr.A, pr.b, "hs", maxit=50)["history"]
     for v in ["pr", "pipe_pr", "m", "pipe_m", "gv"]:
         h = run(pr.A, pr.b, v, maxit=50)["history"]
+        assert np.all(np.abs(h - ref) <= 1e-8 * ref), v
+
+
+def test_variants_agree_with_hs_on_poisson3d_128_jacobi():
+    """P9 on the 128^3 Jacobi benchmark problem: PR-CG and pipe-PR-CG follow
+    HS-CG's residual norms to 1e-8 over the first 50 iterations (Section 2:
+    the variants are equivalent in exact arithmetic)."""
+    pr = P.config2()
+    ref = run(pr.A, pr.b, "hs", "jacobi", maxit=50)["history"]
+    for v in ["pr", "pipe_pr"]:
+        h = run(pr.A, pr.b, v, "jacobi", maxit=50)["history"]
         assert np.all(np.abs(h - ref) <= 1e-8 * ref), v
 
 
@@ -455,38 +620,74 @@ def test_invalid_arguments():
 # ---------------------------------------------------------------- mutation test of the pins
 
 MUTANTS = [
-    # (name, original text, replacement, variant, precond)
-    ("sign of 2 alpha sigma", "nup = nu - 2.0 * alpha * sigma + alpha * alpha * gamma;",
-     "nup = nu + 2.0 * alpha * sigma + alpha * alpha * gamma;", "pr", "none"),
-    ("dropped gamma term", "nup = nu - 2.0 * alpha * sigma + alpha * alpha * gamma;",
-     "nup = nu - 2.0 * alpha * sigma;", "pipe_pr", "none"),
+    # (name, original text, replacement, variant, precond[, pin]); the pin is
+    # the Krylov/Galerkin comparison unless named
+    ("sign of 2 alpha sigma", "default: return nu - 2.0 * alpha * sigma + alpha * alpha * gamma;",
+     "default: return nu + 2.0 * alpha * sigma + alpha * alpha * gamma;", "pr", "none"),
+    ("dropped gamma term", "default: return nu - 2.0 * alpha * sigma + alpha * alpha * gamma;",
+     "default: return nu - 2.0 * alpha * sigma;", "pipe_pr", "none"),
     ("HS beta inverted", "double beta = nu_new / nu;", "double beta = nu / nu_new;", "hs", "none"),
-    ("pipe s from u", "orc_xpay(n, w, beta, s);                           /* s_k = w'_k",
-     "orc_xpay(n, u, beta, s);                           /* s_k = w'_k", "pipe_pr", "none"),
-    ("PR r~ from s", "if (pre) orc_axpy(n, -alpha, st, rt);              /* r~_k = r~_{k-1} - alpha s~   */\n            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta_k p_{k-1}  */\n            orc_spmv",
-     "if (pre) orc_axpy(n, -alpha, s, rt);              /* r~_k = r~_{k-1} - alpha s~   */\n            orc_xpay(n, rt, beta, p);                          /* p_k = r~_k + beta_k p_{k-1}  */\n            orc_spmv",
-     "pr", "jacobi"),
+    # (the pipelined recurrences come first in the source, CG-CG's and GV-CG's after them)
+    ("pipe s from u", "v->s[i] = v->w[i] + beta * v->s[i];", "v->s[i] = v->u[i] + beta * v->s[i];", "pipe_pr", "none"),
+    # (PR-CG's recurrences come first in the source)
+    ("PR r~ from s", "if (v->pre) v->rt[i] = v->rt[i] - alpha * v->st[i];",
+     "if (v->pre) v->rt[i] = v->rt[i] - alpha * v->s[i];", "pr", "jacobi"),
     ("preconditioner divides", "out[i] = d[i] * v[i];", "out[i] = v[i] / d[i];", "hs", "jacobi"),
     ("spmv transposed", "acc = acc + A->val[e] * x[A->col[e]];", "acc = acc + A->val[e] * x[i];", "pr", "none"),
-    ("sigma from r", "double sigma = orc_dot(n, rt, s);", "double sigma = orc_dot(n, r, s);", "pr", "jacobi"),
+    ("sigma from r", "const double* a[6] = {v->p, v->rt, v->st, v->rt, v->r, v->st};",
+     "const double* a[6] = {v->p, v->r, v->st, v->rt, v->r, v->st};", "pr", "jacobi"),
     ("eq. nuk delta sign", "alpha * (sigma + delta)", "alpha * (sigma - delta)", "pr_unsimplified", "jacobi"),
-    ("eq. nuk delta from r~", "if (unsimplified) delta = orc_dot(n, st, r);",
-     "if (unsimplified) delta = orc_dot(n, st, rt);", "pr_unsimplified", "jacobi"),
-    # the two mu lines (CG-CG, then GV-CG) are told apart by what follows them
-    ("CG mu sign", 'mu = eta - (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */\n            nu = nu_new;\n            rr = pre ? orc_dot(n, r, r) : nu;\n        } else {', 'mu = eta + (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */\n            nu = nu_new;\n            rr = pre ? orc_dot(n, r, r) : nu;\n        } else {', "cg", "none"),
-    ("GV mu sign", 'mu = eta - (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */\n            nu = nu_new;\n            rr = pre ? orc_dot(n, r, r) : nu;\n        }\n        orc_record_orth', 'mu = eta + (beta / alpha) * nu_new;                /* mu_k = eta_k - (beta_k/alpha_{k-1}) nu_k */\n            nu = nu_new;\n            rr = pre ? orc_dot(n, r, r) : nu;\n        }\n        orc_record_orth', "gv", "none"),
+    ("eq. nuk delta from r~", "const double* b[6] = {v->s, v->s, v->s, v->r, v->r, v->r};",
+     "const double* b[6] = {v->s, v->s, v->s, v->r, v->r, v->rt};", "pr_unsimplified", "jacobi"),
+    ("CG mu sign", "mu = eta - (beta / alpha) * nu_new;", "mu = eta + (beta / alpha) * nu_new;", "cg", "none"),
+    ("GV mu sign", "mu = eta - (beta / alpha) * nu_new;", "mu = eta + (beta / alpha) * nu_new;", "gv", "none"),
+    # the ablations of Section 2
+    ("eq. nuk_norecomp sign of 2 alpha sigma",
+     "case FORM_NORECOMPUTE: return nup_prev - 2.0 * alpha * sigma + alpha * alpha * gamma;",
+     "case FORM_NORECOMPUTE: return nup_prev + 2.0 * alpha * sigma + alpha * alpha * gamma;", "pr_norecompute", "none"),
+    ("no-recompute ablation recomputes nu", "nu = recompute_nu ? red[3] : nup;", "nu = red[3];",
+     "pr_norecompute", "none", "nu_identity"),
+    ("w' from s", "v->w[i] = v->w[i] - alpha * v->u[i];", "v->w[i] = v->w[i] - alpha * v->s[i];",
+     "pipe_pr_nowrecompute", "none"),
+    ("w~' without the preconditioner", "if (v->pre) v->wt[i] = v->wt[i] - alpha * v->ut[i];",
+     "if (v->pre) v->wt[i] = v->wt[i] - alpha * v->u[i];", "pipe_pr_nowrecompute", "jacobi"),
+    ("w ablation recomputes w", "if (recompute_w) {", "if (1) {", "pipe_pr_nowrecompute", "none", "like_gv"),
 ]
 
 
-@pytest.mark.parametrize("name,old,new,variant,precond", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_catch_planted_mistakes(tmp_path, name, old, new, variant, precond):
+def pin_fails(pin, variant, precond, lib):
+    """True when the named pin rejects the oracle build `lib`."""
+    if pin == "krylov":
+        try:
+            return krylov_mismatch(variant, precond, lib=lib) > 1e-6
+        except AssertionError:
+            return True  # the planted mistake broke the iteration count itself
+    if pin == "nu_identity":  # test_no_recompute_keeps_the_predicted_nu
+        pr = P.config1()
+        a = oracle.solve(pr.A.row_ptr, pr.A.col_idx, pr.A.values, pr.b, variant, precond, 0.0, 60,
+                         diagnostics=["nu", "nup"], lib=lib)
+        return not np.array_equal(a["nu"][1:], a["nup"][1:])
+    if pin == "like_gv":  # test_w_ablation_behaves_like_gv
+        mins = []
+        for seed in range(8):
+            mp = P.model_48_8_3(seed)
+            out = oracle.solve(mp.A.row_ptr, mp.A.col_idx, mp.A.values, mp.b, variant, precond, 0.0, 200,
+                               diagnostics=["err_a"], xstar=mp.xstar, lib=lib)
+            mins.append(float(np.log10(np.nanmin(out["err_a"] / out["err_a"][0]))))
+        gv = GOLD["none"]["min_log10_error"]["GV"]
+        return abs(float(np.median(mins)) - gv) > 0.1 * abs(gv)
+    raise ValueError(pin)
+
+
+@pytest.mark.parametrize("mutant", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistakes(tmp_path, mutant):
+    name, old, new, variant, precond = mutant[:5]
+    pin = mutant[5] if len(mutant) > 5 else "krylov"
     src = open(oracle._SRC).read()
     assert src.count(old) >= 1, name
     mutated = tmp_path / "mutant.c"
     mutated.write_text(src.replace(old, new, 1))
     lib = oracle.load_library(oracle._compile(str(mutated), str(tmp_path / "libmutant.so")))
-    try:
-        worst = krylov_mismatch(variant, precond, lib=lib)
-    except AssertionError:
-        return  # the planted mistake broke the iteration count itself
-    assert worst > 1e-6, f"pin missed planted mistake: {name}"
+    assert pin_fails(pin, variant, precond, lib), f"pin missed planted mistake: {name}"
+    # the same pin passes the oracle itself
+    assert not pin_fails(pin, variant, precond, None), name
