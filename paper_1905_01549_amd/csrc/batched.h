@@ -19,16 +19,19 @@ struct BatchView {
 };
 
 // Row groups of the lockstep solver: up to kLockstepSlices consecutive
-// slices (rows row0 .. row0 + nrows - 1) of one system; system s owns groups
-// [sys_grp0[s], sys_grp0[s+1]).  One 32-byte record per group, so a
-// workgroup learns everything about its group in one round trip.
+// slices (rows row0 .. row0 + nrows - 1) of one system, whose rows are
+// lo .. hi; system s owns groups [sys_grp0[s], sys_grp0[s+1]).  One 32-byte
+// record per group, so a workgroup learns everything about its group in one
+// round trip.  (Rows and slices fit int32: column indices are int32.)
 constexpr int kLockstepSlices = 16;
 struct Group {
-    int64_t slice0;
-    int64_t row0;
+    int32_t slice0;
+    int32_t row0;
     int32_t sys;
     int32_t nsl;
     int32_t nrows;
+    int32_t lo;
+    int32_t hi;
     int32_t spare;
 };
 static_assert(sizeof(Group) == 32, "two 16-byte loads per group");

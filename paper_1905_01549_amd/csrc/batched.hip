@@ -19,19 +19,20 @@ namespace {
 
 // Products of the rows of Q offset-aligned slices of the same width W at
 // once (their value, offset and gather loads all in flight together), each
-// row's entries summed in stored order from 0.0 as in sell_row.
+// row's entries summed in stored order from 0.0 as in sell_row.  Zero slots
+// read a column clamped into the system's own rows [lo, hi].
 template <int W, int NX, int Q>
 __device__ __forceinline__ void aligned_group(const SellView& A, const int64_t (&base)[Q], const int32_t* const (&off)[Q],
-                                              int lane, const int64_t (&row)[Q], const double* __restrict__ x0,
-                                              const double* __restrict__ x1, double (&y0)[Q], double (&y1)[Q])
+                                              int lane, const int64_t (&row)[Q], int lo, int hi,
+                                              const double* __restrict__ x0, const double* __restrict__ x1,
+                                              double (&y0)[Q], double (&y1)[Q])
 {
-    const int last = (int)A.n - 1;
     int c[Q][W];
     double a[Q][W], g0[Q][W], g1[Q][W];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
-        for (int u = 0; u < W; ++u) c[q][u] = min(max((int)row[q] + off[q][u], 0), last);
+        for (int u = 0; u < W; ++u) c[q][u] = min(max((int)row[q] + off[q][u], lo), hi);
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -55,7 +56,8 @@ __device__ __forceinline__ void aligned_group(const SellView& A, const int64_t (
     }
 }
 
-// Calls f(row, y0, y1) for every row of the system's slices [sl0, sl1):
+// Calls f(row, y0, y1) for every row of the system's slices [sl0, sl1)
+// (the system's rows are [lo, hi]; zero slots never read past them):
 // wavefront w takes slices sl0 + w, sl0 + w + NW, ... in that order, Q = 2
 // at a time; Q offset-aligned slices of equal width (every slice of a
 // stencil matrix) are multiplied with all their loads in flight together,
@@ -64,8 +66,8 @@ __device__ __forceinline__ void aligned_group(const SellView& A, const int64_t (
 // workload: pairs 21% faster than single slices; Q = 4 no faster than
 // pairs, with more registers.)
 template <int NT, int NX, class F>
-__device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_t sl1, const double* __restrict__ x0,
-                                         const double* __restrict__ x1, F&& f)
+__device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_t sl1, int lo, int hi,
+                                         const double* __restrict__ x0, const double* __restrict__ x1, F&& f)
 {
     constexpr int NW = NT / 64;
     constexpr int Q = 2;
@@ -119,18 +121,18 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
             const int32_t* const(&co)[Q] = off;
             const int64_t(&base)[Q] = cur.base;
             switch (width[0]) {
-            case 1: aligned_group<1, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            case 2: aligned_group<2, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            case 3: aligned_group<3, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            case 4: aligned_group<4, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            case 5: aligned_group<5, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            case 6: aligned_group<kWMax < 6 ? 1 : 6, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            case 7: aligned_group<kWMax < 7 ? 1 : 7, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
-            default: aligned_group<kWMax < 8 ? 1 : 8, NX, Q>(A, base, co, lane, row, x0, x1, y0, y1); break;
+            case 1: aligned_group<1, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            case 2: aligned_group<2, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            case 3: aligned_group<3, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            case 4: aligned_group<4, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            case 5: aligned_group<5, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            case 6: aligned_group<kWMax < 6 ? 1 : 6, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            case 7: aligned_group<kWMax < 7 ? 1 : 7, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
+            default: aligned_group<kWMax < 8 ? 1 : 8, NX, Q>(A, base, co, lane, row, lo, hi, x0, x1, y0, y1); break;
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) sell_row<NX>(A, sq[q], lane, row[q], x0, x1, y0[q], y1[q]);
+            for (int q = 0; q < Q; ++q) sell_row<NX>(A, sq[q], lane, row[q], x0, x1, y0[q], y1[q], lo, hi);
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -141,7 +143,7 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
         const int64_t row = B.slice_row0[sl] + lane;
         const bool valid = lane < B.slice_nrows[sl];
         double y0, y1;
-        sell_row<NX>(A, sl, lane, row, x0, x1, y0, y1);
+        sell_row<NX>(A, sl, lane, row, x0, x1, y0, y1, lo, hi);
         if (valid) f(row, y0, y1);
     }
 }
@@ -163,10 +165,11 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
     constexpr int kRowsAtOnce = NT >= 1024 ? 2 : 4;
     const int64_t r0 = B.sys_row0[sys], r1 = B.sys_row0[sys + 1];
     const int64_t sl0 = B.sys_slice0[sys], sl1 = B.sys_slice0[sys + 1];
+    const int lo = (int)r0, hi = (int)r1 - 1;
 
     // ---- initialize (Appendix D): r0 = b - A x0, r~0 = M^{-1} r0, p0 = r~0
     double bb[1] = {0.0};
-    sys_spmv<NT, 1>(B, sl0, sl1, x, nullptr, [&](int64_t i, double ax, double) {
+    sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, x, nullptr, [&](int64_t i, double ax, double) {
         const double bi = b[i];
         const double ri = bi - ax;
         r[i] = ri;
@@ -178,7 +181,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
     __syncthreads();
     // s0 = A p0 and mu0, sigma0, gamma0, nu0, <r0, r0>, <b, b>
     double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, bb[0]};
-    sys_spmv<NT, 1>(B, sl0, sl1, p, nullptr, [&](int64_t i, double si, double) {
+    sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
         s[i] = si;
         const double ri = r[i];
         const double di = PRE ? d[i] : 1.0;
@@ -211,7 +214,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
         if (KIND == 2) {
             // w0 = A r~0 = s0; u0 = A s~0
             for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) w[i] = s[i];
-            sys_spmv<NT, 1>(B, sl0, sl1, PRE ? stv : s, nullptr, [&](int64_t i, double ui, double) { u[i] = ui; });
+            sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, PRE ? stv : s, nullptr, [&](int64_t i, double ui, double) { u[i] = ui; });
             __syncthreads();
         }
         step_one_reduction(st, t5, PRE, form, nullptr, false);
@@ -233,7 +236,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
             }
             __syncthreads();
             double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            sys_spmv<NT, 1>(B, sl0, sl1, p, nullptr, [&](int64_t i, double si, double) {
+            sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
                 s[i] = si;
                 const double ri = r[i];
                 const double rti = PRE ? rt[i] : ri;
@@ -278,7 +281,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
             step_one_reduction(st, q, PRE, form, nullptr, false);
             if (st.done) break;
             // u = A s~, w = A r~ (one pass over the system's matrix)
-            sys_spmv<NT, 2>(B, sl0, sl1, PRE ? stv : s, PRE ? rt : r, [&](int64_t i, double ui, double wi) {
+            sys_spmv<NT, 2>(B, sl0, sl1, lo, hi, PRE ? stv : s, PRE ? rt : r, [&](int64_t i, double ui, double wi) {
                 u[i] = ui;
                 w[i] = wi;
             });
@@ -306,7 +309,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
             }
             __syncthreads();
             double m[1] = {0.0};
-            sys_spmv<NT, 1>(B, sl0, sl1, p, nullptr, [&](int64_t i, double si, double) {
+            sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
                 s[i] = si;
                 m[0] = fma(p[i], si, m[0]);
             });
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_ls_spmv(BatchView B, GroupView gv, c
     double q[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) q[i] = 0.0;
-    sys_spmv<kBlock, 1>(B, G.slice0, G.slice0 + G.nsl, PHASE == 1 ? v.x : p, nullptr,
+    sys_spmv<kBlock, 1>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, PHASE == 1 ? v.x : p, nullptr,
                         [&](int64_t row, double y0, double) {
                             if constexpr (PHASE == 1) {
                                 const double bi = b[row];

@@ -967,12 +967,14 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         sys_grp0[q] = (int64_t)grp.size();
         for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1]; s0 += kLockstepSlices) {
             Group G{};
-            G.slice0 = s0;
+            G.slice0 = (int32_t)s0;
             G.nsl = (int32_t)std::min<int64_t>(kLockstepSlices, sys_slice0[q + 1] - s0);
-            G.row0 = slice_row0[(size_t)s0];
+            G.row0 = (int32_t)slice_row0[(size_t)s0];
             const int64_t last = s0 + G.nsl - 1;
             G.nrows = (int32_t)(slice_row0[(size_t)last] + slice_nrows[(size_t)last] - G.row0);
             G.sys = q;
+            G.lo = (int32_t)sys_row_offset[q];
+            G.hi = (int32_t)(sys_row_offset[q + 1] - 1);
             grp.push_back(G);
         }
     }
@@ -1008,6 +1010,9 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     BTRY(hipMalloc(&B->order, sizeof(int32_t) * nsys));
     BTRY(hipMemcpyAsync(B->order, order.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
     BTRY(hipMalloc(&B->vecs, sizeof(double) * 9 * (size_t)n));
+    // zero slots read the vectors at clamped columns of their own system
+    // before every entry has been written once: start from finite values
+    BTRY(hipMemsetAsync(B->vecs, 0, sizeof(double) * 9 * (size_t)n, st));
     BTRY(hipMalloc(&B->queue, sizeof(int32_t) * 4));
     BTRY(hipMalloc(&B->iters, sizeof(int32_t) * nsys));
     BTRY(hipMalloc(&B->status, sizeof(int32_t) * nsys));

@@ -317,12 +317,17 @@ __device__ __forceinline__ void chunk_of(int b, int G, int64_t ngroups, int64_t&
 // MI355X: a 27-point product 1.5x slower).
 constexpr int kChunk = 8;
 
-// Column of slot j: offset-aligned (off != nullptr, clamped into [0, n) so
-// zero slots of boundary rows read a valid entry) or packed (explicit).
+// Column of slot j: offset-aligned (off != nullptr, clamped into
+// [first, last] so that zero slots of boundary rows read a valid entry: the
+// whole matrix, or the owning system's rows in a block-diagonal batch, so
+// that no system reads another's vectors) or packed (explicit).  A zero slot
+// still multiplies 0 by the entry it reads: a non-finite vector entry at
+// such a column makes the row's result NaN where a CSR product, which has no
+// such slot, would stay finite.
 struct SlotCols {
     const int32_t* off;
     const int32_t* col;
-    int row, last;
+    int row, first, last;
     int stride;  // elements between consecutive slots of a row
 };
 
@@ -338,7 +343,7 @@ __device__ __forceinline__ void slot_piece(const double* __restrict__ v, const S
 #pragma unroll
         for (int u = 0; u < K; ++u) o[u] = cols.off[j0 + u];  // uniform: scalar loads
 #pragma unroll
-        for (int u = 0; u < K; ++u) c[u] = min(max(cols.row + o[u], 0), cols.last);
+        for (int u = 0; u < K; ++u) c[u] = min(max(cols.row + o[u], cols.first), cols.last);
     } else {
 #pragma unroll
         for (int u = 0; u < K; ++u) c[u] = cols.col[(int64_t)(j0 + u) * cols.stride];
@@ -392,7 +397,7 @@ __device__ __forceinline__ void slot_loop(const double* __restrict__ v, const Sl
 }
 
 __device__ __forceinline__ SlotCols slot_cols(const SellView& A, int64_t slice, int lane, int64_t row64,
-                                              int64_t& base, int& width)
+                                              int64_t& base, int& width, int first, int last)
 {
     base = A.slice_ptr[slice];
     const int32_t shape = A.slice_shape[slice];
@@ -402,7 +407,8 @@ __device__ __forceinline__ SlotCols slot_cols(const SellView& A, int64_t slice, 
     c.off = meta >= 0 ? A.soff + meta : nullptr;
     c.col = A.col + base + lane;
     c.row = (int)row64;
-    c.last = (int)A.n - 1;
+    c.first = first;
+    c.last = last;
     c.stride = shape_stride(shape);
     return c;
 }
@@ -410,11 +416,11 @@ __device__ __forceinline__ SlotCols slot_cols(const SellView& A, int64_t slice, 
 template <int NX>
 __device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, int64_t row64,
                                          const double* __restrict__ x0, const double* __restrict__ x1, double& y0,
-                                         double& y1)
+                                         double& y1, int first, int last)
 {
     int64_t base;
     int width;
-    const SlotCols cols = slot_cols(A, slice, lane, row64, base, width);
+    const SlotCols cols = slot_cols(A, slice, lane, row64, base, width, first, last);
     const double* __restrict__ v = A.val + base + lane;
     double a0 = 0.0, a1 = 0.0;
     if (NX == 1) {
@@ -431,6 +437,15 @@ __device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int l
     y1 = a1;
 }
 
+// A row of the whole matrix: zero slots clamped into [0, n).
+template <int NX>
+__device__ __forceinline__ void sell_row(const SellView& A, int64_t slice, int lane, int64_t row64,
+                                         const double* __restrict__ x0, const double* __restrict__ x1, double& y0,
+                                         double& y1)
+{
+    sell_row<NX>(A, slice, lane, row64, x0, x1, y0, y1, 0, (int)A.n - 1);
+}
+
 // Both products of one SELL-64 row with a block vector of pairs:
 // (y0, y1) = sum_j a_ij (xy_j.x, xy_j.y), entries in stored column order.
 __device__ __forceinline__ void sell_row_pair(const SellView& A, int64_t slice, int lane, int64_t row64,
@@ -438,7 +453,7 @@ __device__ __forceinline__ void sell_row_pair(const SellView& A, int64_t slice, 
 {
     int64_t base;
     int width;
-    const SlotCols cols = slot_cols(A, slice, lane, row64, base, width);
+    const SlotCols cols = slot_cols(A, slice, lane, row64, base, width, 0, (int)A.n - 1);
     const double* __restrict__ v = A.val + base + lane;
     double a0 = 0.0, a1 = 0.0;
     slot_loop<double2>(v, cols, width, slice >= A.stream_from, [&](int c) { return xy[c]; },

@@ -221,3 +221,29 @@ def test_full_batched_workload_sampled(prcg, batch512, mode):
     for s in range(len(sizes)):
         sl = slice(offs[s], offs[s + 1])
         assert np.linalg.norm(res[sl]) <= 2e-10 * np.linalg.norm(b[sl]), s
+
+
+@pytest.mark.parametrize("mode,config", [("persistent", "256,1"), ("persistent", "512,2"), ("lockstep", None)])
+def test_nan_system_leaves_neighbours_alone(prcg, mode, config, monkeypatch):
+    """A system whose right-hand side holds NaN breaks down on its own: the
+    zero slots of its neighbours' boundary rows read only their own system's
+    vectors, so every other system still matches the oracle."""
+    if config:
+        monkeypatch.setenv("PRCG_BATCH_CONFIG", config)
+    A, offs, b, mats, bs = small_batch(6)
+    b = b.copy()
+    bad = 2
+    b[offs[bad]] = np.nan          # first row: read by the previous system's last rows
+    b[offs[bad + 1] - 1] = np.nan  # last row: read by the next system's first rows
+    bs = list(bs)
+    bs[bad] = b[offs[bad]:offs[bad + 1]].copy()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    B.set_mode(mode)
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000)
+    x = x.cpu().numpy()
+    ref = oracle.solve(mats[bad].row_ptr, mats[bad].col_idx, mats[bad].values, bs[bad], "pr", "none", 1e-10, 5000)
+    assert status[bad] == ref["status"] == "breakdown", (status[bad], ref["status"])
+    others = [s for s in range(len(mats)) if s != bad]
+    check_systems(x, iters, status, mats, bs, offs, "pr", "none", 1e-10, which=others)
+    assert all(np.all(np.isfinite(x[offs[s]:offs[s + 1]])) for s in others)
