@@ -242,6 +242,27 @@ prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x
                        int32_t maxit, prcg_info* info, double* history);
 
 /*
+ * prcg_solve for callers that cannot allocate device memory: code that runs
+ * between graph captures, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and bits as prcg_solve on the same
+ * handle, but the call allocates nothing: the partial sums, the scalar
+ * state and the residual history live in a fixed device array of the
+ * library (about 1.6 MB per device, held from the first such call until the
+ * process ends), and the iterations are launched directly instead of
+ * through an instantiated graph.  The handle (created beforehand) still
+ * owns the vectors.
+ *   maxit    0 <= maxit <= PRCG_NOALLOC_MAX_ITERS, else PRCG_EINVAL (nothing
+ *            written): the history array holds PRCG_NOALLOC_MAX_ITERS + 1
+ *            entries.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind: calls that overlap on one device (from several threads
+ * or streams) race and give undefined results.
+ */
+#define PRCG_NOALLOC_MAX_ITERS 65536
+prcg_status prcg_solve_noalloc(prcg_matrix A, prcg_variant v, const double* b, double* x, double tol,
+                               int32_t maxit, prcg_info* info, double* history);
+
+/*
  * Per-kernel device time of `iters` iterations of variant v on A, from
  * x0 = 0 with b = (1, ..., 1) and tol = 0 (so every iteration does its full
  * work; PRCG_EDEVICE if the run ends early).  Each launch carries dispatch

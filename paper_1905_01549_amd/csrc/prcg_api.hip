@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,6 +56,29 @@ bool is_device_pointer(const void* p)
         return false;
     }
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// Words of the partial-sum buffers: PS | PU | PB | PS2 | PN | PD | PW, each
+// reduction value a row of kMaxGrid doubles.
+constexpr int64_t kPartialWords = (int64_t)(2 * kMaxDots + 7) * kMaxGrid;
+
+// The reduction buffers of a solve laid out over `partials` (kPartialWords
+// doubles), two state copies, the residual history and the ticket counter.
+Bufs bufs_at(double* partials, State* S, double* hist, int* ticket)
+{
+    Bufs B;
+    B.S[0] = S;
+    B.S[1] = S + 1;
+    B.hist = hist;
+    B.PS = partials;
+    B.PU = partials + (size_t)kMaxDots * kMaxGrid;
+    B.PB = partials + (size_t)(kMaxDots + 2) * kMaxGrid;
+    B.PS2 = partials + (size_t)(kMaxDots + 3) * kMaxGrid;
+    B.PN = partials + (size_t)(2 * kMaxDots + 3) * kMaxGrid;
+    B.PD = partials + (size_t)(2 * kMaxDots + 5) * kMaxGrid;
+    B.PW = partials + (size_t)(2 * kMaxDots + 6) * kMaxGrid;
+    B.ticket = ticket;
+    return B;
 }
 
 }  // namespace
@@ -148,22 +172,7 @@ struct prcg_matrix_s {
         return f;
     }
 
-    Bufs bufs() const
-    {
-        Bufs B;
-        B.S[0] = S;
-        B.S[1] = S + 1;
-        B.hist = hist;
-        B.PS = partials;
-        B.PU = partials + (size_t)kMaxDots * kMaxGrid;
-        B.PB = partials + (size_t)(kMaxDots + 2) * kMaxGrid;
-        B.PS2 = partials + (size_t)(kMaxDots + 3) * kMaxGrid;
-        B.PN = partials + (size_t)(2 * kMaxDots + 3) * kMaxGrid;
-        B.PD = partials + (size_t)(2 * kMaxDots + 5) * kMaxGrid;
-        B.PW = partials + (size_t)(2 * kMaxDots + 6) * kMaxGrid;
-        B.ticket = dflags + 4;
-        return B;
-    }
+    Bufs bufs() const { return bufs_at(partials, S, hist, dflags + 4); }
 };
 
 struct prcg_batch_s {
@@ -371,10 +380,9 @@ prcg_status ensure_hist(prcg_matrix A, int64_t need)
 
 // Kernel j of the iteration at position `it` (its parity selects the buffer
 // copies of the fused kernels).
-hipError_t launch_iteration(prcg_matrix A, int variant, int j, int it, int& cur, hipStream_t st,
+hipError_t launch_iteration(prcg_matrix A, const Bufs& B, int variant, int j, int it, int& cur, hipStream_t st,
                             const LaunchEvents* ev = nullptr)
 {
-    const Bufs B = A->bufs();
     if (A->sp.textbook && variant == kHS)
         return launch_textbook_kernel(A->precond, j, cur, A->sellp(), A->csrp(), A->sp, A->vecs_view(), B, st, ev);
     if (uses_fused(variant, A->sp)) {
@@ -397,7 +405,7 @@ prcg_status build_graph(prcg_matrix A, int variant)
     hipError_t err = hipSuccess;
     for (int it = 0; it < kGraphIters && err == hipSuccess; ++it)
         for (int j = 0; j < iter_kernel_count(variant, A->sp) && err == hipSuccess; ++j)
-            err = launch_iteration(A, variant, j, it, cur, A->capture);
+            err = launch_iteration(A, A->bufs(), variant, j, it, cur, A->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(A->capture, &g);
     if (err != hipSuccess) {
@@ -415,29 +423,44 @@ prcg_status build_graph(prcg_matrix A, int variant)
     return PRCG_OK;
 }
 
-// Runs a complete solve on the handle's stream.  x0 (device) may be the
-// spare zero vector; xout receives the result.
-prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double* x0, double* xout, double tol,
-                      int32_t maxit, State* final_state)
+// One chunk of kGraphIters iterations: a replay of the variant's graph, or
+// (graph == nullptr) the same launches, in the same order, made one by one.
+prcg_status launch_chunk(prcg_matrix A, const Bufs& B, int variant, hipGraphExec_t graph)
 {
-    prcg_status s = ensure_hist(A, (int64_t)maxit + 1);
-    if (s != PRCG_OK) return s;
-    s = build_graph(A, variant);
-    if (s != PRCG_OK) return s;
+    if (graph) {
+        HIP_TRY(hipGraphLaunch(graph, A->stream));
+        return PRCG_OK;
+    }
+    int cur = 0;
+    const int nk = iter_kernel_count(variant, A->sp);
+    for (int it = 0; it < kGraphIters; ++it)
+        for (int j = 0; j < nk; ++j) HIP_TRY(launch_iteration(A, B, variant, j, it, cur, A->stream));
+    if (cur != 0) return fail(PRCG_EDEVICE, "internal: state copy does not return to 0 after a chunk");
+    return PRCG_OK;
+}
+
+// A complete solve on the handle's stream with the reduction buffers B:
+// the initialisation, chunks of kGraphIters iterations until the
+// device-side state says the solve ended (the host reads the state once per
+// chunk, overlapped with the next chunk), then the true residual.  x0
+// (device) may be the spare zero vector; xout receives the result.
+prcg_status solve_loop(prcg_matrix A, const Bufs& B, int variant, hipGraphExec_t graph, const double* b,
+                       const double* x0, double* xout, double tol, int32_t maxit, State* final_state)
+{
     const Vecs v = A->vecs_view();
-    const Bufs B = A->bufs();
     HIP_TRY(launch_init(variant, A->precond, A->sellp(), A->csrp(), A->sp, v, B, b, x0, tol, maxit, A->stream));
-    // transitions needed <= maxit + 2; each replay performs kGraphIters (HS: 2 per iteration)
-    const int64_t max_replays = ((int64_t)maxit + 2) / kGraphIters + 3;
+    // transitions needed <= maxit + 2; each chunk performs kGraphIters (HS: 2 per iteration)
+    const int64_t max_chunks = ((int64_t)maxit + 2) / kGraphIters + 3;
     int64_t launched = 0;
     int pending = -1;  // slot whose copy is in flight
     bool done = false;
     while (!done) {
-        if (launched > max_replays)
-            return fail(PRCG_EDEVICE, "internal: solve did not finish within the expected number of replays");
-        HIP_TRY(hipGraphLaunch(A->graph[variant], A->stream));
+        if (launched > max_chunks)
+            return fail(PRCG_EDEVICE, "internal: solve did not finish within the expected number of chunks");
+        prcg_status s = launch_chunk(A, B, variant, graph);
+        if (s != PRCG_OK) return s;
         const int slot = (int)(launched & 1);
-        HIP_TRY(hipMemcpyAsync(&A->hstate[slot], A->S, sizeof(State), hipMemcpyDeviceToHost, A->stream));
+        HIP_TRY(hipMemcpyAsync(&A->hstate[slot], B.S[0], sizeof(State), hipMemcpyDeviceToHost, A->stream));
         HIP_TRY(hipEventRecord(A->ev[slot], A->stream));
         ++launched;
         if (pending >= 0) {
@@ -447,9 +470,21 @@ prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double*
         pending = slot;
     }
     HIP_TRY(launch_final(A->sellp(), A->csrp(), A->sp, v, B, 0, b, xout, A->stream));
-    HIP_TRY(hipMemcpyAsync(final_state, A->S, sizeof(State), hipMemcpyDeviceToHost, A->stream));
+    HIP_TRY(hipMemcpyAsync(&A->hstate[0], B.S[0], sizeof(State), hipMemcpyDeviceToHost, A->stream));
     HIP_TRY(hipStreamSynchronize(A->stream));
+    *final_state = A->hstate[0];
     return PRCG_OK;
+}
+
+// A complete solve with the handle's own buffers and graph.
+prcg_status run_solve(prcg_matrix A, int variant, const double* b, const double* x0, double* xout, double tol,
+                      int32_t maxit, State* final_state)
+{
+    prcg_status s = ensure_hist(A, (int64_t)maxit + 1);
+    if (s != PRCG_OK) return s;
+    s = build_graph(A, variant);
+    if (s != PRCG_OK) return s;
+    return solve_loop(A, A->bufs(), variant, A->graph[variant], b, x0, xout, tol, maxit, final_state);
 }
 
 prcg_status check_variant(int v)
@@ -474,6 +509,45 @@ void fill_info(const State& st, prcg_info* info)
     info->relres_updated = st.bnorm > 0.0 ? std::sqrt(st.rr > 0.0 ? st.rr : 0.0) / st.bnorm : 0.0;
     info->relres_true = st.relres_true;
 }
+
+// ---- scratch of the no-allocation solve ----
+// prcg_solve_noalloc takes its partial sums, two state copies, the reduction
+// ticket and the residual history from one file-scope device array, so that
+// a solve allocates nothing.  Every device that runs the library holds its
+// own copy (at its own address) until the process ends; every call on a
+// device shares that device's copy.  Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+constexpr int64_t kStateWords = (int64_t)(2 * sizeof(State) / sizeof(double));
+constexpr int64_t kTicketWords = 16;  // 128 bytes: the history stays 128-byte aligned
+constexpr int64_t kScratchWords = kPartialWords + kStateWords + kTicketWords + PRCG_NOALLOC_MAX_ITERS + 1;
+static_assert(kPartialWords % 16 == 0, "the state copies stay 128-byte aligned");
+
+static __device__ __align__(256) double scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch[kMaxDevices] = {};
+
+// Device address of the calling device's scratch (the device must be current).
+prcg_status scratch_of(int device, double** out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(PRCG_EDEVICE, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PRCG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch[device];
+    return PRCG_OK;
+}
+
+// The last-workgroup reduction expects its ticket counter at zero between
+// kernels; the scratch keeps whatever the previous call left.
+__global__ void k_clear_ticket(int* ticket) { *ticket = 0; }
 
 }  // namespace
 
@@ -650,7 +724,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     HTRY(hipMalloc(&A->S, sizeof(State) * 2));
     HTRY(hipMemsetAsync(A->S, 0, sizeof(State) * 2, A->stream));
     // partials sized for the largest grid, so the grid can change later
-    HTRY(hipMalloc(&A->partials, sizeof(double) * (2 * kMaxDots + 7) * (size_t)kMaxGrid));
+    HTRY(hipMalloc(&A->partials, sizeof(double) * (size_t)kPartialWords));
     HTRY(hipStreamSynchronize(A->stream));
     TRY(ensure_hist(A, 1024));
     *out = A;
@@ -741,6 +815,39 @@ prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x
     return (prcg_status)st.status;
 }
 
+prcg_status prcg_solve_noalloc(prcg_matrix A, prcg_variant v, const double* b, double* x, double tol,
+                               int32_t maxit, prcg_info* info, double* history)
+{
+    if (!A) return fail(PRCG_EINVAL, "null handle");
+    if (check_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    if (!(tol >= 0.0)) return fail(PRCG_EINVAL, "tol must be >= 0");
+    if (maxit < 0) return fail(PRCG_EINVAL, "maxit must be >= 0");
+    if (maxit > PRCG_NOALLOC_MAX_ITERS)
+        return fail(PRCG_EINVAL, "maxit exceeds PRCG_NOALLOC_MAX_ITERS: the residual history lives in a fixed "
+                                 "device array of PRCG_NOALLOC_MAX_ITERS + 1 entries");
+    if (A->sp.G > kMaxGrid) return fail(PRCG_EINVAL, "more workgroups than the scratch holds partial sums for");
+    if (!is_device_pointer(b) || !is_device_pointer(x)) return fail(PRCG_EINVAL, "b and x must be device pointers");
+    HIP_TRY(hipSetDevice(A->device));
+    double* base = nullptr;
+    prcg_status s = scratch_of(A->device, &base);
+    if (s != PRCG_OK) return s;
+    State* S = reinterpret_cast<State*>(base + kPartialWords);
+    int* ticket = reinterpret_cast<int*>(base + kPartialWords + kStateWords);
+    double* hist = base + kPartialWords + kStateWords + kTicketWords;
+    const Bufs B = bufs_at(base, S, hist, ticket);
+    hipLaunchKernelGGL(k_clear_ticket, dim3(1), dim3(1), 0, A->stream, ticket);
+    HIP_TRY(hipGetLastError());
+    State st;
+    s = solve_loop(A, B, v, nullptr, b, x, x, tol, maxit, &st);
+    if (s != PRCG_OK) return s;
+    if (history) {
+        const int32_t k = st.k < 0 ? 0 : st.k;
+        HIP_TRY(hipMemcpy(history, hist, sizeof(double) * (k + 1), hipMemcpyDeviceToHost));
+    }
+    fill_info(st, info);
+    return (prcg_status)st.status;
+}
+
 prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props)
 {
     if (!A || !props) return fail(PRCG_EINVAL, "null argument");
@@ -799,7 +906,7 @@ prcg_status prcg_time_kernels(prcg_matrix A, prcg_variant v, int32_t iters, doub
         for (int j = 0; j < nk && err == hipSuccess; ++j) {
             const size_t q = (size_t)2 * (it * nk + j);
             const LaunchEvents le{ev[q], ev[q + 1]};
-            err = launch_iteration(A, v, j, it, cur, ts, &le);
+            err = launch_iteration(A, B, v, j, it, cur, ts, &le);
         }
     if (err == hipSuccess) err = hipStreamSynchronize(ts);
     std::vector<double> tot((size_t)nk, 0.0);

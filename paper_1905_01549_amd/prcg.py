@@ -35,7 +35,8 @@ BATCH_MODES = {"auto": 0, "persistent": 1, "lockstep": 2}
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
             "prcg_time_kernels", "prcg_get_props", "prcg_create_batch", "prcg_solve_batched",
             "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config",
-            "prcg_batch_set_mode", "prcg_batch_mode")
+            "prcg_batch_set_mode", "prcg_batch_mode", "prcg_solve_noalloc")
+NOALLOC_MAX_ITERS = 65536  # PRCG_NOALLOC_MAX_ITERS
 
 
 class PrcgError(RuntimeError):
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "prcg_set_option": (i32, [_VP, i32, i32]),
         "prcg_spmv": (i32, [_VP, _VP, _VP]),
         "prcg_solve": (i32, [_VP, i32, _VP, _VP, dbl, i32, ctypes.POINTER(prcg_info), _VP]),
+        "prcg_solve_noalloc": (i32, [_VP, i32, _VP, _VP, dbl, i32, ctypes.POINTER(prcg_info), _VP]),
         "prcg_time_kernels": (i32, [_VP, i32, i32, _VP, _VP, i32, ctypes.POINTER(i32)]),
         "prcg_get_props": (i32, [_VP, ctypes.POINTER(prcg_matrix_props)]),
         "prcg_create_batch": (i32, [_VP, i32, _VP, ctypes.POINTER(_VP)]),
@@ -137,6 +139,12 @@ def prcg_spmv(A, x, y):
 def prcg_solve(A, variant, b, x, tol, maxit, info=None, history=None) -> int:
     return _check(load_library().prcg_solve(A, variant, b, x, tol, maxit,
                                             ctypes.byref(info) if info is not None else None, history),
+                  allow_numeric=True)
+
+
+def prcg_solve_noalloc(A, variant, b, x, tol, maxit, info=None, history=None) -> int:
+    return _check(load_library().prcg_solve_noalloc(A, variant, b, x, tol, maxit,
+                                                    ctypes.byref(info) if info is not None else None, history),
                   allow_numeric=True)
 
 
@@ -288,16 +296,19 @@ class Matrix:
         return y
 
     def solve(self, b, variant: str = "pr", tol: float = 1e-10, maxit: int = 10000, x0=None,
-              history: bool = False):
-        """Solve A x = b; returns (x as a CUDA tensor, SolveInfo)."""
+              history: bool = False, noalloc: bool = False):
+        """Solve A x = b; returns (x as a CUDA tensor, SolveInfo).  noalloc:
+        through prcg_solve_noalloc (the library allocates nothing during the
+        call; maxit <= NOALLOC_MAX_ITERS)."""
         torch = _torch()
         bd = _dev(b, torch.float64)
         x = torch.zeros_like(bd) if x0 is None else _dev(x0, torch.float64).clone()
         info = prcg_info()
         hist = np.full(maxit + 1, np.nan) if history else None
         prcg_set_stream(self.handle, _stream_ptr())
-        prcg_solve(self.handle, VARIANTS[variant], bd.data_ptr(), x.data_ptr(), float(tol), int(maxit), info,
-                   hist.ctypes.data if hist is not None else None)
+        call = prcg_solve_noalloc if noalloc else prcg_solve
+        call(self.handle, VARIANTS[variant], bd.data_ptr(), x.data_ptr(), float(tol), int(maxit), info,
+             hist.ctypes.data if hist is not None else None)
         return x, SolveInfo(info.iters, STATUS[info.status], info.relres_updated, info.relres_true,
                             hist[:info.iters + 1].copy() if hist is not None else None)
 

@@ -80,3 +80,9 @@ def test_binding_structs_match_the_header(name):
     ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
     fields = getattr(prcg, name)._fields_
     assert [(f, ctype[t]) for t, f in header_struct(name)] == [(f, t) for f, t in fields]
+
+
+def test_noalloc_limit_matches_the_header():
+    from paper_1905_01549_amd import prcg
+    m = re.search(r"#define\s+PRCG_NOALLOC_MAX_ITERS\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == prcg.NOALLOC_MAX_ITERS
