@@ -46,10 +46,16 @@ def parse():
     ap.add_argument("--m", type=int, default=128, help="grid edge (128 = the benchmark workload)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the flagship variant's kernels (the launches the roofline uses)")
+    ap.add_argument("--workload", default="poisson3d_128_jacobi", choices=("poisson3d_128_jacobi", "varcoef27_160"),
+                    help="workload of --kernels-only (varcoef27_160: the 27-point 160^3 problem, no preconditioner)")
+    ap.add_argument("--no-27pt", action="store_true", help="skip the 27-point 160^3 section")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched workload (both modes; one JSON line)")
+    ap.add_argument("--batched-reps", type=int, default=3, help="timed batched solves per mode")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the 512 one-at-a-time solves of the batched comparison (profiling runs)")
     ap.add_argument("--suite", action="store_true",
                     help="per-iteration times of every variant on every workload (one JSON line each)")
     return ap.parse_args()
@@ -141,7 +147,7 @@ def device_facts(torch):
     return facts
 
 
-def batched_section(torch, prcg, problems, traffic):
+def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True):
     """512 anisotropic systems in one batched solve (the mode the solver picks;
     both modes are timed) vs one prcg_solve per system."""
     A, offs, b, xs, eps = problems.config4()
@@ -150,7 +156,6 @@ def batched_section(torch, prcg, problems, traffic):
     bt = torch.as_tensor(b, device="cuda")
     x, iters, status = B.solve(bt, "pr", 1e-10, 20000)  # includes the autotuner's trial runs
     assert all(st == "ok" for st in status)
-    reps = 3
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
@@ -176,27 +181,91 @@ def batched_section(torch, prcg, problems, traffic):
     per_row_matrix = 8.0 * 5  # offset-aligned slices: 8 bytes per stored entry, 5 entries per row
     moved = float(np.sum(iters * sizes * (80.0 + per_row_matrix)))
     # sequential: one handle and one solve per system (handles created before timing)
-    mats = [problems.batch_system(s_)[0] for s_ in range(len(sizes))]
-    handles = [prcg.Matrix(m.row_ptr, m.col_idx, m.values, "none") for m in mats]
-    bs = [bt[offs[s_]:offs[s_ + 1]].contiguous() for s_ in range(len(sizes))]
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    seq_iters = 0
-    for h, bb in zip(handles, bs):
-        _, info = h.solve(bb, "pr", 1e-10, 20000)
-        seq_iters += info.iters
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t
-    for h in handles:
-        h.close()
+    t_seq, seq_iters = float("nan"), 0
+    if sequential:
+        mats = [problems.batch_system(s_)[0] for s_ in range(len(sizes))]
+        handles = [prcg.Matrix(m.row_ptr, m.col_idx, m.values, "none") for m in mats]
+        bs = [bt[offs[s_]:offs[s_ + 1]].contiguous() for s_ in range(len(sizes))]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for h, bb in zip(handles, bs):
+            _, info = h.solve(bb, "pr", 1e-10, 20000)
+            seq_iters += info.iters
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t
+        for h in handles:
+            h.close()
     B.close()
     M.close()
     return {"workload": "aniso2d_batch_512", "systems": int(len(sizes)), "n_total": int(A.n),
             "nnz_total": int(A.nnz), "batched_solves_per_s": len(sizes) / t_batch, "batched_ms": t_batch * 1e3,
-            "sequential_solves_per_s": len(sizes) / t_seq, "sequential_ms": t_seq * 1e3,
-            "speedup": t_seq / t_batch, "iterations_total": int(iters.sum()), "sequential_iterations": seq_iters,
+            "sequential_solves_per_s": len(sizes) / t_seq if sequential else None,
+            "sequential_ms": t_seq * 1e3 if sequential else None,
+            "speedup": t_seq / t_batch if sequential else None, "iterations_total": int(iters.sum()), "sequential_iterations": seq_iters,
             "algorithmic_GBps": moved / t_batch / 1e9, "mode": mode, "modes": per_mode,
             "threads_per_workgroup": nt, "workgroups": grid}
+
+
+def roofline_of(kernel_us, fmt_bytes, csr_bytes):
+    """A kernel's achieved GB/s and fraction of peak on two byte counts: the
+    bytes its own storage format must move (the SELL-64 layout: offset-aligned
+    slices store no column index) and the CSR count of the byte model
+    (12 nnz + 4 (n + 1) for the matrix), which overstates what this format
+    reads."""
+    sec = kernel_us * 1e-6
+    return {"bytes_per_launch": fmt_bytes, "achieved": fmt_bytes / sec / 1e9,
+            "frac": fmt_bytes / sec / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_launch_csr_model": csr_bytes, "achieved_csr_model": csr_bytes / sec / 1e9,
+            "frac_csr_model": csr_bytes / sec / 1e9 / HBM_PEAK_GBS}
+
+
+def varcoef27_section(torch, prcg, problems, traffic):
+    """The 27-point variable-coefficient problem on 160^3 cells (n 4,096,000,
+    nnz 109,215,352, lognormal(0,1) cell coefficients, no preconditioner),
+    whose 1.2 GB iteration streams from HBM: complete solves to 1e-10 of
+    HS-CG, PR-CG and pipe-PR-CG (best of 2, us per iteration and algorithmic
+    GB/s over the iteration) and every kernel's full-work launch time (100
+    iterations at tol = 0, HIP dispatch events)."""
+    pr = problems.config3b()
+    A = pr.A
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    b = torch.as_tensor(pr.b, device="cuda")
+    props = M.props
+    n = A.n
+    csr = traffic.csr_matrix_bytes(n, A.nnz)
+    out = {"workload": "varcoef27_160", "n": int(n), "nnz": int(A.nnz), "precond": "none", "tol": TOL,
+           "matrix_bytes_format": int(props.matrix_bytes), "matrix_bytes_csr_model": int(csr),
+           "grid": int(props.grid), "variants": {}}
+    for v in ("hs", "pr", "pipe_pr"):
+        _, info = M.solve(b, v, TOL, 20000)
+        best = float("inf")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = M.solve(b, v, TOL, 20000)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        it_fmt = traffic.iteration_bytes(v, False, n, props.matrix_bytes)
+        it_csr = traffic.iteration_bytes(v, False, n, csr)
+        sec = best / max(info.iters, 1)
+        kt = M.time_kernels(v, 100)
+        kb = traffic.kernel_bytes(v, False, n, props.matrix_bytes)
+        kc = traffic.kernel_bytes(v, False, n, csr)
+        out["variants"][v] = {
+            "iters": info.iters, "status": info.status, "relres_true": info.relres_true,
+            "us_per_iter": sec * 1e6, "iters_per_s": 1.0 / sec,
+            "bytes_per_iter": it_fmt, "algorithmic_GBps": it_fmt / sec / 1e9,
+            "frac": it_fmt / sec / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_iter_csr_model": it_csr, "frac_csr_model": it_csr / sec / 1e9 / HBM_PEAK_GBS,
+            "kernels": {k: {"us": ms * 1e3, **(roofline_of(ms * 1e3, kb[k], kc[k]) if k in kb else {})}
+                        for k, ms in kt}}
+    prk = out["variants"]["pr"]["kernels"]
+    dom = max((k for k in prk if "bytes_per_launch" in prk[k]), key=lambda k: prk[k]["us"])
+    out["dominant_kernel"] = {"kernel": dom, "us_per_launch": prk[dom]["us"], **{k: v for k, v in prk[dom].items()
+                                                                                 if k != "us"},
+                              "traffic": load_traffic(dom, "varcoef27_160")}
+    M.close()
+    return out
 
 
 def unrolled_pr_cg(torch, rows, cols, vals, b, iters):
@@ -235,14 +304,26 @@ def adjoint_section(torch, prcg, problems):
     vals0 = torch.as_tensor(A.values, device="cuda")
     b0 = torch.as_tensor(pr.b, device="cuda")
 
-    def adjoint_grad():
+    def adjoint_grad(tol=1e-10):
         vals = vals0.clone().requires_grad_(True)
         b = b0.clone().requires_grad_(True)
-        x = dsolve(vals, b, M, "pr", 1e-10, 20000)
+        x = dsolve(vals, b, M, "pr", tol, 20000)
         (w * x).sum().backward()
         return vals.grad, b.grad
 
+    def rel(g, ref):
+        return float((g - ref).abs().max() / ref.abs().max())
+
+    # reference gradients: forward and adjoint solves to 1e-13 (1e-12 if the
+    # updated residual does not get there)
+    try:
+        ref_tol = 1e-13
+        gv_ref, gb_ref = adjoint_grad(ref_tol)
+    except RuntimeError:
+        ref_tol = 1e-12
+        gv_ref, gb_ref = adjoint_grad(ref_tol)
     gv, gb = adjoint_grad()
+    err_adj = {"values": rel(gv, gv_ref), "b": rel(gb, gb_ref)}
     reps = 3
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -262,24 +343,49 @@ def adjoint_section(torch, prcg, problems):
         (w * x).sum().backward()
         return vals.grad, b.grad
 
-    # the unrolled values-gradient converges about twice as slowly as the
-    # iterate: time it at the forward iteration count and at twice that
+    # Equal accuracy: the unrolled gradients at the forward iteration count
+    # and at 2x and 3x that count, until both are as close to the reference
+    # gradients (max relative difference) as the adjoint's are; the unrolled
+    # graph keeps every iteration's vectors, so a count whose predicted
+    # memory exceeds 3/4 of the free device memory is not run.
     unrolled = {}
     unrolled_grad(iters)  # warm-up (allocator, kernels)
-    for k in (iters, 2 * iters):
+    matched = None
+    for k in (iters, 2 * iters, 3 * iters):
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        free, _ = torch.cuda.mem_get_info()
+        if unrolled:
+            last = unrolled[max(unrolled)]
+            if last["peak_bytes"] / last["iterations"] * k > 0.75 * free:
+                break
         t = time.perf_counter()
         uv, ub = unrolled_grad(k)
         torch.cuda.synchronize()
         unrolled[k] = {"iterations": k, "ms": (time.perf_counter() - t) * 1e3,
-                       "max_rel_diff_values_grad": float((uv - gv).abs().max() / gv.abs().max()),
-                       "max_rel_diff_b_grad": float((ub - gb).abs().max() / gb.abs().max())}
+                       "max_rel_diff_values_grad": rel(uv, gv), "max_rel_diff_b_grad": rel(ub, gb),
+                       "error_values_grad": rel(uv, gv_ref), "error_b_grad": rel(ub, gb_ref),
+                       "peak_bytes": int(torch.cuda.max_memory_allocated() - base)}
+        del uv, ub
+        if unrolled[k]["error_values_grad"] <= err_adj["values"] and unrolled[k]["error_b_grad"] <= err_adj["b"]:
+            matched = k
+            break
     M.close()
-    same, twice = unrolled[iters], unrolled[2 * iters]
+    same, last = unrolled[iters], unrolled[max(unrolled)]
+    ref = unrolled[matched] if matched else last
     return {"workload": "varcoef7_96", "n": int(A.n), "nnz": int(A.nnz), "forward_iterations": iters,
             "adjoint_gradients_per_s": 1.0 / t_adj, "adjoint_ms": t_adj * 1e3,
-            "unrolled_autograd_gradients_per_s": 1e3 / twice["ms"], "speedup": twice["ms"] * 1e-3 / t_adj,
-            "unrolled_same_iterations": same, "unrolled_twice_iterations": twice,
+            "equal_accuracy": {"criterion": "each unrolled gradient at most as far (max relative difference) "
+                                            "from the gradients of solves to ref_tol as the adjoint's",
+                               "ref_tol": ref_tol,
+                               "adjoint_error_values_grad": err_adj["values"], "adjoint_error_b_grad": err_adj["b"],
+                               "reached_at_iterations": matched, "searched_iterations": sorted(unrolled),
+                               "note": None if matched else "not reached: the speedup is against the most "
+                                       "iterations run, a lower bound on the unrolled cost at equal accuracy"},
+            "unrolled_autograd_gradients_per_s": 1e3 / ref["ms"], "speedup": ref["ms"] * 1e-3 / t_adj,
+            "unrolled": [unrolled[k] for k in sorted(unrolled)],
             "speedup_vs_same_iterations": same["ms"] * 1e-3 / t_adj}
 
 
@@ -338,12 +444,15 @@ def main():
         suite(torch, prcg, problems)
         return
     if args.batched_only:
-        print(json.dumps(batched_section(torch, prcg, problems, traffic)), flush=True)
+        print(json.dumps(batched_section(torch, prcg, problems, traffic, args.batched_reps, not args.no_sequential)),
+              flush=True)
         return
-    pr = problems.config2(m=args.m)
+    if args.kernels_only and args.workload == "varcoef27_160":
+        pr, workload, pre = problems.config3b(), "varcoef27_160", "none"
+    else:
+        pr, workload, pre = problems.config2(m=args.m), f"poisson3d_{args.m}_jacobi", "jacobi"
     A = pr.A
-    workload = f"poisson3d_{args.m}_jacobi"
-    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, pre)
     if args.grid:
         M.set_grid(args.grid)
     M.set_kernels(args.kernels)
@@ -360,10 +469,13 @@ def main():
         torch.cuda.synchronize()
         kt = M.time_kernels(args.variant, 200)
         fused = any("fused" in name for name, _ in kt)  # the structure the variant runs
-        kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
+        jac = pre == "jacobi"
+        kb = traffic.kernel_bytes(args.variant, jac, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
+        kc = traffic.kernel_bytes(args.variant, jac, n, traffic.csr_matrix_bytes(n, A.nnz), fused,
+                                  nu_in_update=nu_split(M))
         print(json.dumps({"workload": workload, "variant": args.variant, "launches": 200,
-                          "kernels": {k: {"us": ms * 1e3, "bytes": kb.get(k, 0),
-                                          "GBps": kb.get(k, 0) / (ms * 1e-3) / 1e9} for k, ms in kt}}))
+                          "kernels": {k: {"us": ms * 1e3, **(roofline_of(ms * 1e3, kb[k], kc[k]) if k in kb else {})}
+                                      for k, ms in kt}}))
         return
 
     def solve(variant):
@@ -424,11 +536,15 @@ def main():
     fused = any("fused" in name for name in kt)  # the structure the variant runs
     kb = traffic.kernel_bytes(args.variant, True, n, props.matrix_bytes, fused, nu_in_update=nu_split(M))
     dom = max((k for k in kt if k in kb), key=lambda k: kt[k])
-    achieved = kb[dom] / (kt[dom] * 1e-3) / 1e9
+    kc = traffic.kernel_bytes(args.variant, True, n, traffic.csr_matrix_bytes(n, A.nnz), fused,
+                              nu_in_update=nu_split(M))
+    rl = roofline_of(kt[dom] * 1e3, kb[dom], kc[dom])
     tb = load_traffic(dom, workload)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": kb[dom], "us_per_launch": kt[dom] * 1e3,
-                "traffic": tb}
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": rl["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": rl["frac"], "traffic": tb, "bytes": "sell64_format",
+                "bytes_per_launch": kb[dom], "us_per_launch": kt[dom] * 1e3, "launches_timed": 200,
+                "bytes_per_launch_csr_model": kc[dom], "achieved_csr_model": rl["achieved_csr_model"],
+                "frac_csr_model": rl["frac_csr_model"]}
 
     cpu = None
     cpu_host = None
@@ -462,6 +578,7 @@ def main():
     triad = stream_triad(torch)
     batched = None if args.no_batched else batched_section(torch, prcg, problems, traffic)
     adjoint = None if args.no_adjoint else adjoint_section(torch, prcg, problems)
+    varcoef27 = None if args.no_27pt else varcoef27_section(torch, prcg, problems, traffic)
 
     out = {
         "metric": "CG iterations/sec (FP64 PR-CG solve to 1e-10 relative residual)",
@@ -492,6 +609,7 @@ def main():
         "cpu_host": cpu_host,
         "batched": batched,
         "adjoint": adjoint,
+        "varcoef27_160": varcoef27,
     }
     print(json.dumps(out))
 
