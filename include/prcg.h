@@ -167,9 +167,9 @@ typedef struct {
  *   All two-pass placements add the partials in the same fixed order:
  *   results are bitwise identical across them.
  *   PRCG_OPT_GRID  largest number of workgroups of the row-parallel kernels
- *     (8..8192; the actual count is a multiple of 8), or 0 (the default):
+ *     (8..16384; the actual count is a multiple of 8), or 0 (the default):
  *     by size, one 256-row group per workgroup from 8192 groups (2M rows)
- *     up (at most 8192 workgroups), else at most 1024. */
+ *     up (at most 16384 workgroups), else at most 1024. */
 typedef enum { PRCG_OPT_KERNELS = 0, PRCG_OPT_GRID = 1 } prcg_option;
 typedef enum {
     PRCG_KERNELS_FUSED = 0,
@@ -247,7 +247,7 @@ prcg_status prcg_solve(prcg_matrix A, prcg_variant v, const double* b, double* x
  * hipMalloc.  Same arguments, results and bits as prcg_solve on the same
  * handle, but the call allocates nothing: the partial sums, the scalar
  * state and the residual history live in a fixed device array of the
- * library (about 1.6 MB per device, held from the first such call until the
+ * library (about 2.8 MB per device, held from the first such call until the
  * process ends), and the iterations are launched directly instead of
  * through an instantiated graph.  The handle (created beforehand) still
  * owns the vectors.

@@ -20,10 +20,15 @@ struct BatchView {
 
 // Row groups of the lockstep solver: up to kLockstepSlices consecutive
 // slices (rows row0 .. row0 + nrows - 1) of one system, whose rows are
-// lo .. hi; system s owns groups [sys_grp0[s], sys_grp0[s+1]).  One 32-byte
-// record per group, so a workgroup learns everything about its group in one
-// round trip.  (Rows and slices fit int32: column indices are int32.)
+// lo .. hi; system s owns groups [sys_grp0[s], sys_grp0[s+1]).  A uniform
+// group (off >= 0) holds offset-aligned slices of one width (1 ..
+// kUniformMaxWidth) and one list of column offsets, soff[off .. off +
+// width - 1], stored one after another from value slot 64 vrow: the
+// product reads everything about it from this record.  Other groups
+// (off < 0) hold any slices and take the general slice-by-slice product.
+// (Rows, slices and value slots / 64 fit int32: column indices are int32.)
 constexpr int kLockstepSlices = 16;
+constexpr int kUniformMaxWidth = 8;
 struct Group {
     int32_t slice0;
     int32_t row0;
@@ -32,9 +37,12 @@ struct Group {
     int32_t nrows;
     int32_t lo;
     int32_t hi;
-    int32_t spare;
+    int32_t off;    // uniform groups: first of the slices' common offsets in soff; -1 otherwise
+    int32_t width;  // uniform groups: slots per row
+    int32_t vrow;   // uniform groups: the first slice's values start at slot 64 vrow
+    int32_t spare0, spare1;
 };
-static_assert(sizeof(Group) == 32, "two 16-byte loads per group");
+static_assert(sizeof(Group) == 48, "three 16-byte loads per group");
 struct GroupView {
     const Group* grp;          // [ngroups]
     const int64_t* sys_grp0;   // [nsys + 1]

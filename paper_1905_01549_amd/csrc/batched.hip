@@ -359,13 +359,71 @@ __global__ void k_batch_reset(int32_t* queue) { *queue = 0; }
 // system that has finished (its state says done) costs each of its groups
 // one load of the flag per launch.
 
+// Product of a uniform row group (Group: offset-aligned slices of width W
+// with one list of column offsets, stored one after another): wave w takes
+// slices w, w + kWaves, ... of the group, R = kLockstepSlices / kWaves of
+// them, in rounds of RR slices (RR W <= 20 value loads, to bound the
+// registers): a round issues the loads of its values, of the W offsets and
+// of each row's own entries (pre(i, row)) together, before any gather, so a
+// round costs two memory round trips.  Slices past the group's end are
+// clamped to its last slice (their loads stay inside the group; their rows
+// are skipped).  Calls f(i, row, y) for the valid rows in slice order, y
+// summed over the slots in stored order from 0.0 as in sell_row.
+template <int W, class Pre, class F>
+__device__ __forceinline__ void uniform_group(const SellView& A, const Group& G, const double* __restrict__ x,
+                                              Pre&& pre, F&& f)
+{
+    constexpr int R = kLockstepSlices / kWaves;
+    constexpr int RR = W * R <= 20 ? R : (W * R / 2 <= 20 ? R / 2 : 1);
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    int o[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) o[u] = A.soff[G.off + u];
+    const double* __restrict__ vb = A.val + (int64_t)G.vrow * kSlice + lane;
+#pragma unroll
+    for (int i0 = 0; i0 < R; i0 += RR) {
+        int row[RR];
+        bool valid[RR];
+        double a[RR][W];
+#pragma unroll
+        for (int j = 0; j < RR; ++j) {
+            const int sl = w + kWaves * (i0 + j);
+            const int slc = min(sl, G.nsl - 1);
+            const int local = slc * kSlice + lane;
+            valid[j] = sl < G.nsl && local < G.nrows;
+            row[j] = G.row0 + min(local, G.nrows - 1);
+#pragma unroll
+            for (int u = 0; u < W; ++u) a[j][u] = vb[(int64_t)(slc * W + u) * kSlice];
+            pre(i0 + j, row[j]);
+        }
+        double g[RR][W];
+#pragma unroll
+        for (int j = 0; j < RR; ++j) {
+#pragma unroll
+            for (int u = 0; u < W; ++u) g[j][u] = x[min(max(row[j] + o[u], G.lo), G.hi)];
+        }
+#pragma unroll
+        for (int j = 0; j < RR; ++j) {
+            double y = 0.0;
+#pragma unroll
+            for (int u = 0; u < W; ++u) y = fma(a[j][u], g[j][u], y);
+            if (valid[j]) f(i0 + j, row[j], y);
+        }
+    }
+}
+
+// Occupancy floor of the lockstep product (wavefronts per SIMD: at most
+// 128 registers per thread).
+constexpr int kLockstepSpmvWaves = 4;
+
 // PHASE 1: r0 = b - A x0, r~0 = M^{-1} r0, p0 = r~0 and the <b, b> partial.
 // PHASE 2: s0 = A p0 and the partials of mu, sigma, gamma, nu, <r, r>.
 // PHASE 0: the same product for an iteration of a system still running.
 // The group's slices go through sys_spmv (two slices per wavefront with
 // their loads in flight together).
 template <bool PRE, int PHASE>
-__global__ __launch_bounds__(kBlock) void k_ls_spmv(BatchView B, GroupView gv, const State* __restrict__ S, Vecs v,
+__global__ __launch_bounds__(kBlock, kLockstepSpmvWaves) void k_ls_spmv(BatchView B, GroupView gv, const State* __restrict__ S, Vecs v,
                                                     const double* __restrict__ b, double* __restrict__ P)
 {
     __shared__ double lds[kWaves * 5];
@@ -381,28 +439,65 @@ __global__ __launch_bounds__(kBlock) void k_ls_spmv(BatchView B, GroupView gv, c
     double q[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) q[i] = 0.0;
-    sys_spmv<kBlock, 1>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, PHASE == 1 ? v.x : p, nullptr,
-                        [&](int64_t row, double y0, double) {
-                            if constexpr (PHASE == 1) {
-                                const double bi = b[row];
-                                const double ri = bi - y0;
-                                const double rti = PRE ? d[row] * ri : ri;
-                                r[row] = ri;
-                                if (PRE) rt[row] = rti;
-                                p[row] = rti;
-                                q[0] = fma(bi, bi, q[0]);
-                            } else {
-                                s[row] = y0;
-                                const double ri = r[row];
-                                const double rti = PRE ? rt[row] : ri;
-                                const double sti = PRE ? d[row] * y0 : y0;
-                                q[0] = fma(p[row], y0, q[0]);
-                                q[1] = fma(rti, y0, q[1]);
-                                q[2] = fma(sti, y0, q[2]);
-                                q[3] = fma(rti, ri, q[3]);
-                                if (PRE) q[4] = fma(ri, ri, q[4]);
-                            }
-                        });
+    // the row's contribution once y = (A x)_row is known; e0 .. e3 hold the
+    // row's own entries (PHASE 1: b; else p, r, r~, d)
+    auto row_done = [&](int64_t row, double y0, double e0, double e1, double e2, double e3) {
+        if constexpr (PHASE == 1) {
+            const double bi = e0;
+            const double ri = bi - y0;
+            const double rti = PRE ? e3 * ri : ri;
+            r[row] = ri;
+            if (PRE) rt[row] = rti;
+            p[row] = rti;
+            q[0] = fma(bi, bi, q[0]);
+        } else {
+            s[row] = y0;
+            const double ri = e1;
+            const double rti = PRE ? e2 : ri;
+            const double sti = PRE ? e3 * y0 : y0;
+            q[0] = fma(e0, y0, q[0]);
+            q[1] = fma(rti, y0, q[1]);
+            q[2] = fma(sti, y0, q[2]);
+            q[3] = fma(rti, ri, q[3]);
+            if (PRE) q[4] = fma(ri, ri, q[4]);
+        }
+    };
+    const double* __restrict__ xin = PHASE == 1 ? v.x : p;
+    if (G.off >= 0) {
+        constexpr int R = kLockstepSlices / kWaves;
+        double e0[R], e1[R], e2[R], e3[R];
+        auto pre = [&](int i, int row) {
+            if constexpr (PHASE == 1) {
+                e0[i] = b[row];
+                e1[i] = e2[i] = 0.0;
+                e3[i] = PRE ? d[row] : 1.0;
+            } else {
+                e0[i] = p[row];
+                e1[i] = r[row];
+                e2[i] = PRE ? rt[row] : 0.0;
+                e3[i] = PRE ? d[row] : 1.0;
+            }
+        };
+        auto f = [&](int i, int row, double y) { row_done(row, y, e0[i], e1[i], e2[i], e3[i]); };
+        switch (G.width) {
+        case 1: uniform_group<1>(B.A, G, xin, pre, f); break;
+        case 2: uniform_group<2>(B.A, G, xin, pre, f); break;
+        case 3: uniform_group<3>(B.A, G, xin, pre, f); break;
+        case 4: uniform_group<4>(B.A, G, xin, pre, f); break;
+        case 5: uniform_group<5>(B.A, G, xin, pre, f); break;
+        case 6: uniform_group<6>(B.A, G, xin, pre, f); break;
+        case 7: uniform_group<7>(B.A, G, xin, pre, f); break;
+        default: uniform_group<kUniformMaxWidth>(B.A, G, xin, pre, f); break;
+        }
+    } else {
+        sys_spmv<kBlock, 1>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, xin, nullptr,
+                            [&](int64_t row, double y0, double) {
+                                if constexpr (PHASE == 1)
+                                    row_done(row, y0, b[row], 0.0, 0.0, PRE ? d[row] : 1.0);
+                                else
+                                    row_done(row, y0, p[row], r[row], PRE ? rt[row] : 0.0, PRE ? d[row] : 1.0);
+                            });
+    }
     block_sum<NV, kWaves>(q, lds);
     if (threadIdx.x == 0) {
         const int64_t ng = gv.ngroups;

@@ -204,6 +204,7 @@ struct prcg_batch_s {
     int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
     // lockstep solver (PR-CG, M-CG): row groups, per-system states, partials
     int64_t ngroups = 0;
+    int64_t uniform_groups = 0;
     Group* grp = nullptr;
     int64_t* sys_grp0 = nullptr;
     State* lstate = nullptr;
@@ -640,11 +641,11 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     }
     // runs of up to kRunSlices consecutive slices of one width and kind,
     // each stored slot-major, for matrices whose default grid gives every
-    // workgroup at least one 256-row group (from kMaxGrid groups up);
+    // workgroup at least one 256-row group (from kBigGroups groups up);
     // smaller ones keep single slices (measured on MI355X: runs take 6% off
     // the 27-point 160^3 product at 8192 workgroups, but slow the fused
     // PR-CG iteration of an 884,736-row problem at 1024 workgroups by 7%)
-    const int64_t run_max = (n + kGroupRows - 1) / kGroupRows >= kMaxGrid ? kRunSlices : 1;
+    const int64_t run_max = (n + kGroupRows - 1) / kGroupRows >= kBigGroups ? kRunSlices : 1;
     std::vector<int64_t> hptr((size_t)A->nslices + 1);
     std::vector<int32_t> hmeta((size_t)A->nslices), hshape((size_t)A->nslices);
     int64_t pos = 0;
@@ -742,7 +743,7 @@ prcg_status prcg_set_option(prcg_matrix A, int32_t option, int32_t value)
         A->kernels_mode = value;
     } else if (option == PRCG_OPT_GRID) {
         if (value != 0 && (value < 8 || value > kMaxGrid))
-            return fail(PRCG_EINVAL, "grid must be 0 (by size) or in [8, 8192]");
+            return fail(PRCG_EINVAL, "grid must be 0 (by size) or in [8, 16384]");
         A->grid_opt = value;
     } else {
         return fail(PRCG_EINVAL, "unknown option");
@@ -1067,36 +1068,6 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
             B->stream_from = q + 1;
             break;
         }
-    // row groups of the lockstep solver: up to kLockstepSlices slices of one system
-    std::vector<Group> grp;
-    std::vector<int64_t> sys_grp0((size_t)nsys + 1);
-    for (int32_t q = 0; q < nsys; ++q) {
-        sys_grp0[q] = (int64_t)grp.size();
-        for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1]; s0 += kLockstepSlices) {
-            Group G{};
-            G.slice0 = (int32_t)s0;
-            G.nsl = (int32_t)std::min<int64_t>(kLockstepSlices, sys_slice0[q + 1] - s0);
-            G.row0 = (int32_t)slice_row0[(size_t)s0];
-            const int64_t last = s0 + G.nsl - 1;
-            G.nrows = (int32_t)(slice_row0[(size_t)last] + slice_nrows[(size_t)last] - G.row0);
-            G.sys = q;
-            G.lo = (int32_t)sys_row_offset[q];
-            G.hi = (int32_t)(sys_row_offset[q + 1] - 1);
-            grp.push_back(G);
-        }
-    }
-    sys_grp0[nsys] = (int64_t)grp.size();
-    B->ngroups = sys_grp0[nsys];
-    BTRY(hipMalloc(&B->grp, sizeof(Group) * B->ngroups));
-    BTRY(hipMalloc(&B->sys_grp0, sizeof(int64_t) * (nsys + 1)));
-    BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
-    BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * B->ngroups));
-    BTRY(hipMalloc(&B->lactive, sizeof(int32_t) * 4));
-    BTRY(hipHostMalloc(&B->hactive, sizeof(int32_t) * 2, hipHostMallocDefault));
-    BTRY(hipEventCreateWithFlags(&B->lev[0], hipEventDisableTiming));
-    BTRY(hipEventCreateWithFlags(&B->lev[1], hipEventDisableTiming));
-    BTRY(hipMemcpyAsync(B->grp, grp.data(), sizeof(Group) * B->ngroups, hipMemcpyHostToDevice, st));
-    BTRY(hipMemcpyAsync(B->sys_grp0, sys_grp0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
     BTRY(hipMalloc(&B->slice_ptr, sizeof(int64_t) * (ns + 1)));
     BTRY(hipMalloc(&B->slice_meta, sizeof(int32_t) * ns));
     BTRY(hipMalloc(&B->slice_shape, sizeof(int32_t) * ns));
@@ -1108,6 +1079,64 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     BTRY(hipMemcpyAsync(B->slice_shape, hshape.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
     BTRY(launch_fill_sell(n, ns, A->row_ptr, A->col, A->val, B->slice_row0, B->slice_nrows, B->slice_ptr,
                           B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, 1, st));
+    // Row groups of the lockstep solver: runs of up to kLockstepSlices slices
+    // of one system.  Offset-aligned slices of one width (at most
+    // kUniformMaxWidth) with the same column offsets form uniform groups,
+    // which the product multiplies with all their value loads issued at
+    // once; every other run of slices forms a general group.
+    std::vector<int32_t> hsoff((size_t)std::max<int64_t>(noff, 1));
+    if (noff > 0) {
+        BTRY(hipMemcpyAsync(hsoff.data(), B->soff, sizeof(int32_t) * noff, hipMemcpyDeviceToHost, st));
+        BTRY(hipStreamSynchronize(st));
+    }
+    auto uniform_slice = [&](int64_t q) {
+        return aligned[q] && width[q] >= 1 && width[q] <= kUniformMaxWidth && hptr[q] / kSlice < INT32_MAX;
+    };
+    auto same_key = [&](int64_t q, int64_t t) {
+        if (uniform_slice(q) != uniform_slice(t)) return false;
+        if (!uniform_slice(q)) return true;
+        if (width[q] != width[t]) return false;
+        for (int32_t u = 0; u < width[q]; ++u)
+            if (hsoff[(size_t)hmeta[q] + u] != hsoff[(size_t)hmeta[t] + u]) return false;
+        return true;
+    };
+    std::vector<Group> grp;
+    std::vector<int64_t> sys_grp0((size_t)nsys + 1);
+    for (int32_t q = 0; q < nsys; ++q) {
+        sys_grp0[q] = (int64_t)grp.size();
+        for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1];) {
+            int64_t len = 1;
+            while (len < kLockstepSlices && s0 + len < sys_slice0[q + 1] && same_key(s0, s0 + len)) ++len;
+            Group G{};
+            G.slice0 = (int32_t)s0;
+            G.nsl = (int32_t)len;
+            G.row0 = (int32_t)slice_row0[(size_t)s0];
+            const int64_t last = s0 + len - 1;
+            G.nrows = (int32_t)(slice_row0[(size_t)last] + slice_nrows[(size_t)last] - G.row0);
+            G.sys = q;
+            G.lo = (int32_t)sys_row_offset[q];
+            G.hi = (int32_t)(sys_row_offset[q + 1] - 1);
+            G.off = uniform_slice(s0) ? hmeta[s0] : -1;
+            G.width = width[s0];
+            G.vrow = (int32_t)(hptr[s0] / kSlice);
+            grp.push_back(G);
+            s0 += len;
+        }
+    }
+    sys_grp0[nsys] = (int64_t)grp.size();
+    B->ngroups = sys_grp0[nsys];
+    B->uniform_groups = 0;
+    for (const Group& G : grp) B->uniform_groups += G.off >= 0;
+    BTRY(hipMalloc(&B->grp, sizeof(Group) * B->ngroups));
+    BTRY(hipMalloc(&B->sys_grp0, sizeof(int64_t) * (nsys + 1)));
+    BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
+    BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * B->ngroups));
+    BTRY(hipMalloc(&B->lactive, sizeof(int32_t) * 4));
+    BTRY(hipHostMalloc(&B->hactive, sizeof(int32_t) * 2, hipHostMallocDefault));
+    BTRY(hipEventCreateWithFlags(&B->lev[0], hipEventDisableTiming));
+    BTRY(hipEventCreateWithFlags(&B->lev[1], hipEventDisableTiming));
+    BTRY(hipMemcpyAsync(B->grp, grp.data(), sizeof(Group) * B->ngroups, hipMemcpyHostToDevice, st));
+    BTRY(hipMemcpyAsync(B->sys_grp0, sys_grp0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
     // largest systems first
     std::vector<int32_t> order((size_t)nsys);
     for (int32_t q = 0; q < nsys; ++q) order[q] = q;

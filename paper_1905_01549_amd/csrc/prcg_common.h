@@ -12,7 +12,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kSlice = 64;      // SELL slice height: one wavefront, one row per lane
 constexpr int kGroupRows = kBlock;  // rows handled by one workgroup step (4 slices)
 constexpr int kMaxDots = 5;
-constexpr int kMaxGrid = 8192;  // largest workgroup count of the row-parallel kernels
+constexpr int kMaxGrid = 16384;  // largest workgroup count of the row-parallel kernels
 
 enum Variant {
     kHS = 0,

@@ -45,25 +45,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NW * N
 // P1[i * Gs + g], value i >= N1 from P2[(i - N1) * Gs + g] (two kernels may
 // produce the partials of one reduction; the rows are 16-byte aligned).  The
 // order: the partials are taken in pairs (2k, 2k + 1), read as one 16-byte
-// load; lane t < kBlock owns the pairs k = t + kBlock j, j = 0 .. 2 kLanePairs
-// - 1 (partials at or beyond G count as absent), and adds the partials of
-// the first kLanePairs of them in order from 0.0, then those of the rest
-// likewise, and adds the two sums; the kBlock lane sums go through
+// load; lane t < kBlock owns the pairs k = t + kBlock j, j = 0 .. kChunks
+// kChunkPairs - 1 (partials at or beyond G count as absent), in kChunks
+// chunks of kChunkPairs consecutive j; each chunk's partials are added in
+// order from 0.0, and the lane's sum is ((c_0 + c_1) + c_2) + c_3 over its
+// chunk sums (an absent chunk adds 0.0); the kBlock lane sums go through
 // block_sum.  Every thread receives the totals.
 //
 // ALL = false (kernels that reduce beside other work, kBlock threads):
-// thread t is lane t and loads two pairs per value at a time (one in the
-// second half), to keep its register count down.  lds: kWaves * NV doubles.
+// thread t is lane t and walks its chunks in order, loading two pairs per
+// value at a time, to keep its register count down.  lds: kWaves * NV
+// doubles.
 // ALL = true (the one-workgroup stage-2 kernels, kStage2Block = 2 kBlock
-// threads): threads t and t + kBlock take the two halves of lane t, each
-// with all its loads issued before its first addition, so stage 2 costs one
-// memory round trip; the second half's wavefronts load nothing when G fits
-// in the first.  lds: kStage2Waves * NV doubles.
+// threads): threads t and t + kBlock take the chunks of lane t in turns
+// (chunks 0 and 2, and 1 and 3), each chunk with all its loads issued before
+// its first addition, so stage 2 costs one memory round trip up to
+// G = 2 kBlock kChunkPairs partials and two beyond; chunks without a
+// partial below G load nothing.  lds: kStage2Waves * NV doubles.
 // (Measured on MI355X: a one-workgroup reduction is bound by its load
 // instructions, so 16-byte loads halve its cost; 1024-thread workgroups are
 // limited to 128 registers per thread and spilled.)  The bits are the same
 // either way.
-constexpr int kLanePairs = kMaxGrid / kBlock / 4;  // pairs per lane half
+constexpr int kChunkPairs = 8;                                  // pairs per chunk
+constexpr int kChunks = kMaxGrid / (2 * kBlock * kChunkPairs);  // chunks per lane
+static_assert(kChunks == 4, "the lane sum adds four chunk sums");
 constexpr int kStage2Block = 2 * kBlock;
 constexpr int kStage2Waves = kStage2Block / 64;
 
@@ -75,65 +80,90 @@ __device__ __forceinline__ double2 load_pair(const double* __restrict__ P, int k
     return reinterpret_cast<const double2*>(P)[kc];
 }
 
+// adds pair k's partials that lie below G to a
+__device__ __forceinline__ double add_pair(double a, double2 v, int k, int G)
+{
+    a += 2 * k < G ? v.x : 0.0;
+    a += 2 * k + 1 < G ? v.y : 0.0;
+    return a;
+}
+
+// Whether chunk c of some lane holds a partial below G.
+__device__ __forceinline__ bool chunk_used(int c, int G) { return 2 * kBlock * kChunkPairs * c < G; }
+
+// Chunk c of lane `lane` for NV values: every load issued before the first
+// addition (one memory round trip); sums from 0.0 in pair order.
+template <int NV>
+__device__ __forceinline__ void chunk_sum(const double* const (&P)[NV], int lane, int c, int G, double (&sum)[NV])
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sum[i] = 0.0;
+    if (!chunk_used(c, G)) return;
+    double2 buf[NV][kChunkPairs];
+#pragma unroll
+    for (int j = 0; j < kChunkPairs; ++j) {
+        const int k = lane + kBlock * (c * kChunkPairs + j);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) buf[i][j] = load_pair(P[i], k, G);
+    }
+    // keep the scheduler from starting the sums before the last load
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChunkPairs; ++j) sum[i] = add_pair(sum[i], buf[i][j], lane + kBlock * (c * kChunkPairs + j), G);
+    }
+}
+
+template <int NV, int N1>
+__device__ __forceinline__ void partial_rows(const double* __restrict__ P1, const double* __restrict__ P2, int Gs,
+                                             const double* (&P)[NV])
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+}
+
 template <int NV, int N1, bool ALL = false, int M>
 __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1, const double* __restrict__ P2, int G,
                                                    int Gs, double (&tot)[NV], double (&lds)[M])
 {
-    static_assert(kMaxGrid % (4 * kBlock) == 0, "two halves of whole pairs per lane");
     static_assert(M >= (ALL ? kStage2Waves : kWaves) * NV, "lds must hold one sum per wavefront and value");
     const double* P[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
-    // adds pair k's partials that lie below G to a
-    auto add_pair = [G](double a, double2 v, int k) {
-        a += 2 * k < G ? v.x : 0.0;
-        a += 2 * k + 1 < G ? v.y : 0.0;
-        return a;
-    };
+    partial_rows<NV, N1>(P1, P2, Gs, P);
     double acc[NV];
     if constexpr (ALL) {
-        __shared__ double hi[NV][kBlock];  // the second half of each lane
+        __shared__ double odd[2][NV][kBlock];  // chunks 1 and 3 of each lane
         const int lane = threadIdx.x % kBlock;
         const int half = threadIdx.x / kBlock;  // uniform per wavefront
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-        if (half == 0 || 2 * kBlock * kLanePairs < G) {
-            double2 buf[NV][kLanePairs];
-#pragma unroll
-            for (int j = 0; j < kLanePairs; ++j) {
-                const int k = lane + kBlock * (half * kLanePairs + j);
-#pragma unroll
-                for (int i = 0; i < NV; ++i) buf[i][j] = load_pair(P[i], k, G);
-            }
-            // keep the scheduler from starting the sums before the last load
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-#pragma unroll
-                for (int j = 0; j < kLanePairs; ++j)
-                    acc[i] = add_pair(acc[i], buf[i][j], lane + kBlock * (half * kLanePairs + j));
-            }
-        }
+        double c0[NV], c1[NV];
+        chunk_sum<NV>(P, lane, half, G, c0);
+        chunk_sum<NV>(P, lane, half + 2, G, c1);
         if (half == 1) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) hi[i][lane] = acc[i];
+            for (int i = 0; i < NV; ++i) {
+                odd[0][i][lane] = c0[i];
+                odd[1][i][lane] = c1[i];
+            }
         }
         __syncthreads();
         if (half == 0) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + hi[i][lane];
+            for (int i = 0; i < NV; ++i) acc[i] = ((c0[i] + odd[0][i][lane]) + c1[i]) + odd[1][i][lane];
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] = 0.0;
         }
         // every wavefront writes its sum; only the first kWaves (lanes
         // 0 .. kBlock - 1) are added
         block_sum<NV, kWaves>(acc, lds);
     } else {
-        // the first half two pairs per value at a time; the second half
-        // (only when G exceeds the first) one pair at a time, so that its
-        // accumulators cost no registers beyond the first half's
+        // chunk 0 two pairs per value at a time; the other chunks (only when
+        // G exceeds chunk 0) one pair at a time, so that their accumulators
+        // cost no registers beyond chunk 0's
         const int t = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-        for (int j0 = 0; j0 < kLanePairs && 2 * kBlock * j0 < G; j0 += 2) {
+        for (int j0 = 0; j0 < kChunkPairs && 2 * kBlock * j0 < G; j0 += 2) {
             double2 buf[NV][2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -143,25 +173,22 @@ __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i] = add_pair(acc[i], buf[i][j], t + kBlock * (j0 + j));
+                for (int j = 0; j < 2; ++j) acc[i] = add_pair(acc[i], buf[i][j], t + kBlock * (j0 + j), G);
             }
         }
-        if (2 * kBlock * kLanePairs < G) {
-            double hv[NV];
+        for (int c = 1; c < kChunks; ++c) {
+            double cs[NV];
 #pragma unroll
-            for (int i = 0; i < NV; ++i) hv[i] = 0.0;
-            for (int j = kLanePairs; j < 2 * kLanePairs && 2 * kBlock * j < G; ++j) {
+            for (int i = 0; i < NV; ++i) cs[i] = 0.0;
+            for (int j = c * kChunkPairs; j < (c + 1) * kChunkPairs && 2 * kBlock * j < G; ++j) {
                 double2 buf[NV];
 #pragma unroll
                 for (int i = 0; i < NV; ++i) buf[i] = load_pair(P[i], t + kBlock * j, G);
 #pragma unroll
-                for (int i = 0; i < NV; ++i) hv[i] = add_pair(hv[i], buf[i], t + kBlock * j);
+                for (int i = 0; i < NV; ++i) cs[i] = add_pair(cs[i], buf[i], t + kBlock * j, G);
             }
 #pragma unroll
-            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + hv[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + 0.0;  // the empty second half
+            for (int i = 0; i < NV; ++i) acc[i] = acc[i] + cs[i];
         }
         block_sum<NV>(acc, lds);
     }
@@ -171,55 +198,36 @@ __device__ __forceinline__ void reduce_partials_at(const double* __restrict__ P1
 
 // Stage 2 split over kWaves workgroups (grid kWaves, kWaveBlock threads):
 // workgroup w forms the sum of lanes 64 w .. 64 w + 63 of reduce_partials_at's
-// order (each lane's two halves, threads h * 64 + l taking half h of lane
-// 64 w + l, then the wavefront butterfly) and writes it to W[i * kWaves + w].
-// sum_wave_sums adds W[i * kWaves + 0 .. kWaves - 1] in order, which is
-// block_sum's last step: the totals have reduce_partials_at's bits.  The
-// wavefronts of the second halves load nothing when G fits in the first.
-constexpr int kWaveBlock = 128;
+// order (thread c * 64 + l takes chunk c of lane 64 w + l; the chunk sums
+// are added in order, then the wavefront butterfly) and writes it to
+// W[i * kWaves + w].  sum_wave_sums adds W[i * kWaves + 0 .. kWaves - 1] in
+// order, which is block_sum's last step: the totals have
+// reduce_partials_at's bits.  The wavefronts of chunks without a partial
+// below G load nothing.
+constexpr int kWaveBlock = 64 * kChunks;
 
 template <int NV, int N1>
 __device__ __forceinline__ void wave_partial_sums(const double* __restrict__ P1, const double* __restrict__ P2, int G,
                                                   int Gs, double* __restrict__ W)
 {
-    __shared__ double hi[NV][64];
+    __shared__ double cs[kChunks][NV][64];
     const double* P[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) P[i] = i < N1 ? P1 + (int64_t)i * Gs : P2 + (int64_t)(i - N1) * Gs;
+    partial_rows<NV, N1>(P1, P2, Gs, P);
     const int l = threadIdx.x & 63;
-    const int half = threadIdx.x >> 6;  // uniform per wavefront
+    const int c = threadIdx.x >> 6;  // chunk, uniform per wavefront
     const int lane = 64 * blockIdx.x + l;
-    double acc[NV];
+    double sum[NV];
+    chunk_sum<NV>(P, lane, c, G, sum);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    if (half == 0 || 2 * kBlock * kLanePairs < G) {
-        double2 buf[NV][kLanePairs];
-#pragma unroll
-        for (int j = 0; j < kLanePairs; ++j) {
-            const int k = lane + kBlock * (half * kLanePairs + j);
-#pragma unroll
-            for (int i = 0; i < NV; ++i) buf[i][j] = load_pair(P[i], k, G);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-#pragma unroll
-            for (int j = 0; j < kLanePairs; ++j) {
-                const int k = lane + kBlock * (half * kLanePairs + j);
-                acc[i] += 2 * k < G ? buf[i][j].x : 0.0;
-                acc[i] += 2 * k + 1 < G ? buf[i][j].y : 0.0;
-            }
-        }
-    }
-    if (half == 1) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) hi[i][l] = acc[i];
-    }
+    for (int i = 0; i < NV; ++i) cs[c][i][l] = sum[i];
     __syncthreads();
-    if (half == 0) {
+    if (c == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const double v = wave_sum(acc[i] + hi[i][l]);
+            double a = cs[0][i][l];
+#pragma unroll
+            for (int q = 1; q < kChunks; ++q) a = a + cs[q][i][l];
+            const double v = wave_sum(a);
             if (l == 0) W[i * kWaves + blockIdx.x] = v;
         }
     }
