@@ -234,22 +234,30 @@ def test_varcoef27_parity(prcg, torch_cuda, variant):
     ways after a dozen iterations while both converge, and in the oracle
     alone moving every entry of b by one ulp moves x_12 by up to 5e-11
     relative, x_30 by up to 9e-9 and x_139 (the solution) by up to 4e-11.  So
-    x_12 and the first 12 residual norms are compared with the oracle element
-    by element at the history bar (1e-8 relative); the solve to 1e-10 by
-    status, iteration count (within one) and the true residual of the
-    returned x, computed on the host; and the attainable accuracy by the
-    paper's 10%-on-a-log-scale criterion."""
+    the first 12 residual norms are compared with the oracle element by
+    element at the history bar (1e-8 relative) and x_12 at 1e-9 (a
+    different summation order moved it by 1.4e-10, three ulp-of-b
+    sensitivities); the solve to 1e-10 by status, iteration count (within
+    one), the solution at the GPU's stopping iteration against the oracle's
+    at that iteration, and the true residual of the returned x, computed on
+    the host; and the attainable accuracy by the paper's
+    10%-on-a-log-scale criterion.  The solution bar here is 1e-9, not the
+    1e-10 of the well-conditioned problems: one-ulp changes of every entry
+    of b move the oracle's own x_139 by 3e-11 (HS-CG) and 1e-11 (PR-CG,
+    pipe-PR-CG), and the GPU's summation order moves HS-CG's by 1.7e-10."""
     A = P.varcoef27(20, 3)
     xs = P.uniform_vector(A.n, 3)
     b = P.rhs_from_solution(A, xs)
     M = gpu_matrix(prcg, A)
     x12, i12 = M.solve(b, variant, 0.0, 12, history=True)
     ref = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, "none", 0.0, 12)
-    assert np.linalg.norm(x12.cpu().numpy() - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+    assert np.linalg.norm(x12.cpu().numpy() - ref["x"]) <= 1e-9 * np.linalg.norm(ref["x"])
     assert hist_close(i12.history, ref["history"])
     x, info = M.solve(b, variant, 1e-10, 3000)
     stop = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, "none", 1e-10, 3000)
     assert info.status == stop["status"] == "ok" and abs(info.iters - stop["iters"]) <= 1
+    at = oracle.solve(A.row_ptr, A.col_idx, A.values, b, variant, "none", 0.0, info.iters)
+    assert np.linalg.norm(x.cpu().numpy() - at["x"]) <= 1e-9 * np.linalg.norm(at["x"])
     true = np.linalg.norm(b - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(b)
     assert true <= 2e-10 and abs(info.relres_true - true) <= 1e-6 * true
     _, deep = M.solve(b, variant, 1e-16, 1500)
@@ -421,22 +429,26 @@ def test_reduction_placements_agree_bitwise(prcg, torch_cuda):
                 assert np.array_equal(x, out[0][0]) and np.array_equal(h, out[0][2]), (v, pre)
 
 
-@pytest.mark.parametrize("grid", [1456, 8192])
+@pytest.mark.parametrize("grid", [1456, 8192, 16000])
 def test_reduction_order_is_independent_of_load_batching(prcg, torch_cuda, grid):
-    """With more partials than a lane's first half holds (8192: both halves
-    of every lane), the in-kernel reductions (redundant, last-workgroup),
-    which load two pairs of partials per thread and value at a time, and the
-    stage-2 kernels, which split each lane over two threads that load all of
-    theirs at once, add in one order: identical bits."""
+    """With partials in one, two (8192) or all four (16000) chunks of every
+    lane, the in-kernel reductions (redundant, last-workgroup), which walk a
+    lane's chunks loading two pairs of partials per thread and value at a
+    time, and the stage-2 kernels, which split each lane's chunks over two
+    threads (over four in the split stage 2 of PR-CG) that load a chunk at
+    once, add in one order: identical bits."""
     if grid == 1456:
         A = P.poisson3d(72)  # 1458 row groups
         b = P.uniform_vector(A.n, 8)
-    else:
+    elif grid == 8192:
         pr = P.config2()  # 8192 row groups
         A, b = pr.A, pr.b
+    else:
+        A = P.poisson3d(160)  # 16000 row groups
+        b = P.uniform_vector(A.n, 9)
     for v in ("hs", "pr", "pipe_pr", "cg"):
         out = []
-        for kernels in ("two_pass_redundant", "two_pass_stage2", "two_pass_last"):
+        for kernels in ("two_pass_redundant", "two_pass_stage2", "two_pass_last", "two_pass"):
             M = gpu_matrix(prcg, A, "jacobi", kernels)
             M.set_grid(grid)
             assert M.props.grid == grid
@@ -493,12 +505,14 @@ def test_poisson3d_128_jacobi_history_first_200(prcg, torch_cuda, kernels):
 @pytest.mark.parametrize("variant", ["hs", "pr", "pipe_pr", "cg"])
 def test_ragged_full_scale_jacobi(prcg, torch_cuda, variant):
     """A 131x127x129 grid (n = 2,146,173: a partial last slice, 8384 row
-    groups over the default 8192 workgroups, so some workgroups take two
-    groups, and partials in both halves of every lane of the reduction):
-    x_60 and the first 60 residual norms against the oracle."""
+    groups over 8192 workgroups, so some workgroups take two groups, and
+    partials in two chunks of every lane of the reduction): x_60 and the
+    first 60 residual norms against the oracle."""
     A = P.poisson3d(131, 127, 129)
     b = P.uniform_vector(A.n, 12)
     M = gpu_matrix(prcg, A, "jacobi", "auto")
+    assert M.props.grid == 8384  # the default: one row group per workgroup
+    M.set_grid(8192)
     assert M.props.grid == 8192
     x, info = M.solve(b, variant, 0.0, 60, history=True)
     ref = oracle_solve(A, b, variant, "jacobi", 0.0, 60)
