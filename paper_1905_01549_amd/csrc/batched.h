@@ -22,11 +22,12 @@ struct BatchView {
 // slices (rows row0 .. row0 + nrows - 1) of one system, whose rows are
 // lo .. hi; system s owns groups [sys_grp0[s], sys_grp0[s+1]).  A uniform
 // group (off >= 0) holds offset-aligned slices of one width (1 ..
-// kUniformMaxWidth) and one list of column offsets, soff[off .. off +
-// width - 1], stored one after another from value slot 64 vrow: the
-// product reads everything about it from this record.  Other groups
-// (off < 0) hold any slices and take the general slice-by-slice product.
-// (Rows, slices and value slots / 64 fit int32: column indices are int32.)
+// kUniformMaxWidth) and one list of column offsets, o[0 .. width - 1] (also
+// at soff[off ..]), stored one after another from value slot 64 vrow: the
+// product reads everything about it from this record, so its gathers need
+// no other load first.  Other groups (off < 0) hold any slices and take the
+// general slice-by-slice product.  (Rows, slices and value slots / 64 fit
+// int32: column indices are int32.)
 constexpr int kLockstepSlices = 16;
 constexpr int kUniformMaxWidth = 8;
 struct Group {
@@ -40,13 +41,17 @@ struct Group {
     int32_t off;    // uniform groups: first of the slices' common offsets in soff; -1 otherwise
     int32_t width;  // uniform groups: slots per row
     int32_t vrow;   // uniform groups: the first slice's values start at slot 64 vrow
-    int32_t spare0, spare1;
+    int32_t diag;   // uniform groups: the slot whose offset is 0, or -1
+    int32_t flags;  // uniform groups: kGroupShift when slots diag - 1 and diag + 1 hold offsets -1 and +1
+    int32_t o[kUniformMaxWidth];  // uniform groups: the column offsets
 };
-static_assert(sizeof(Group) == 48, "three 16-byte loads per group");
+constexpr int32_t kGroupShift = 1;
+static_assert(sizeof(Group) == 80, "five 16-byte loads per group");
 struct GroupView {
     const Group* grp;          // [ngroups]
     const int64_t* sys_grp0;   // [nsys + 1]
     int64_t ngroups;
+    int32_t* gdone;            // [ngroups]: 1 once the group's system has finished
 };
 
 // Lockstep PR-CG / M-CG (variant kPR or kM): the initialisation (three

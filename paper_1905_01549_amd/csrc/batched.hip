@@ -363,29 +363,40 @@ __global__ void k_batch_reset(int32_t* queue) { *queue = 0; }
 // with one list of column offsets, stored one after another): wave w takes
 // slices w, w + kWaves, ... of the group, R = kLockstepSlices / kWaves of
 // them, in rounds of RR slices (RR W <= 20 value loads, to bound the
-// registers): a round issues the loads of its values, of the W offsets and
-// of each row's own entries (pre(i, row)) together, before any gather, so a
-// round costs two memory round trips.  Slices past the group's end are
+// registers): a round issues the loads of its values, of the W offsets, of
+// each row's own entry x[row] and of each row's other entries (pre(i, row))
+// together, before any gather, so a round costs two memory round trips.
+// D0 >= 0: slot D0 holds offset 0 and slots D0 - 1 and D0 + 1 offsets -1 and
+// +1; slot D0 then takes x[row] and its two neighbours x[row -+ 1] from the
+// neighbouring lanes (cross-lane moves, no memory request) and the slice's
+// two boundary entries, so a 5-point row gathers two entries instead of
+// five.  D0 < 0: every slot is gathered.  Slices past the group's end are
 // clamped to its last slice (their loads stay inside the group; their rows
-// are skipped).  Calls f(i, row, y) for the valid rows in slice order, y
-// summed over the slots in stored order from 0.0 as in sell_row.
-template <int W, class Pre, class F>
+// are skipped).  Columns are clamped into the system's rows [lo, hi] as in
+// sell_row, and each row's slots are summed in stored order from 0.0: the
+// same operands in the same order.  Calls f(i, row, y, x[row]) for the valid
+// rows in slice order.
+constexpr int kLsRoundLoads = 20;  // value loads per round of uniform_group
+template <int W, int D0, class Pre, class F>
 __device__ __forceinline__ void uniform_group(const SellView& A, const Group& G, const double* __restrict__ x,
                                               Pre&& pre, F&& f)
 {
     constexpr int R = kLockstepSlices / kWaves;
-    constexpr int RR = W * R <= 20 ? R : (W * R / 2 <= 20 ? R / 2 : 1);
+    constexpr int RR = W * R <= kLsRoundLoads ? R : (W * R / 2 <= kLsRoundLoads ? R / 2 : 1);
+    constexpr bool SHIFT = D0 >= 1 && D0 + 1 < W;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     int o[W];
 #pragma unroll
-    for (int u = 0; u < W; ++u) o[u] = A.soff[G.off + u];
+    for (int u = 0; u < W; ++u) o[u] = G.o[u];
+    // slot u reads the row's own entry or a lane neighbour's instead of memory
+    constexpr auto local_slot = [](int u) { return SHIFT && (u == D0 - 1 || u == D0 || u == D0 + 1); };
     const double* __restrict__ vb = A.val + (int64_t)G.vrow * kSlice + lane;
 #pragma unroll
     for (int i0 = 0; i0 < R; i0 += RR) {
         int row[RR];
         bool valid[RR];
-        double a[RR][W];
+        double a[RR][W], xs[RR], below[RR], above[RR];
 #pragma unroll
         for (int j = 0; j < RR; ++j) {
             const int sl = w + kWaves * (i0 + j);
@@ -395,26 +406,45 @@ __device__ __forceinline__ void uniform_group(const SellView& A, const Group& G,
             row[j] = G.row0 + min(local, G.nrows - 1);
 #pragma unroll
             for (int u = 0; u < W; ++u) a[j][u] = vb[(int64_t)(slc * W + u) * kSlice];
+            xs[j] = x[row[j]];
+            if constexpr (SHIFT) {
+                // the entries next to the slice, clamped into the system
+                const int first = G.row0 + slc * kSlice;
+                below[j] = x[max(first - 1, G.lo)];
+                above[j] = x[min(first + kSlice, G.hi)];
+            }
             pre(i0 + j, row[j]);
         }
         double g[RR][W];
 #pragma unroll
         for (int j = 0; j < RR; ++j) {
 #pragma unroll
-            for (int u = 0; u < W; ++u) g[j][u] = x[min(max(row[j] + o[u], G.lo), G.hi)];
+            for (int u = 0; u < W; ++u) {
+                if (!local_slot(u)) g[j][u] = x[min(max(row[j] + o[u], G.lo), G.hi)];
+            }
         }
 #pragma unroll
         for (int j = 0; j < RR; ++j) {
+            if constexpr (SHIFT) {
+                double xm = __shfl_up(xs[j], 1, 64);
+                double xp = __shfl_down(xs[j], 1, 64);
+                if (lane == 0) xm = below[j];
+                if (lane == kSlice - 1) xp = above[j];
+                g[j][D0 - 1] = xm;
+                g[j][D0] = xs[j];
+                g[j][D0 + 1] = xp;
+            }
             double y = 0.0;
 #pragma unroll
             for (int u = 0; u < W; ++u) y = fma(a[j][u], g[j][u], y);
-            if (valid[j]) f(i0 + j, row[j], y);
+            if (valid[j]) f(i0 + j, row[j], y, xs[j]);
         }
     }
 }
 
 // Occupancy floor of the lockstep product (wavefronts per SIMD: at most
-// 128 registers per thread).
+// 128 registers per thread; with a preconditioner, whose rows carry two more
+// entries, one wavefront less).
 constexpr int kLockstepSpmvWaves = 4;
 
 // PHASE 1: r0 = b - A x0, r~0 = M^{-1} r0, p0 = r~0 and the <b, b> partial.
@@ -423,13 +453,13 @@ constexpr int kLockstepSpmvWaves = 4;
 // The group's slices go through sys_spmv (two slices per wavefront with
 // their loads in flight together).
 template <bool PRE, int PHASE>
-__global__ __launch_bounds__(kBlock, kLockstepSpmvWaves) void k_ls_spmv(BatchView B, GroupView gv, const State* __restrict__ S, Vecs v,
+__global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpmvWaves) void k_ls_spmv(BatchView B, GroupView gv, const State* __restrict__ S, Vecs v,
                                                     const double* __restrict__ b, double* __restrict__ P)
 {
     __shared__ double lds[kWaves * 5];
     const int64_t g = blockIdx.x;
+    if (PHASE == 0 && gv.gdone[g]) return;  // the whole workgroup
     const Group G = gv.grp[g];
-    if (PHASE == 0 && S[G.sys].done) return;  // the whole workgroup
     double* __restrict__ r = v.r;
     double* __restrict__ rt = v.rt;
     double* __restrict__ p = v.p;
@@ -472,22 +502,33 @@ __global__ __launch_bounds__(kBlock, kLockstepSpmvWaves) void k_ls_spmv(BatchVie
                 e1[i] = e2[i] = 0.0;
                 e3[i] = PRE ? d[row] : 1.0;
             } else {
-                e0[i] = p[row];
                 e1[i] = r[row];
                 e2[i] = PRE ? rt[row] : 0.0;
                 e3[i] = PRE ? d[row] : 1.0;
             }
         };
-        auto f = [&](int i, int row, double y) { row_done(row, y, e0[i], e1[i], e2[i], e3[i]); };
+        // PHASE 0 and 2 multiply p, so p[row] is the row's own entry
+        auto f = [&](int i, int row, double y, double xrow) {
+            row_done(row, y, PHASE == 1 ? e0[i] : xrow, e1[i], e2[i], e3[i]);
+        };
+        // stencils whose sorted offsets put 0 in the middle slot, flanked by
+        // -1 and +1, take the neighbours from the lanes
+        auto go = [&](auto Wc) {
+            constexpr int W = decltype(Wc)::value;
+            if (W >= 3 && (G.flags & kGroupShift) && G.diag == W / 2)
+                uniform_group<W, W / 2>(B.A, G, xin, pre, f);
+            else
+                uniform_group<W, -1>(B.A, G, xin, pre, f);
+        };
         switch (G.width) {
-        case 1: uniform_group<1>(B.A, G, xin, pre, f); break;
-        case 2: uniform_group<2>(B.A, G, xin, pre, f); break;
-        case 3: uniform_group<3>(B.A, G, xin, pre, f); break;
-        case 4: uniform_group<4>(B.A, G, xin, pre, f); break;
-        case 5: uniform_group<5>(B.A, G, xin, pre, f); break;
-        case 6: uniform_group<6>(B.A, G, xin, pre, f); break;
-        case 7: uniform_group<7>(B.A, G, xin, pre, f); break;
-        default: uniform_group<kUniformMaxWidth>(B.A, G, xin, pre, f); break;
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        case 5: go(std::integral_constant<int, 5>{}); break;
+        case 6: go(std::integral_constant<int, 6>{}); break;
+        case 7: go(std::integral_constant<int, 7>{}); break;
+        default: go(std::integral_constant<int, kUniformMaxWidth>{}); break;
         }
     } else {
         sys_spmv<kBlock, 1>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, xin, nullptr,
@@ -515,8 +556,10 @@ __global__ __launch_bounds__(kBlock, kLockstepSpmvWaves) void k_ls_spmv(BatchVie
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_ls_update(GroupView gv, const State* __restrict__ S, Vecs v)
 {
+    // the flag and the record load together; the state's scalars load
+    // with the rows (they are needed only for the arithmetic)
+    if (gv.gdone[blockIdx.x]) return;
     const Group G = gv.grp[blockIdx.x];
-    if (S[G.sys].done) return;
     const double alpha = S[G.sys].alpha, beta = S[G.sys].beta;
     double* __restrict__ x = v.x;
     double* __restrict__ r = v.r;
@@ -588,6 +631,11 @@ __global__ __launch_bounds__(kBlock) void k_ls_finish(BatchView B, GroupView gv,
         store_state(S + sys, st);
         iters[sys] = st.k < 0 ? 0 : st.k;
         status[sys] = st.status;
+    }
+    // the groups' copies of the flag (the next kernels read them instead of
+    // the state, with no load before)
+    if (INIT || st.done) {
+        for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) gv.gdone[g] = st.done;
     }
 }
 

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -79,6 +80,21 @@ Bufs bufs_at(double* partials, State* S, double* hist, int* ticket)
     B.PW = partials + (size_t)(2 * kMaxDots + 6) * kMaxGrid;
     B.ticket = ticket;
     return B;
+}
+
+// Offset-aligned slices whose column-offset lists are equal are pointed at
+// one copy of the list (meta[q] rewritten; the other copies stay unused), so
+// that the products' scalar loads of the offsets hit the scalar cache
+// instead of missing once per slice.
+void share_offsets(const std::vector<int32_t>& soff, const std::vector<int32_t>& width, std::vector<int32_t>& meta)
+{
+    std::map<std::vector<int32_t>, int32_t> first;
+    for (size_t q = 0; q < meta.size(); ++q) {
+        if (meta[q] < 0) continue;
+        std::vector<int32_t> key(soff.begin() + meta[q], soff.begin() + meta[q] + width[q]);
+        auto it = first.emplace(std::move(key), meta[q]).first;
+        meta[q] = it->second;
+    }
 }
 
 }  // namespace
@@ -207,6 +223,7 @@ struct prcg_batch_s {
     int64_t uniform_groups = 0;
     Group* grp = nullptr;
     int64_t* sys_grp0 = nullptr;
+    int32_t* gdone = nullptr;
     State* lstate = nullptr;
     double* lpart = nullptr;   // 6 * ngroups
     int32_t* lactive = nullptr;
@@ -216,7 +233,7 @@ struct prcg_batch_s {
     int32_t mode_req = PRCG_BATCH_AUTO;
     int32_t mode[3] = {0, 0, 0};  // per kind: 0 undecided, else PRCG_BATCH_PERSISTENT / _LOCKSTEP
 
-    GroupView groups() const { return GroupView{grp, sys_grp0, ngroups}; }
+    GroupView groups() const { return GroupView{grp, sys_grp0, ngroups, gdone}; }
 
     Vecs vecs_view() const
     {
@@ -267,7 +284,7 @@ void free_batch(prcg_batch B)
     if (B->hactive) (void)hipHostFree(B->hactive);
     void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
                    B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
-                   B->grp, B->sys_grp0, B->lstate, B->lpart, B->lactive};
+                   B->grp, B->sys_grp0, B->gdone, B->lstate, B->lpart, B->lactive};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     delete B;
@@ -711,6 +728,12 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         HTRY(launch_fill_sell(n, A->nslices, A->row_ptr, A->col, A->val, nullptr, nullptr, A->slice_ptr,
                               A->slice_meta, A->slice_shape, A->soff, A->scol, A->sval, 1, A->stream));
         HTRY(hipStreamSynchronize(A->stream));  // host vectors above must outlive the copies
+        if (A->noffsets > 0) {
+            std::vector<int32_t> hso((size_t)A->noffsets);
+            HTRY(hipMemcpy(hso.data(), A->soff, sizeof(int32_t) * A->noffsets, hipMemcpyDeviceToHost));
+            share_offsets(hso, width, hmeta);
+            HTRY(hipMemcpy(A->slice_meta, hmeta.data(), sizeof(int32_t) * A->nslices, hipMemcpyHostToDevice));
+        }
     }
     A->kernels_mode = PRCG_KERNELS_AUTO;
     A->grid_opt = 0;
@@ -1088,6 +1111,8 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     if (noff > 0) {
         BTRY(hipMemcpyAsync(hsoff.data(), B->soff, sizeof(int32_t) * noff, hipMemcpyDeviceToHost, st));
         BTRY(hipStreamSynchronize(st));
+        share_offsets(hsoff, width, hmeta);
+        BTRY(hipMemcpy(B->slice_meta, hmeta.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice));
     }
     auto uniform_slice = [&](int64_t q) {
         return aligned[q] && width[q] >= 1 && width[q] <= kUniformMaxWidth && hptr[q] / kSlice < INT32_MAX;
@@ -1119,6 +1144,17 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
             G.off = uniform_slice(s0) ? hmeta[s0] : -1;
             G.width = width[s0];
             G.vrow = (int32_t)(hptr[s0] / kSlice);
+            G.diag = -1;
+            G.flags = 0;
+            if (G.off >= 0) {
+                const int32_t* o = hsoff.data() + G.off;
+                for (int32_t u = 0; u < G.width; ++u) {
+                    G.o[u] = o[u];
+                    if (o[u] == 0) G.diag = u;
+                }
+                if (G.diag >= 1 && G.diag + 1 < G.width && o[G.diag - 1] == -1 && o[G.diag + 1] == 1)
+                    G.flags |= kGroupShift;
+            }
             grp.push_back(G);
             s0 += len;
         }
@@ -1129,6 +1165,7 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     for (const Group& G : grp) B->uniform_groups += G.off >= 0;
     BTRY(hipMalloc(&B->grp, sizeof(Group) * B->ngroups));
     BTRY(hipMalloc(&B->sys_grp0, sizeof(int64_t) * (nsys + 1)));
+    BTRY(hipMalloc(&B->gdone, sizeof(int32_t) * B->ngroups));
     BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
     BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * B->ngroups));
     BTRY(hipMalloc(&B->lactive, sizeof(int32_t) * 4));

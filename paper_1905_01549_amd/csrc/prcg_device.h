@@ -370,22 +370,32 @@ __device__ __forceinline__ void slot_piece(const double* __restrict__ v, const S
     for (int u = 0; u < K; ++u) acc(a[u], g[u]);
 }
 
+// The last piece of a row, 1 .. N slots (one uniform branch per size).
+template <int N, bool ALIGNED, class T, bool NT, class Gather, class Acc>
+__device__ __forceinline__ void slot_rest(int rem, const double* __restrict__ v, const SlotCols& cols, int j0,
+                                          Gather&& gather, Acc&& acc)
+{
+    if constexpr (N >= 1) {
+        if (rem == N)
+            slot_piece<N, ALIGNED, T, NT>(v, cols, j0, gather, acc);
+        else
+            slot_rest<N - 1, ALIGNED, T, NT>(rem, v, cols, j0, gather, acc);
+    }
+}
+
+// Slots of offset-aligned slices per piece (their offsets are scalar loads).
+// Measured on MI355X: pieces of 9 take the 27-point product (27 = 3 x 9) from
+// 184.4 to 181.2 us against pieces of 8; 14 and 27 were slower (189, 200).
+constexpr int kAlignedChunk = 9;
+
 template <bool ALIGNED, class T, bool NT, class Gather, class Acc>
 __device__ __forceinline__ void slot_loop_of(const double* __restrict__ v, const SlotCols& cols, int width,
                                              Gather&& gather, Acc&& acc)
 {
+    constexpr int K = ALIGNED ? kAlignedChunk : kChunk;
     int j0 = 0;
-    for (; j0 + kChunk <= width; j0 += kChunk) slot_piece<kChunk, ALIGNED, T, NT>(v, cols, j0, gather, acc);
-    switch (width - j0) {
-    case 1: slot_piece<1, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    case 2: slot_piece<2, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    case 3: slot_piece<3, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    case 4: slot_piece<4, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    case 5: slot_piece<5, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    case 6: slot_piece<6, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    case 7: slot_piece<7, ALIGNED, T, NT>(v, cols, j0, gather, acc); break;
-    default: break;
-    }
+    for (; j0 + K <= width; j0 += K) slot_piece<K, ALIGNED, T, NT>(v, cols, j0, gather, acc);
+    slot_rest<K - 1, ALIGNED, T, NT>(width - j0, v, cols, j0, gather, acc);
 }
 
 // stream: load the values nontemporally (offset-aligned slices only; a
