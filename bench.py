@@ -164,6 +164,7 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True):
     t_batch = (time.perf_counter() - t) / reps
     nt, grid = B.config("pr")
     mode = B.mode("pr")
+    props = B.props("pr")  # the configuration the autotuner chose
     per_mode = {}
     for m in ("persistent", "lockstep"):
         B.set_mode(m)
@@ -177,8 +178,10 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True):
         per_mode[m] = {"solves_per_s": (len(offs) - 1) / ((time.perf_counter() - t) / reps),
                        "iterations_total": int(it_m.sum())}
     sizes = np.diff(offs)
-    # algorithmic bytes: per system-iteration 10 vectors (PR two-pass, no preconditioner) + its matrix
-    per_row_matrix = 8.0 * 5  # offset-aligned slices: 8 bytes per stored entry, 5 entries per row
+    # algorithmic bytes: per system-iteration 10 vectors (PR-CG: the update reads
+    # x, r, p, s and writes x, r, p; the product reads p, r and writes s) and
+    # the system's share of the batch's SELL-64 bytes (taken per row)
+    per_row_matrix = props["matrix_bytes"] / float(A.n)
     moved = float(np.sum(iters * sizes * (80.0 + per_row_matrix)))
     # sequential: one handle and one solve per system (handles created before timing)
     t_seq, seq_iters = float("nan"), 0
@@ -202,8 +205,9 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True):
             "sequential_solves_per_s": len(sizes) / t_seq if sequential else None,
             "sequential_ms": t_seq * 1e3 if sequential else None,
             "speedup": t_seq / t_batch if sequential else None, "iterations_total": int(iters.sum()), "sequential_iterations": seq_iters,
-            "algorithmic_GBps": moved / t_batch / 1e9, "mode": mode, "modes": per_mode,
-            "threads_per_workgroup": nt, "workgroups": grid}
+            "algorithmic_GBps": moved / t_batch / 1e9, "hbm_frac": moved / t_batch / 1e9 / HBM_PEAK_GBS,
+            "bytes_moved": moved, "mode": mode, "modes": per_mode, "threads_per_workgroup": nt, "workgroups": grid,
+            "tuned": props}
 
 
 def roofline_of(kernel_us, fmt_bytes, csr_bytes):

@@ -214,7 +214,12 @@ prcg_status prcg_set_stream(prcg_matrix A, void* hip_stream);
 
 /* y = A x (device float64[n] each; x and y must not overlap).  The product
  * of Section 3 eq. Ax: each row summed in stored order with fused
- * multiply-adds. */
+ * multiply-adds.  Non-finite entries of x: the SELL-64 layout pads rows to
+ * their slice's width with zero slots, which multiply 0 by an entry of x in
+ * the row's own system (offset-aligned slices: the column row + offset,
+ * clamped into range; packed slices: the row itself), so a non-finite x at
+ * such a column makes y_i NaN where a product over the stored entries alone
+ * would stay finite.  Finite x gives the same result either way. */
 prcg_status prcg_spmv(prcg_matrix A, const double* x, double* y);
 
 /*
@@ -285,9 +290,11 @@ prcg_status prcg_get_props(prcg_matrix A, prcg_matrix_props* props);
 /*
  * Batched solve of nsys independent systems stored as one block-diagonal
  * matrix (not in the paper; the block-diagonal structure is the only
- * assumption).  One persistent kernel advances every system: each
- * workgroup takes the next-largest unsolved system from a queue and runs
- * the whole solve with workgroup-local reductions.
+ * assumption).  Two modes (prcg_batch_set_mode): a persistent kernel in
+ * which each workgroup takes the next-largest unsolved system from a queue
+ * and runs its whole solve with workgroup-local reductions, and (PR-CG,
+ * M-CG) a lockstep mode in which every iteration is three launches over the
+ * row groups of all systems still running.
  *   blockdiag       a handle created by prcg_create_csr (no column index
  *                   may leave its block; checked here).
  *   sys_row_offset  host int64[nsys+1]: system s owns rows
@@ -301,14 +308,23 @@ prcg_status prcg_create_batch(prcg_matrix blockdiag, int32_t nsys, const int64_t
  * as prcg_solve (the matrix handle's preconditioner applies).  b, x: device
  * float64[n]; x holds x_0 on entry.  iters, status: host int32[nsys],
  * nullable.  Returns the largest per-system status (OK < NOT_CONVERGED <
- * BREAKDOWN).  The first call with a variant runs the autotuner: a few
- * iterations of every system under each candidate launch shape (threads per
- * workgroup x workgroups per compute unit), timed with HIP events; the
- * fastest is kept for the batch.  The persistent launch is captured in a
- * HIP graph.  For PR-CG and M-CG the first call also times one whole solve
- * in the persistent mode and one in the lockstep mode (see
- * prcg_batch_set_mode) and keeps the faster, unless a mode was set.
- * Reductions are deterministic for a fixed configuration and mode. */
+ * BREAKDOWN).  The first call with a variant runs the autotuner, each
+ * candidate timed with HIP events on this batch:
+ *   persistent launch: threads per workgroup (256, 512, 1024) x workgroups
+ *     per compute unit (1, 2, 4, 8; at most 2048 threads per compute unit)
+ *     x slices multiplied together per wavefront in the product (1 or 2),
+ *     a few iterations of every system each;
+ *   lockstep row groups (PR-CG, M-CG): 8, 16 or 32 slices of 64 rows per
+ *     group (2, 4 or 8 slices per wavefront), the initialisation and 32
+ *     iterations each;
+ *   mode (PR-CG, M-CG, unless set): one whole solve in each, the faster kept.
+ * prcg_batch_set_config fixes any of these instead.  The persistent launch
+ * and chunks of lockstep iterations are captured in HIP graphs.
+ * Reductions are deterministic for a fixed configuration (threads per
+ * workgroup and group size set the order of a system's sums; the number of
+ * slices in flight does not): a configuration the autotuner picks can differ
+ * between processes, so fix it for results that must agree bit for bit
+ * across processes. */
 prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, double* x, double tol,
                                int32_t maxit, int32_t* iters, int32_t* status);
 
@@ -319,11 +335,41 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
  * 256/512/1024, 1 <= per_cu <= 8) fixes it instead. */
 prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, int32_t* grid);
 
+/* Fix parts of the batched configuration for later solves (0 leaves a part
+ * to the autotuner); forgets earlier choices.
+ *   threads           0, 256, 512 or 1024 threads per persistent workgroup
+ *   per_cu            0..8 persistent workgroups per compute unit
+ *                     (threads x per_cu <= 2048)
+ *   slices_in_flight  0, 1 or 2 slices multiplied together per wavefront
+ *   group_slices      0, 8, 16 or 32 slices per lockstep row group
+ * PRCG_EINVAL for other values. */
+prcg_status prcg_batch_set_config(prcg_batch B, int32_t threads, int32_t per_cu, int32_t slices_in_flight,
+                                  int32_t group_slices);
+
+/* The batch's storage and the configuration in use for variant v (zeros
+ * for parts not chosen yet). */
+typedef struct {
+    int64_t n;                /* rows of all systems                                  */
+    int64_t stored_entries;   /* value slots of the batch's SELL-64 slices            */
+    int64_t matrix_bytes;     /* bytes of those slices read by one product of all
+                                 systems (values, packed columns, offsets, metadata) */
+    int64_t groups;           /* lockstep row groups of the size in use               */
+    int64_t uniform_groups;   /* of which uniform (one width and offset list)         */
+    int32_t nsys;
+    int32_t mode;             /* PRCG_BATCH_PERSISTENT / _LOCKSTEP, 0 if undecided    */
+    int32_t threads;          /* persistent: threads per workgroup                    */
+    int32_t grid;             /* persistent: workgroups                               */
+    int32_t slices_in_flight; /* persistent: slices multiplied together per wavefront */
+    int32_t group_slices;     /* lockstep: slices per row group (PR-CG, M-CG)         */
+} prcg_batch_props;
+prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props* props);
+
 /* How the batched solver runs PR-CG and M-CG (HS-CG and the pipelined
  * variants always run persistent):
  *   PRCG_BATCH_PERSISTENT  one persistent kernel, a workgroup per system;
  *   PRCG_BATCH_LOCKSTEP    three launches per iteration over the row groups
- *     (up to 256 rows of one system) of every system still running: the
+ *     (8, 16 or 32 slices of 64 rows of one system) of every system still
+ *     running: the
  *     vector update, the product with one partial per group of each inner
  *     product, then one workgroup per system that sums its partials in a
  *     fixed order and takes the scalar step (Alg. 2); the host checks every

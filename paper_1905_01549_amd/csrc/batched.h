@@ -18,7 +18,7 @@ struct BatchView {
     int32_t nsys;
 };
 
-// Row groups of the lockstep solver: up to kLockstepSlices consecutive
+// Row groups of the lockstep solver: up to kWaves spw consecutive
 // slices (rows row0 .. row0 + nrows - 1) of one system, whose rows are
 // lo .. hi; system s owns groups [sys_grp0[s], sys_grp0[s+1]).  A uniform
 // group (off >= 0) holds offset-aligned slices of one width (1 ..
@@ -28,7 +28,7 @@ struct BatchView {
 // no other load first.  Other groups (off < 0) hold any slices and take the
 // general slice-by-slice product.  (Rows, slices and value slots / 64 fit
 // int32: column indices are int32.)
-constexpr int kLockstepSlices = 16;
+constexpr int kLockstepSlices = 16;  // the default group: 4 slices per wavefront
 constexpr int kUniformMaxWidth = 8;
 struct Group {
     int32_t slice0;
@@ -52,6 +52,7 @@ struct GroupView {
     const int64_t* sys_grp0;   // [nsys + 1]
     int64_t ngroups;
     int32_t* gdone;            // [ngroups]: 1 once the group's system has finished
+    int32_t spw;               // slices per wavefront (2, 4 or 8): groups hold kWaves spw slices
 };
 
 // Lockstep PR-CG / M-CG (variant kPR or kM): the initialisation (three
@@ -66,9 +67,11 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
                                       int32_t* active, hipStream_t st);
 
 // Reset the queue and launch the persistent kernel (nt threads per
-// workgroup: 256, 512 or 1024; grid workgroups).  Both launches go on `st`
-// and may be captured in a graph.
+// workgroup: 256, 512 or 1024; grid workgroups; q = 1 or 2 slices
+// multiplied together per wavefront).  Both launches go on `st` and may be
+// captured in a graph.
 hipError_t launch_batch(const BatchView& B, const Vecs& v, const double* b, double tol, int maxit, int variant,
-                        int pre, int nt, int grid, int32_t* queue, int32_t* iters, int32_t* status, hipStream_t st);
+                        int pre, int nt, int grid, int q, int32_t* queue, int32_t* iters, int32_t* status,
+                        hipStream_t st);
 
 }  // namespace prcg

@@ -58,19 +58,19 @@ __device__ __forceinline__ void aligned_group(const SellView& A, const int64_t (
 
 // Calls f(row, y0, y1) for every row of the system's slices [sl0, sl1)
 // (the system's rows are [lo, hi]; zero slots never read past them):
-// wavefront w takes slices sl0 + w, sl0 + w + NW, ... in that order, Q = 2
-// at a time; Q offset-aligned slices of equal width (every slice of a
-// stencil matrix) are multiplied with all their loads in flight together,
-// so a workgroup that runs a system on its own waits about one memory round
-// trip per Q slices instead of three per slice.  (Measured on the batched
-// workload: pairs 21% faster than single slices; Q = 4 no faster than
-// pairs, with more registers.)
-template <int NT, int NX, class F>
+// wavefront w takes slices sl0 + w, sl0 + w + NW, ... in that order, Q at a
+// time; Q offset-aligned slices of equal width (every slice of a stencil
+// matrix) are multiplied with all their loads in flight together, so a
+// workgroup that runs a system on its own waits about one memory round trip
+// per Q slices instead of three per slice.  Q (1 or 2) is a choice of the
+// batched autotuner (measured on the batched workload: pairs 21% faster
+// than single slices; Q = 4 no faster than pairs, with more registers).
+// The rows reach f in the same order for every Q.
+template <int NT, int NX, int Q, class F>
 __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_t sl1, int lo, int hi,
                                          const double* __restrict__ x0, const double* __restrict__ x1, F&& f)
 {
     constexpr int NW = NT / 64;
-    constexpr int Q = 2;
     constexpr int kWMax = NX == 2 ? 5 : 8;  // widest slice grouped (registers)
     const SellView& A = B.A;
     const int w = uniform(threadIdx.x >> 6);
@@ -151,7 +151,7 @@ __device__ __forceinline__ void sys_spmv(const BatchView& B, int64_t sl0, int64_
 // The vectors are parameters of their own, marked restrict (distinct
 // arrays), so that loads of one row may be issued ahead of stores to
 // another.  rt and stv are accessed only with a preconditioner.
-template <int NT, bool PRE, int KIND>
+template <int NT, bool PRE, int KIND, int Q>
 __device__ __forceinline__ void solve_system(const BatchView& B, double* __restrict__ x, double* __restrict__ r,
                              double* __restrict__ rt, double* __restrict__ p, double* __restrict__ s,
                              double* __restrict__ stv, double* __restrict__ w, double* __restrict__ u,
@@ -169,7 +169,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
 
     // ---- initialize (Appendix D): r0 = b - A x0, r~0 = M^{-1} r0, p0 = r~0
     double bb[1] = {0.0};
-    sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, x, nullptr, [&](int64_t i, double ax, double) {
+    sys_spmv<NT, 1, Q>(B, sl0, sl1, lo, hi, x, nullptr, [&](int64_t i, double ax, double) {
         const double bi = b[i];
         const double ri = bi - ax;
         r[i] = ri;
@@ -181,7 +181,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
     __syncthreads();
     // s0 = A p0 and mu0, sigma0, gamma0, nu0, <r0, r0>, <b, b>
     double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, bb[0]};
-    sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
+    sys_spmv<NT, 1, Q>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
         s[i] = si;
         const double ri = r[i];
         const double di = PRE ? d[i] : 1.0;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
         if (KIND == 2) {
             // w0 = A r~0 = s0; u0 = A s~0
             for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) w[i] = s[i];
-            sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, PRE ? stv : s, nullptr, [&](int64_t i, double ui, double) { u[i] = ui; });
+            sys_spmv<NT, 1, Q>(B, sl0, sl1, lo, hi, PRE ? stv : s, nullptr, [&](int64_t i, double ui, double) { u[i] = ui; });
             __syncthreads();
         }
         step_one_reduction(st, t5, PRE, form, nullptr, false);
@@ -236,7 +236,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
             }
             __syncthreads();
             double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
+            sys_spmv<NT, 1, Q>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
                 s[i] = si;
                 const double ri = r[i];
                 const double rti = PRE ? rt[i] : ri;
@@ -281,7 +281,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
             step_one_reduction(st, q, PRE, form, nullptr, false);
             if (st.done) break;
             // u = A s~, w = A r~ (one pass over the system's matrix)
-            sys_spmv<NT, 2>(B, sl0, sl1, lo, hi, PRE ? stv : s, PRE ? rt : r, [&](int64_t i, double ui, double wi) {
+            sys_spmv<NT, 2, Q>(B, sl0, sl1, lo, hi, PRE ? stv : s, PRE ? rt : r, [&](int64_t i, double ui, double wi) {
                 u[i] = ui;
                 w[i] = wi;
             });
@@ -309,7 +309,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
             }
             __syncthreads();
             double m[1] = {0.0};
-            sys_spmv<NT, 1>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
+            sys_spmv<NT, 1, Q>(B, sl0, sl1, lo, hi, p, nullptr, [&](int64_t i, double si, double) {
                 s[i] = si;
                 m[0] = fma(p[i], si, m[0]);
             });
@@ -324,7 +324,7 @@ __device__ __forceinline__ void solve_system(const BatchView& B, double* __restr
     __syncthreads();
 }
 
-template <int NT, bool PRE, int KIND>
+template <int NT, bool PRE, int KIND, int Q>
 __global__ __launch_bounds__(NT) void k_batch(BatchView B, Vecs v, const double* __restrict__ b, double tol,
                                               int maxit, int form, int32_t* __restrict__ queue,
                                               int32_t* __restrict__ iters_out, int32_t* __restrict__ status_out)
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchView B, Vecs v, const double*
         const int q = s_next;
         __syncthreads();
         if (q >= B.nsys) return;  // the queue only grows: every workgroup reaches this
-        solve_system<NT, PRE, KIND>(B, v.x, v.r, v.rt, v.p, v.s, v.st, v.w, v.u, v.d, b, tol, maxit, form, B.order[q],
+        solve_system<NT, PRE, KIND, Q>(B, v.x, v.r, v.rt, v.p, v.s, v.st, v.w, v.u, v.d, b, tol, maxit, form, B.order[q],
                                     iters_out, status_out, lds);
     }
 }
@@ -361,8 +361,8 @@ __global__ void k_batch_reset(int32_t* queue) { *queue = 0; }
 
 // Product of a uniform row group (Group: offset-aligned slices of width W
 // with one list of column offsets, stored one after another): wave w takes
-// slices w, w + kWaves, ... of the group, R = kLockstepSlices / kWaves of
-// them, in rounds of RR slices (RR W <= 20 value loads, to bound the
+// slices w, w + kWaves, ... of the group, R of them (the group holds
+// kWaves R slices), in rounds of RR slices (RR W <= 20 value loads, to bound the
 // registers): a round issues the loads of its values, of the W offsets, of
 // each row's own entry x[row] and of each row's other entries (pre(i, row))
 // together, before any gather, so a round costs two memory round trips.
@@ -377,11 +377,10 @@ __global__ void k_batch_reset(int32_t* queue) { *queue = 0; }
 // same operands in the same order.  Calls f(i, row, y, x[row]) for the valid
 // rows in slice order.
 constexpr int kLsRoundLoads = 20;  // value loads per round of uniform_group
-template <int W, int D0, class Pre, class F>
+template <int W, int D0, int R, class Pre, class F>
 __device__ __forceinline__ void uniform_group(const SellView& A, const Group& G, const double* __restrict__ x,
                                               Pre&& pre, F&& f)
 {
-    constexpr int R = kLockstepSlices / kWaves;
     constexpr int RR = W * R <= kLsRoundLoads ? R : (W * R / 2 <= kLsRoundLoads ? R / 2 : 1);
     constexpr bool SHIFT = D0 >= 1 && D0 + 1 < W;
     const int w = uniform(threadIdx.x >> 6);
@@ -452,7 +451,7 @@ constexpr int kLockstepSpmvWaves = 4;
 // PHASE 0: the same product for an iteration of a system still running.
 // The group's slices go through sys_spmv (two slices per wavefront with
 // their loads in flight together).
-template <bool PRE, int PHASE>
+template <bool PRE, int PHASE, int SPW>
 __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpmvWaves) void k_ls_spmv(BatchView B, GroupView gv, const State* __restrict__ S, Vecs v,
                                                     const double* __restrict__ b, double* __restrict__ P)
 {
@@ -494,7 +493,7 @@ __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpm
     };
     const double* __restrict__ xin = PHASE == 1 ? v.x : p;
     if (G.off >= 0) {
-        constexpr int R = kLockstepSlices / kWaves;
+        constexpr int R = SPW;
         double e0[R], e1[R], e2[R], e3[R];
         auto pre = [&](int i, int row) {
             if constexpr (PHASE == 1) {
@@ -516,9 +515,9 @@ __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpm
         auto go = [&](auto Wc) {
             constexpr int W = decltype(Wc)::value;
             if (W >= 3 && (G.flags & kGroupShift) && G.diag == W / 2)
-                uniform_group<W, W / 2>(B.A, G, xin, pre, f);
+                uniform_group<W, W / 2, R>(B.A, G, xin, pre, f);
             else
-                uniform_group<W, -1>(B.A, G, xin, pre, f);
+                uniform_group<W, -1, R>(B.A, G, xin, pre, f);
         };
         switch (G.width) {
         case 1: go(std::integral_constant<int, 1>{}); break;
@@ -531,7 +530,7 @@ __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpm
         default: go(std::integral_constant<int, kUniformMaxWidth>{}); break;
         }
     } else {
-        sys_spmv<kBlock, 1>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, xin, nullptr,
+        sys_spmv<kBlock, 1, 2>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, xin, nullptr,
                             [&](int64_t row, double y0, double) {
                                 if constexpr (PHASE == 1)
                                     row_done(row, y0, b[row], 0.0, 0.0, PRE ? d[row] : 1.0);
@@ -651,36 +650,54 @@ __global__ __launch_bounds__(kBlock) void k_ls_count(const State* __restrict__ S
 
 
 template <int NT, class F>
-hipError_t with_kind(int kind, int pre, F&& f)
+hipError_t with_kind(int kind, int pre, int q, F&& f)
 {
-    auto go = [&](auto P) -> hipError_t {
+    auto go = [&](auto P, auto Q) -> hipError_t {
         switch (kind) {
-        case 0: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 0>{});
-        case 1: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 1>{});
-        default: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 2>{});
+        case 0: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 0>{}, Q);
+        case 1: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 1>{}, Q);
+        default: return f(std::integral_constant<int, NT>{}, P, std::integral_constant<int, 2>{}, Q);
         }
     };
-    return pre ? go(std::true_type{}) : go(std::false_type{});
+    auto goq = [&](auto P) -> hipError_t {
+        return q == 1 ? go(P, std::integral_constant<int, 1>{}) : go(P, std::integral_constant<int, 2>{});
+    };
+    return pre ? goq(std::true_type{}) : goq(std::false_type{});
+}
+
+// Calls f(std::integral_constant<int, SPW>) for the group view's slices per
+// wavefront.
+template <class F>
+hipError_t with_spw(const GroupView& gv, F&& f)
+{
+    switch (gv.spw) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_batch(const BatchView& B, const Vecs& v, const double* b, double tol, int maxit, int variant,
-                        int pre, int nt, int grid, int32_t* queue, int32_t* iters, int32_t* status, hipStream_t st)
+                        int pre, int nt, int grid, int q, int32_t* queue, int32_t* iters, int32_t* status,
+                        hipStream_t st)
 {
     const int kind = variant == kHS ? 0 : (variant == kPR || variant == kM) ? 1 : 2;
     const int form = nu_form(variant);
+    if (q != 1 && q != 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, queue);
-    auto body = [&](auto NTc, auto P, auto Kc) -> hipError_t {
+    auto body = [&](auto NTc, auto P, auto Kc, auto Qc) -> hipError_t {
         constexpr int T = decltype(NTc)::value;
-        hipLaunchKernelGGL((k_batch<T, decltype(P)::value, decltype(Kc)::value>), dim3(grid), dim3(T), 0, st, B, v, b,
-                           tol, maxit, form, queue, iters, status);
+        hipLaunchKernelGGL((k_batch<T, decltype(P)::value, decltype(Kc)::value, decltype(Qc)::value>), dim3(grid),
+                           dim3(T), 0, st, B, v, b, tol, maxit, form, queue, iters, status);
         return hipGetLastError();
     };
     switch (nt) {
-    case 256: return with_kind<256>(kind, pre, body);
-    case 512: return with_kind<512>(kind, pre, body);
-    case 1024: return with_kind<1024>(kind, pre, body);
+    case 256: return with_kind<256>(kind, pre, q, body);
+    case 512: return with_kind<512>(kind, pre, q, body);
+    case 1024: return with_kind<1024>(kind, pre, q, body);
     default: return hipErrorInvalidValue;
     }
 }
@@ -691,18 +708,21 @@ hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const V
 {
     const int form = nu_form(variant);
     const dim3 grid((unsigned)gv.ngroups), nsys((unsigned)B.nsys), blk(kBlock);
-    if (pre) {
-        hipLaunchKernelGGL((k_ls_spmv<true, 1>), grid, blk, 0, st, B, gv, S, v, b, P);
-        hipLaunchKernelGGL((k_ls_spmv<true, 2>), grid, blk, 0, st, B, gv, S, v, b, P);
-        hipLaunchKernelGGL((k_ls_finish<true, true>), nsys, blk, 0, st, B, gv, S, P, v.x, tol, maxit, form, iters,
-                           status);
-    } else {
-        hipLaunchKernelGGL((k_ls_spmv<false, 1>), grid, blk, 0, st, B, gv, S, v, b, P);
-        hipLaunchKernelGGL((k_ls_spmv<false, 2>), grid, blk, 0, st, B, gv, S, v, b, P);
-        hipLaunchKernelGGL((k_ls_finish<false, true>), nsys, blk, 0, st, B, gv, S, P, v.x, tol, maxit, form, iters,
-                           status);
-    }
-    return hipGetLastError();
+    return with_spw(gv, [&](auto SPWc) -> hipError_t {
+        constexpr int SPW = decltype(SPWc)::value;
+        if (pre) {
+            hipLaunchKernelGGL((k_ls_spmv<true, 1, SPW>), grid, blk, 0, st, B, gv, S, v, b, P);
+            hipLaunchKernelGGL((k_ls_spmv<true, 2, SPW>), grid, blk, 0, st, B, gv, S, v, b, P);
+            hipLaunchKernelGGL((k_ls_finish<true, true>), nsys, blk, 0, st, B, gv, S, P, v.x, tol, maxit, form, iters,
+                               status);
+        } else {
+            hipLaunchKernelGGL((k_ls_spmv<false, 1, SPW>), grid, blk, 0, st, B, gv, S, v, b, P);
+            hipLaunchKernelGGL((k_ls_spmv<false, 2, SPW>), grid, blk, 0, st, B, gv, S, v, b, P);
+            hipLaunchKernelGGL((k_ls_finish<false, true>), nsys, blk, 0, st, B, gv, S, P, v.x, tol, maxit, form,
+                               iters, status);
+        }
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, const Vecs& v, State* S, double* P,
@@ -711,19 +731,24 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
 {
     const int form = nu_form(variant);
     const dim3 grid((unsigned)gv.ngroups), nsys((unsigned)B.nsys), blk(kBlock);
-    for (int k = 0; k < iterations; ++k) {
-        if (pre) {
-            hipLaunchKernelGGL((k_ls_update<true>), grid, blk, 0, st, gv, S, v);
-            hipLaunchKernelGGL((k_ls_spmv<true, 0>), grid, blk, 0, st, B, gv, S, v, nullptr, P);
-            hipLaunchKernelGGL((k_ls_finish<true, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form, iters,
-                               status);
-        } else {
-            hipLaunchKernelGGL((k_ls_update<false>), grid, blk, 0, st, gv, S, v);
-            hipLaunchKernelGGL((k_ls_spmv<false, 0>), grid, blk, 0, st, B, gv, S, v, nullptr, P);
-            hipLaunchKernelGGL((k_ls_finish<false, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form, iters,
-                               status);
+    hipError_t e = with_spw(gv, [&](auto SPWc) -> hipError_t {
+        constexpr int SPW = decltype(SPWc)::value;
+        for (int k = 0; k < iterations; ++k) {
+            if (pre) {
+                hipLaunchKernelGGL((k_ls_update<true>), grid, blk, 0, st, gv, S, v);
+                hipLaunchKernelGGL((k_ls_spmv<true, 0, SPW>), grid, blk, 0, st, B, gv, S, v, nullptr, P);
+                hipLaunchKernelGGL((k_ls_finish<true, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form,
+                                   iters, status);
+            } else {
+                hipLaunchKernelGGL((k_ls_update<false>), grid, blk, 0, st, gv, S, v);
+                hipLaunchKernelGGL((k_ls_spmv<false, 0, SPW>), grid, blk, 0, st, B, gv, S, v, nullptr, P);
+                hipLaunchKernelGGL((k_ls_finish<false, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form,
+                                   iters, status);
+            }
         }
-    }
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ls_count, dim3(1), blk, 0, st, S, B.nsys, active);
     return hipGetLastError();
 }

@@ -196,6 +196,8 @@ struct prcg_batch_s {
     int32_t nsys = 0;
     int64_t nslices = 0;
     int64_t stored = 0;
+    int64_t stored_packed = 0;  // slots of packed slices (they also read a column index)
+    int64_t noffsets = 0;       // offsets of aligned slices
     int num_cus = 256;
     int64_t* slice_row0 = nullptr;
     int32_t* slice_nrows = nullptr;
@@ -212,20 +214,33 @@ struct prcg_batch_s {
     int32_t* queue = nullptr;
     int32_t* iters = nullptr;
     int32_t* status = nullptr;
+    // persistent launch per kind (HS, PR/M, pipe): threads per workgroup,
+    // workgroups, slices multiplied together per wavefront (0: not tuned)
     int tuned_nt[3] = {0, 0, 0};
     int tuned_grid[3] = {0, 0, 0};
+    int tuned_q[3] = {0, 0, 0};
+    // configuration fixed by prcg_batch_set_config (0: autotuned)
+    int force_nt = 0, force_per_cu = 0, force_q = 0, force_group = 0;
     hipGraphExec_t graph[kNumVariants] = {};
     double graph_tol[kNumVariants] = {};
     int32_t graph_maxit[kNumVariants] = {};
     int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
-    // lockstep solver (PR-CG, M-CG): row groups, per-system states, partials
-    int64_t ngroups = 0;
-    int64_t uniform_groups = 0;
-    Group* grp = nullptr;
-    int64_t* sys_grp0 = nullptr;
-    int32_t* gdone = nullptr;
+    // lockstep solver (PR-CG, M-CG): row groups of 8, 16 and 32 slices
+    // (tables 0, 1, 2: 2, 4, 8 slices per wavefront), per-system states,
+    // partials
+    struct GroupTable {
+        int64_t ngroups = 0;
+        int64_t uniform_groups = 0;
+        Group* grp = nullptr;
+        int64_t* sys_grp0 = nullptr;
+        int32_t* gdone = nullptr;
+        int32_t spw = 0;
+    };
+    static constexpr int kTables = 3;
+    GroupTable tab[kTables];
+    int ls_table = -1;         // table in use (-1: not tuned yet)
     State* lstate = nullptr;
-    double* lpart = nullptr;   // 6 * ngroups
+    double* lpart = nullptr;   // 6 * the largest table's ngroups
     int32_t* lactive = nullptr;
     int32_t* hactive = nullptr;  // pinned, two slots
     hipEvent_t lev[2] = {nullptr, nullptr};
@@ -233,7 +248,10 @@ struct prcg_batch_s {
     int32_t mode_req = PRCG_BATCH_AUTO;
     int32_t mode[3] = {0, 0, 0};  // per kind: 0 undecided, else PRCG_BATCH_PERSISTENT / _LOCKSTEP
 
-    GroupView groups() const { return GroupView{grp, sys_grp0, ngroups, gdone}; }
+    GroupView groups(int t) const
+    {
+        return GroupView{tab[t].grp, tab[t].sys_grp0, tab[t].ngroups, tab[t].gdone, tab[t].spw};
+    }
 
     Vecs vecs_view() const
     {
@@ -284,9 +302,14 @@ void free_batch(prcg_batch B)
     if (B->hactive) (void)hipHostFree(B->hactive);
     void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
                    B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
-                   B->grp, B->sys_grp0, B->gdone, B->lstate, B->lpart, B->lactive};
+                   B->lstate, B->lpart, B->lactive};
     for (void* p : dev)
         if (p) (void)hipFree(p);
+    for (auto& t : B->tab) {
+        void* td[] = {t.grp, t.sys_grp0, t.gdone};
+        for (void* p : td)
+            if (p) (void)hipFree(p);
+    }
     delete B;
 }
 
@@ -1086,6 +1109,9 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         if (aligned[q]) noff += width[q];
     }
     B->stored = hptr[ns];
+    B->noffsets = noff;
+    for (int64_t q = 0; q < ns; ++q)
+        if (!aligned[q]) B->stored_packed += (int64_t)kSlice * width[q];
     for (int64_t q = 0; q < ns; ++q)
         if (hptr[q + 1] * (int64_t)sizeof(double) > kCachedValueBytes) {
             B->stream_from = q + 1;
@@ -1102,8 +1128,8 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     BTRY(hipMemcpyAsync(B->slice_shape, hshape.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
     BTRY(launch_fill_sell(n, ns, A->row_ptr, A->col, A->val, B->slice_row0, B->slice_nrows, B->slice_ptr,
                           B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, 1, st));
-    // Row groups of the lockstep solver: runs of up to kLockstepSlices slices
-    // of one system.  Offset-aligned slices of one width (at most
+    // Row groups of the lockstep solver: runs of up to 8, 16 or 32 slices
+    // of one system (the autotuner picks the size).  Offset-aligned slices of one width (at most
     // kUniformMaxWidth) with the same column offsets form uniform groups,
     // which the product multiplies with all their value loads issued at
     // once; every other run of slices forms a general group.
@@ -1125,55 +1151,66 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
             if (hsoff[(size_t)hmeta[q] + u] != hsoff[(size_t)hmeta[t] + u]) return false;
         return true;
     };
-    std::vector<Group> grp;
-    std::vector<int64_t> sys_grp0((size_t)nsys + 1);
-    for (int32_t q = 0; q < nsys; ++q) {
-        sys_grp0[q] = (int64_t)grp.size();
-        for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1];) {
-            int64_t len = 1;
-            while (len < kLockstepSlices && s0 + len < sys_slice0[q + 1] && same_key(s0, s0 + len)) ++len;
-            Group G{};
-            G.slice0 = (int32_t)s0;
-            G.nsl = (int32_t)len;
-            G.row0 = (int32_t)slice_row0[(size_t)s0];
-            const int64_t last = s0 + len - 1;
-            G.nrows = (int32_t)(slice_row0[(size_t)last] + slice_nrows[(size_t)last] - G.row0);
-            G.sys = q;
-            G.lo = (int32_t)sys_row_offset[q];
-            G.hi = (int32_t)(sys_row_offset[q + 1] - 1);
-            G.off = uniform_slice(s0) ? hmeta[s0] : -1;
-            G.width = width[s0];
-            G.vrow = (int32_t)(hptr[s0] / kSlice);
-            G.diag = -1;
-            G.flags = 0;
-            if (G.off >= 0) {
-                const int32_t* o = hsoff.data() + G.off;
-                for (int32_t u = 0; u < G.width; ++u) {
-                    G.o[u] = o[u];
-                    if (o[u] == 0) G.diag = u;
+    // one table per group size; the host arrays stay alive until the copies
+    // have run (the stream is synchronised below)
+    std::vector<Group> grp[prcg_batch_s::kTables];
+    std::vector<int64_t> sys_grp0[prcg_batch_s::kTables];
+    int64_t max_groups = 1;
+    for (int t = 0; t < prcg_batch_s::kTables; ++t) {
+        const int spw = 2 << t;  // 2, 4, 8 slices per wavefront
+        const int gslices = kWaves * spw;
+        sys_grp0[t].assign((size_t)nsys + 1, 0);
+        for (int32_t q = 0; q < nsys; ++q) {
+            sys_grp0[t][q] = (int64_t)grp[t].size();
+            for (int64_t s0 = sys_slice0[q]; s0 < sys_slice0[q + 1];) {
+                int64_t len = 1;
+                while (len < gslices && s0 + len < sys_slice0[q + 1] && same_key(s0, s0 + len)) ++len;
+                Group G{};
+                G.slice0 = (int32_t)s0;
+                G.nsl = (int32_t)len;
+                G.row0 = (int32_t)slice_row0[(size_t)s0];
+                const int64_t last = s0 + len - 1;
+                G.nrows = (int32_t)(slice_row0[(size_t)last] + slice_nrows[(size_t)last] - G.row0);
+                G.sys = q;
+                G.lo = (int32_t)sys_row_offset[q];
+                G.hi = (int32_t)(sys_row_offset[q + 1] - 1);
+                G.off = uniform_slice(s0) ? hmeta[s0] : -1;
+                G.width = width[s0];
+                G.vrow = (int32_t)(hptr[s0] / kSlice);
+                G.diag = -1;
+                G.flags = 0;
+                if (G.off >= 0) {
+                    const int32_t* o = hsoff.data() + G.off;
+                    for (int32_t u = 0; u < G.width; ++u) {
+                        G.o[u] = o[u];
+                        if (o[u] == 0) G.diag = u;
+                    }
+                    if (G.diag >= 1 && G.diag + 1 < G.width && o[G.diag - 1] == -1 && o[G.diag + 1] == 1)
+                        G.flags |= kGroupShift;
                 }
-                if (G.diag >= 1 && G.diag + 1 < G.width && o[G.diag - 1] == -1 && o[G.diag + 1] == 1)
-                    G.flags |= kGroupShift;
+                grp[t].push_back(G);
+                s0 += len;
             }
-            grp.push_back(G);
-            s0 += len;
         }
+        sys_grp0[t][nsys] = (int64_t)grp[t].size();
+        auto& T = B->tab[t];
+        T.spw = spw;
+        T.ngroups = sys_grp0[t][nsys];
+        for (const Group& G : grp[t]) T.uniform_groups += G.off >= 0;
+        max_groups = std::max(max_groups, T.ngroups);
+        BTRY(hipMalloc(&T.grp, sizeof(Group) * T.ngroups));
+        BTRY(hipMalloc(&T.sys_grp0, sizeof(int64_t) * (nsys + 1)));
+        BTRY(hipMalloc(&T.gdone, sizeof(int32_t) * T.ngroups));
+        BTRY(hipMemcpyAsync(T.grp, grp[t].data(), sizeof(Group) * T.ngroups, hipMemcpyHostToDevice, st));
+        BTRY(hipMemcpyAsync(T.sys_grp0, sys_grp0[t].data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice,
+                            st));
     }
-    sys_grp0[nsys] = (int64_t)grp.size();
-    B->ngroups = sys_grp0[nsys];
-    B->uniform_groups = 0;
-    for (const Group& G : grp) B->uniform_groups += G.off >= 0;
-    BTRY(hipMalloc(&B->grp, sizeof(Group) * B->ngroups));
-    BTRY(hipMalloc(&B->sys_grp0, sizeof(int64_t) * (nsys + 1)));
-    BTRY(hipMalloc(&B->gdone, sizeof(int32_t) * B->ngroups));
     BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
-    BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * B->ngroups));
+    BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * max_groups));
     BTRY(hipMalloc(&B->lactive, sizeof(int32_t) * 4));
     BTRY(hipHostMalloc(&B->hactive, sizeof(int32_t) * 2, hipHostMallocDefault));
     BTRY(hipEventCreateWithFlags(&B->lev[0], hipEventDisableTiming));
     BTRY(hipEventCreateWithFlags(&B->lev[1], hipEventDisableTiming));
-    BTRY(hipMemcpyAsync(B->grp, grp.data(), sizeof(Group) * B->ngroups, hipMemcpyHostToDevice, st));
-    BTRY(hipMemcpyAsync(B->sys_grp0, sys_grp0.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st));
     // largest systems first
     std::vector<int32_t> order((size_t)nsys);
     for (int32_t q = 0; q < nsys; ++q) order[q] = q;
@@ -1219,8 +1256,8 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
     // the count of a chunk is read while the next chunk runs.  Every system
     // is done after maxit iterations, so the chunk count is bounded.
     constexpr int kLockstepChunk = 16;
-    const GroupView gv = B->groups();
     auto run_lockstep = [&]() -> hipError_t {
+        const GroupView gv = B->groups(B->ls_table);
         hipError_t e = launch_lockstep_init(view, gv, vv, bvec, B->lstate, B->lpart, tol, maxit, v, A->precond,
                                             B->iters, B->status, st);
         if (e != hipSuccess) return e;
@@ -1254,40 +1291,120 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
         }
         return hipSuccess;
     };
-    // autotune once per kind: workgroup size x workgroups per CU, timed on a
-    // short run of this batch (tol = 0, a few iterations per system)
-    if (B->tuned_nt[kind] == 0) {
-        const char* force = std::getenv("PRCG_BATCH_CONFIG");
-        int fnt = 0, fper = 0;
-        if (force && std::sscanf(force, "%d,%d", &fnt, &fper) == 2 && (fnt == 256 || fnt == 512 || fnt == 1024) &&
-            fper >= 1 && fper <= 8) {
-            B->tuned_nt[kind] = fnt;
-            B->tuned_grid[kind] = std::min<int64_t>(B->nsys, (int64_t)B->num_cus * fper);
-        } else {
-            const int cand[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
-            hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto elapsed = [&](auto&& work, float& ms) -> prcg_status {
+        if (!e0) {
             HIP_TRY(hipEventCreate(&e0));
             HIP_TRY(hipEventCreate(&e1));
-            float best = 1e30f;
-            const int trial_it = std::min<int32_t>(maxit, 12);
-            for (auto& c : cand) {
-                const int grid = (int)std::min<int64_t>(B->nsys, (int64_t)B->num_cus * c[1]);
-                HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
-                HIP_TRY(hipEventRecord(e0, st));
-                HIP_TRY(launch_batch(view, vv, bvec, 0.0, trial_it, v, A->precond, c[0], grid, B->queue, B->iters,
-                                     B->status, st));
-                HIP_TRY(hipEventRecord(e1, st));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
-                    best = ms;
-                    B->tuned_nt[kind] = c[0];
-                    B->tuned_grid[kind] = grid;
+        }
+        HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipEventRecord(e0, st));
+        HIP_TRY(work());
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        return PRCG_OK;
+    };
+    auto release_events = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        e0 = e1 = nullptr;
+    };
+    // Autotune once per kind the persistent launch: threads per workgroup x
+    // workgroups per compute unit x slices multiplied together per
+    // wavefront, each candidate timed on a short run of this batch (tol = 0,
+    // a few iterations per system).  Dimensions fixed by
+    // prcg_batch_set_config (or PRCG_BATCH_CONFIG="threads,per_cu") are not
+    // searched.
+    if (B->tuned_nt[kind] == 0) {
+        int fnt = B->force_nt, fper = B->force_per_cu;
+        const char* env = std::getenv("PRCG_BATCH_CONFIG");
+        int ent = 0, eper = 0;
+        if (!fnt && env && std::sscanf(env, "%d,%d", &ent, &eper) == 2 && (ent == 256 || ent == 512 || ent == 1024) &&
+            eper >= 1 && eper <= 8) {
+            fnt = ent;
+            fper = eper;
+        }
+        const int nts[] = {256, 512, 1024};
+        const int pers[] = {1, 2, 4, 8};
+        const int qs[] = {1, 2};
+        float best = 1e30f;
+        const int trial_it = std::min<int32_t>(maxit, 12);
+        bool single = true;  // a single candidate needs no trial
+        int ncand = 0;
+        for (int nt : nts)
+            for (int per : pers)
+                for (int q : qs) {
+                    if ((fnt && nt != fnt) || (fper && per != fper) || (B->force_q && q != B->force_q)) continue;
+                    if (nt * per > 2048) continue;  // threads per compute unit
+                    ++ncand;
+                }
+        single = ncand == 1;
+        for (int nt : nts)
+            for (int per : pers)
+                for (int q : qs) {
+                    if ((fnt && nt != fnt) || (fper && per != fper) || (B->force_q && q != B->force_q)) continue;
+                    if (nt * per > 2048) continue;
+                    const int grid = (int)std::min<int64_t>(B->nsys, (int64_t)B->num_cus * per);
+                    float ms = 0.f;
+                    if (!single) {
+                        prcg_status s = elapsed(
+                            [&] {
+                                return launch_batch(view, vv, bvec, 0.0, trial_it, v, A->precond, nt, grid, q,
+                                                    B->queue, B->iters, B->status, st);
+                            },
+                            ms);
+                        if (s != PRCG_OK) {
+                            release_events();
+                            return s;
+                        }
+                    }
+                    if (ms < best) {
+                        best = ms;
+                        B->tuned_nt[kind] = nt;
+                        B->tuned_grid[kind] = grid;
+                        B->tuned_q[kind] = q;
+                    }
+                }
+        if (B->tuned_nt[kind] == 0) {
+            release_events();
+            return fail(PRCG_EINVAL, "no persistent launch shape satisfies the fixed configuration");
+        }
+    }
+    // Lockstep group size (PR-CG and M-CG): groups of 8, 16 and 32 slices,
+    // each timed on the initialisation and 32 iterations of this batch
+    // (tol = 0); fixed by prcg_batch_set_config.
+    if (kind == 1 && B->mode_req != PRCG_BATCH_PERSISTENT && B->ls_table < 0) {
+        float best = 1e30f;
+        for (int t = 0; t < prcg_batch_s::kTables; ++t) {
+            if (B->force_group && kWaves * B->tab[t].spw != B->force_group) continue;
+            float ms = 0.f;
+            if (!B->force_group) {
+                const GroupView gv = B->groups(t);
+                prcg_status s = elapsed(
+                    [&] {
+                        hipError_t e = launch_lockstep_init(view, gv, vv, bvec, B->lstate, B->lpart, 0.0,
+                                                            std::min<int32_t>(maxit, 32), v, A->precond, B->iters,
+                                                            B->status, st);
+                        if (e == hipSuccess)
+                            e = launch_lockstep_iterations(view, gv, vv, B->lstate, B->lpart, 32, v, A->precond,
+                                                           B->iters, B->status, B->lactive, st);
+                        return e;
+                    },
+                    ms);
+                if (s != PRCG_OK) {
+                    release_events();
+                    return s;
                 }
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
+            if (ms < best) {
+                best = ms;
+                B->ls_table = t;
+            }
+        }
+        for (auto& g : B->ls_graph) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
         }
     }
     // persistent or lockstep: PR-CG and M-CG time one whole solve of each on
@@ -1299,27 +1416,26 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
         } else if (B->mode_req == PRCG_BATCH_LOCKSTEP) {
             B->mode[kind] = PRCG_BATCH_LOCKSTEP;
         } else {
-            hipEvent_t e0, e1;
-            HIP_TRY(hipEventCreate(&e0));
-            HIP_TRY(hipEventCreate(&e1));
             float ms[2] = {0.f, 0.f};
             for (int m = 0; m < 2; ++m) {
-                HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
-                HIP_TRY(hipEventRecord(e0, st));
-                if (m == 0)
-                    HIP_TRY(launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
-                                         B->tuned_grid[kind], B->queue, B->iters, B->status, st));
-                else
-                    HIP_TRY(run_lockstep());
-                HIP_TRY(hipEventRecord(e1, st));
-                HIP_TRY(hipEventSynchronize(e1));
-                HIP_TRY(hipEventElapsedTime(&ms[m], e0, e1));
+                prcg_status s = elapsed(
+                    [&] {
+                        if (m == 0)
+                            return launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
+                                                B->tuned_grid[kind], B->tuned_q[kind], B->queue, B->iters, B->status,
+                                                st);
+                        return run_lockstep();
+                    },
+                    ms[m]);
+                if (s != PRCG_OK) {
+                    release_events();
+                    return s;
+                }
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
             B->mode[kind] = ms[1] < ms[0] ? PRCG_BATCH_LOCKSTEP : PRCG_BATCH_PERSISTENT;
         }
     }
+    release_events();
     if (B->mode[kind] == PRCG_BATCH_LOCKSTEP) {
         HIP_TRY(hipMemcpyAsync(vv.x, x, nb, hipMemcpyDeviceToDevice, st));
         HIP_TRY(run_lockstep());
@@ -1330,7 +1446,8 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
             B->graph[v] = nullptr;
             HIP_TRY(hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal));
             hipError_t err = launch_batch(view, vv, bvec, tol, maxit, v, A->precond, B->tuned_nt[kind],
-                                          B->tuned_grid[kind], B->queue, B->iters, B->status, A->capture);
+                                          B->tuned_grid[kind], B->tuned_q[kind], B->queue, B->iters, B->status,
+                                          A->capture);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(A->capture, &g);
             if (err != hipSuccess || e2 != hipSuccess) {
@@ -1364,6 +1481,61 @@ prcg_status prcg_batch_config(prcg_batch B, prcg_variant v, int32_t* threads, in
     const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
     *threads = B->tuned_nt[kind];
     *grid = B->tuned_grid[kind];
+    return PRCG_OK;
+}
+
+prcg_status prcg_batch_set_config(prcg_batch B, int32_t threads, int32_t per_cu, int32_t slices_in_flight,
+                                  int32_t group_slices)
+{
+    if (!B) return fail(PRCG_EINVAL, "null batch");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(PRCG_EINVAL, "threads must be 0, 256, 512 or 1024");
+    if (per_cu < 0 || per_cu > 8 || (threads && per_cu && threads * per_cu > 2048))
+        return fail(PRCG_EINVAL, "per_cu must be in 0..8 with threads x per_cu <= 2048");
+    if (slices_in_flight < 0 || slices_in_flight > 2) return fail(PRCG_EINVAL, "slices_in_flight must be 0, 1 or 2");
+    if (group_slices != 0 && group_slices != 8 && group_slices != 16 && group_slices != 32)
+        return fail(PRCG_EINVAL, "group_slices must be 0, 8, 16 or 32");
+    HIP_TRY(hipSetDevice(B->A->device));
+    HIP_TRY(hipStreamSynchronize(B->A->stream));
+    B->force_nt = threads;
+    B->force_per_cu = per_cu;
+    B->force_q = slices_in_flight;
+    B->force_group = group_slices;
+    for (int k = 0; k < 3; ++k) B->tuned_nt[k] = B->tuned_grid[k] = B->tuned_q[k] = 0;
+    B->ls_table = -1;
+    for (auto& m : B->mode) m = 0;
+    for (auto& g : B->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    for (auto& g : B->ls_graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    return PRCG_OK;
+}
+
+prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props* props)
+{
+    if (!B || !props) return fail(PRCG_EINVAL, "null argument");
+    if (check_batch_variant(v) != PRCG_OK) return PRCG_EINVAL;
+    const int kind = v == PRCG_HS ? 0 : (v == PRCG_PR || v == PRCG_M) ? 1 : 2;
+    prcg_batch_props p{};
+    p.n = B->A->n;
+    p.nsys = B->nsys;
+    p.stored_entries = B->stored;
+    // values, the column indices of packed slices, the offsets of aligned
+    // slices and the per-slice metadata
+    p.matrix_bytes = 8 * B->stored + 4 * B->stored_packed + 4 * B->noffsets + 16 * B->nslices;
+    p.mode = B->mode[kind];
+    p.threads = B->tuned_nt[kind];
+    p.grid = B->tuned_grid[kind];
+    p.slices_in_flight = B->tuned_q[kind];
+    const int t = kind == 1 ? B->ls_table : -1;
+    p.group_slices = t >= 0 ? kWaves * B->tab[t].spw : 0;
+    p.groups = t >= 0 ? B->tab[t].ngroups : 0;
+    p.uniform_groups = t >= 0 ? B->tab[t].uniform_groups : 0;
+    *props = p;
     return PRCG_OK;
 }
 

@@ -35,7 +35,8 @@ BATCH_MODES = {"auto": 0, "persistent": 1, "lockstep": 2}
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
             "prcg_time_kernels", "prcg_get_props", "prcg_create_batch", "prcg_solve_batched",
             "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config",
-            "prcg_batch_set_mode", "prcg_batch_mode", "prcg_solve_noalloc")
+            "prcg_batch_set_mode", "prcg_batch_mode", "prcg_solve_noalloc", "prcg_batch_set_config",
+            "prcg_batch_get_props")
 NOALLOC_MAX_ITERS = 65536  # PRCG_NOALLOC_MAX_ITERS
 
 
@@ -56,6 +57,13 @@ class prcg_matrix_props(ctypes.Structure):
                 ("block", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
                 ("aligned_slices_frac", ctypes.c_double), ("kernels", ctypes.c_int32), ("stage2", ctypes.c_int32),
                 ("streamed_entries", ctypes.c_int64)]
+
+
+class prcg_batch_props(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("stored_entries", ctypes.c_int64), ("matrix_bytes", ctypes.c_int64),
+                ("groups", ctypes.c_int64), ("uniform_groups", ctypes.c_int64), ("nsys", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("threads", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("slices_in_flight", ctypes.c_int32), ("group_slices", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -96,6 +104,8 @@ def load_library(path: str = LIB_PATH):
         "prcg_batch_config": (i32, [_VP, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "prcg_batch_set_mode": (i32, [_VP, i32]),
         "prcg_batch_mode": (i32, [_VP, i32, ctypes.POINTER(i32)]),
+        "prcg_batch_set_config": (i32, [_VP, i32, i32, i32, i32]),
+        "prcg_batch_get_props": (i32, [_VP, i32, ctypes.POINTER(prcg_batch_props)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -183,6 +193,16 @@ def prcg_batch_config(B, variant):
 
 def prcg_batch_set_mode(B, mode):
     _check(load_library().prcg_batch_set_mode(B, mode))
+
+
+def prcg_batch_set_config(B, threads=0, per_cu=0, slices_in_flight=0, group_slices=0):
+    _check(load_library().prcg_batch_set_config(B, threads, per_cu, slices_in_flight, group_slices))
+
+
+def prcg_batch_get_props(B, variant) -> prcg_batch_props:
+    p = prcg_batch_props()
+    _check(load_library().prcg_batch_get_props(B, variant, ctypes.byref(p)))
+    return p
 
 
 def prcg_batch_mode(B, variant) -> int:
@@ -377,3 +397,14 @@ class Batch:
         """The mode in use for a variant, or None before its first solve."""
         m = prcg_batch_mode(self.handle, VARIANTS[variant])
         return {v: k for k, v in BATCH_MODES.items()}.get(m) if m else None
+
+    def set_config(self, threads: int = 0, per_cu: int = 0, slices_in_flight: int = 0, group_slices: int = 0):
+        """Fix parts of the configuration (0: left to the autotuner)."""
+        prcg_batch_set_config(self.handle, threads, per_cu, slices_in_flight, group_slices)
+
+    def props(self, variant: str = "pr") -> dict:
+        """Storage and the configuration in use for a variant."""
+        p = prcg_batch_get_props(self.handle, VARIANTS[variant])
+        out = {name: getattr(p, name) for name, _ in p._fields_}
+        out["mode"] = {v: k for k, v in BATCH_MODES.items()}.get(out["mode"]) if out["mode"] else None
+        return out

@@ -73,7 +73,7 @@ def header_struct(name):
     return re.findall(r"(int32_t|int64_t|double)\s+(\w+)\s*;", body)
 
 
-@pytest.mark.parametrize("name", ["prcg_matrix_props", "prcg_info"])
+@pytest.mark.parametrize("name", ["prcg_matrix_props", "prcg_info", "prcg_batch_props"])
 def test_binding_structs_match_the_header(name):
     """Field order, names and widths of the structs passed across the ABI."""
     from paper_1905_01549_amd import prcg

@@ -247,3 +247,73 @@ def test_nan_system_leaves_neighbours_alone(prcg, mode, config, monkeypatch):
     others = [s for s in range(len(mats)) if s != bad]
     check_systems(x, iters, status, mats, bs, offs, "pr", "none", 1e-10, which=others)
     assert all(np.all(np.isfinite(x[offs[s]:offs[s + 1]])) for s in others)
+
+
+@pytest.mark.parametrize("threads,per_cu,q", [(256, 1, 1), (256, 8, 2), (512, 4, 1), (1024, 2, 2)])
+def test_every_persistent_candidate(prcg, threads, per_cu, q):
+    """Each launch shape the autotuner may pick (threads per workgroup x
+    workgroups per compute unit x slices multiplied together per wavefront),
+    fixed through prcg_batch_set_config: every system against the oracle."""
+    A, offs, b, mats, bs = small_batch(9)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    B = prcg.Batch(M, offs)
+    B.set_config(threads, per_cu, q, 0)
+    B.set_mode("persistent")
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000)
+    p = B.props("pr")
+    assert (p["threads"], p["slices_in_flight"], p["mode"]) == (threads, q, "persistent")
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", "jacobi", 1e-10)
+
+
+def test_slices_in_flight_do_not_change_the_bits(prcg):
+    """Multiplying one or two slices per wavefront at a time feeds the rows
+    to the sums in the same order: identical results."""
+    A, offs, b, mats, bs = small_batch(7)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    out = []
+    for q in (1, 2):
+        B = prcg.Batch(M, offs)
+        B.set_config(512, 2, q, 0)
+        B.set_mode("persistent")
+        x, iters, _ = B.solve(b, "pipe_pr", 1e-10, 5000)
+        out.append((x.cpu().numpy(), iters))
+        B.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("group_slices", [8, 16, 32])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_every_lockstep_group_size(prcg, group_slices, precond):
+    """Lockstep row groups of 8, 16 and 32 slices (2, 4, 8 per wavefront),
+    stencil systems (uniform groups) next to packed and tiny ones: every
+    system against the oracle."""
+    mats = [P.random_spd(700 + 173 * s, 5.0, 20 + s) for s in range(2)]
+    mats += [P.batch_system(s, 64, 5000)[0] for s in range(5)]
+    mats += [P.poisson2d(3), P.poisson2d(40, 37)]
+    bs = [P.uniform_vector(A.n, 50 + s) for s, A in enumerate(mats)]
+    A, offs = P.block_diag(mats)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
+    B = prcg.Batch(M, offs)
+    B.set_config(0, 0, 0, group_slices)
+    B.set_mode("lockstep")
+    x, iters, status = B.solve(np.concatenate(bs), "pr", 1e-10, 5000)
+    p = B.props("pr")
+    assert p["group_slices"] == group_slices and p["mode"] == "lockstep"
+    assert 0 < p["uniform_groups"] < p["groups"]
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", precond, 1e-10)
+
+
+def test_autotuned_configuration_is_reported(prcg):
+    A, offs, b, mats, bs = small_batch(6)
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    B = prcg.Batch(M, offs)
+    assert B.props("pr")["threads"] == 0 and B.props("pr")["mode"] is None
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000)
+    p = B.props("pr")
+    assert p["threads"] in (256, 512, 1024) and p["slices_in_flight"] in (1, 2) and p["grid"] >= 1
+    assert p["group_slices"] in (8, 16, 32) and p["mode"] in ("persistent", "lockstep")
+    assert p["nsys"] == 6 and p["n"] == A.n and p["matrix_bytes"] >= 8 * p["stored_entries"]
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", "none", 1e-10)
+    for bad in [(300, 0, 0, 0), (1024, 4, 0, 0), (0, 9, 0, 0), (0, 0, 3, 0), (0, 0, 0, 12)]:
+        with pytest.raises(prcg.PrcgError):
+            B.set_config(*bad)
