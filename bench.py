@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched workload (both modes; one JSON line)")
     ap.add_argument("--batched-reps", type=int, default=3, help="timed batched solves per mode")
+    ap.add_argument("--batched-config", default="",
+                    help="threads,per_cu,slices_in_flight,group_slices fixed instead of autotuned "
+                         "(0 leaves a part to the autotuner), so that profiled runs launch the same kernels")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the 512 one-at-a-time solves of the batched comparison (profiling runs)")
     ap.add_argument("--suite", action="store_true",
@@ -136,6 +139,15 @@ def stream_triad(torch, n=64 * 1024 * 1024, reps=20):
     return 3 * 8 * n / sec / 1e9
 
 
+def calibration_copy(torch):
+    """A plain device-to-device copy of known size (256 MiB read + 256 MiB
+    written) to calibrate hardware byte counters against."""
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def device_facts(torch):
     """The properties the design assumes, as the runtime reports them."""
     pr = torch.cuda.get_device_properties(0)
@@ -147,12 +159,14 @@ def device_facts(torch):
     return facts
 
 
-def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True):
+def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, config=""):
     """512 anisotropic systems in one batched solve (the mode the solver picks;
     both modes are timed) vs one prcg_solve per system."""
     A, offs, b, xs, eps = problems.config4()
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
+    if config:
+        B.set_config(*[int(v) for v in config.split(",")])
     bt = torch.as_tensor(b, device="cuda")
     x, iters, status = B.solve(bt, "pr", 1e-10, 20000)  # includes the autotuner's trial runs
     assert all(st == "ok" for st in status)
@@ -449,7 +463,9 @@ def main():
         suite(torch, prcg, problems)
         return
     if args.batched_only:
-        print(json.dumps(batched_section(torch, prcg, problems, traffic, args.batched_reps, not args.no_sequential)),
+        calibration_copy(torch)
+        print(json.dumps(batched_section(torch, prcg, problems, traffic, args.batched_reps, not args.no_sequential,
+                                         args.batched_config)),
               flush=True)
         return
     if args.kernels_only and args.workload == "varcoef27_160":
@@ -466,12 +482,7 @@ def main():
     n = A.n
 
     if args.kernels_only:
-        # a plain copy of known size (256 MiB read + 256 MiB written) to
-        # calibrate hardware byte counters against
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        calibration_copy(torch)
         kt = M.time_kernels(args.variant, 200)
         fused = any("fused" in name for name, _ in kt)  # the structure the variant runs
         jac = pre == "jacobi"

@@ -205,14 +205,21 @@ __global__ void k_block_check(int64_t n, const int32_t* __restrict__ row_ptr, co
 }
 
 // g_e = -lambda_{row(e)} * x_{col(e)} for every stored entry (the gradient
-// of w^T A^{-1} b with respect to entry e, given lambda = A^{-1} w).
+// of w^T A^{-1} b with respect to entry e, given lambda = A^{-1} w): L lanes per row,
+// lane t of a row taking its entries t, t + L, ..., so that the lanes of a
+// wavefront read col and write g in consecutive runs (rows are consecutive
+// in CSR) instead of one strided run per thread.
+template <int L>
 __global__ void k_outer_csr(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                             const double* __restrict__ lam, const double* __restrict__ x, double* __restrict__ g)
 {
-    const int64_t i = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * kSetupBlock + threadIdx.x;
+    const int64_t i = t / L;
     if (i >= n) return;
+    const int lane = (int)(t % L);
     const double li = -lam[i];
-    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) g[e] = li * x[col[e]];
+    const int32_t e1 = row_ptr[i + 1];
+    for (int32_t e = row_ptr[i] + lane; e < e1; e += L) g[e] = li * x[col[e]];
 }
 
 }  // namespace
@@ -259,9 +266,21 @@ hipError_t launch_block_check(int64_t n, const int32_t* row_ptr, const int32_t* 
 }
 
 hipError_t launch_outer_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* lam, const double* x,
-                            double* g, hipStream_t st)
+                            double* g, double mean_row, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_outer_csr, rows_grid(n), dim3(kSetupBlock), 0, st, n, row_ptr, col, lam, x, g);
+    // lanes per row: the power of two at or above the mean row length, 4..32
+    auto go = [&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        hipLaunchKernelGGL((k_outer_csr<L>), rows_grid(n * L), dim3(kSetupBlock), 0, st, n, row_ptr, col, lam, x, g);
+    };
+    if (mean_row <= 4.0)
+        go(std::integral_constant<int, 4>{});
+    else if (mean_row <= 8.0)
+        go(std::integral_constant<int, 8>{});
+    else if (mean_row <= 16.0)
+        go(std::integral_constant<int, 16>{});
+    else
+        go(std::integral_constant<int, 32>{});
     return hipGetLastError();
 }
 

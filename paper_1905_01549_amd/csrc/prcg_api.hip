@@ -1000,7 +1000,7 @@ prcg_status prcg_adjoint(prcg_matrix A, prcg_variant v, const double* x, const d
     prcg_status s = run_solve(A, v, gx, x0, lam, tol, maxit, &st);
     if (s != PRCG_OK) return s;
     if (gvals && A->nnz > 0) {
-        HIP_TRY(launch_outer_csr(A->n, A->row_ptr, A->col, lam, x, gvals, A->stream));
+        HIP_TRY(launch_outer_csr(A->n, A->row_ptr, A->col, lam, x, gvals, (double)A->nnz / (double)A->n, A->stream));
         HIP_TRY(hipStreamSynchronize(A->stream));
     }
     fill_info(st, info);

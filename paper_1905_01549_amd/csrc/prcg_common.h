@@ -182,7 +182,7 @@ hipError_t launch_fill_sell(int64_t n, int64_t nslices, const int32_t* row_ptr, 
 hipError_t launch_block_check(int64_t n, const int32_t* row_ptr, const int32_t* col,
                               const int32_t* row_sys, const int64_t* sys_off, int32_t* flags, hipStream_t st);
 hipError_t launch_outer_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* lam,
-                            const double* x, double* g, hipStream_t st);
+                            const double* x, double* g, double mean_row, hipStream_t st);
 hipError_t launch_spmv(const SellView* sell, const CsrView* csr, const Split& sp, const double* x,
                        double* y, hipStream_t st);
 
