@@ -315,10 +315,12 @@ prcg_status prcg_create_batch(prcg_matrix blockdiag, int32_t nsys, const int64_t
  *     x slices multiplied together per wavefront in the product (1 or 2),
  *     a few iterations of every system each;
  *   lockstep row groups (PR-CG, M-CG): 8, 16 or 32 slices of 64 rows per
- *     group (2, 4 or 8 slices per wavefront), the initialisation and 32
- *     iterations each;
+ *     group (2, 4 or 8 slices per wavefront), each with three launches per
+ *     iteration and, where allowed, with the fused iteration
+ *     (prcg_batch_set_fusion), the initialisation and 32 iterations each;
  *   mode (PR-CG, M-CG, unless set): one whole solve in each, the faster kept.
- * prcg_batch_set_config fixes any of these instead.  The persistent launch
+ * prcg_batch_set_config and prcg_batch_set_fusion fix any of these
+ * instead.  The persistent launch
  * and chunks of lockstep iterations are captured in HIP graphs.
  * Reductions are deterministic for a fixed configuration (threads per
  * workgroup and group size set the order of a system's sums; the number of
@@ -361,13 +363,15 @@ typedef struct {
     int32_t grid;             /* persistent: workgroups                               */
     int32_t slices_in_flight; /* persistent: slices multiplied together per wavefront */
     int32_t group_slices;     /* lockstep: slices per row group (PR-CG, M-CG)         */
+    int32_t fused;            /* lockstep: 1 when iterations run fused                */
 } prcg_batch_props;
 prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props* props);
 
 /* How the batched solver runs PR-CG and M-CG (HS-CG and the pipelined
  * variants always run persistent):
  *   PRCG_BATCH_PERSISTENT  one persistent kernel, a workgroup per system;
- *   PRCG_BATCH_LOCKSTEP    three launches per iteration over the row groups
+ *   PRCG_BATCH_LOCKSTEP    three launches per iteration (two when fused:
+ *     prcg_batch_set_fusion) over the row groups
  *     (8, 16 or 32 slices of 64 rows of one system) of every system still
  *     running: the
  *     vector update, the product with one partial per group of each inner
@@ -376,6 +380,31 @@ prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props*
  *     16 iterations whether a system is still running;
  *   PRCG_BATCH_AUTO (default)  the faster of the two on the first solve. */
 typedef enum { PRCG_BATCH_AUTO = 0, PRCG_BATCH_PERSISTENT = 1, PRCG_BATCH_LOCKSTEP = 2 } prcg_batch_mode_t;
+
+/* Lockstep iterations of PR-CG and M-CG without a preconditioner may run
+ * fused: one launch updates x, r and p of a row group and multiplies the
+ * new p, recomputing p at the rows outside the group that its stencil
+ * reaches, then the per-system stage 2 (two launches per iteration; eight
+ * vector words per row move instead of ten).  Allowed for a group table
+ * whose groups are all offset-aligned with one offset list each, of at most
+ * 7 slots and a span (largest minus smallest column offset, 0 included) of
+ * at most 1536, at 8 or 16 slices per group.  The results equal those of three
+ * launches bit for bit.
+ *   PRCG_BATCH_FUSION_AUTO  the autotuner times both (default);
+ *   PRCG_BATCH_FUSION_OFF   three launches per iteration;
+ *   PRCG_BATCH_FUSION_ON    fused only: where no group table allows it, a
+ *                           solve with PR-CG or M-CG fails with PRCG_EINVAL
+ *                           unless the mode is PRCG_BATCH_PERSISTENT. */
+typedef enum {
+    PRCG_BATCH_FUSION_AUTO = 0,
+    PRCG_BATCH_FUSION_OFF = 1,
+    PRCG_BATCH_FUSION_ON = 2
+} prcg_batch_fusion_t;
+
+/* Request a fusion setting (PRCG_BATCH_FUSION_*) for later solves; forgets
+ * the lockstep group size chosen before.  PRCG_EINVAL for an unknown
+ * setting. */
+prcg_status prcg_batch_set_fusion(prcg_batch B, int32_t fusion);
 
 /* Request a mode (PRCG_BATCH_*) for later solves; forgets earlier choices.
  * PRCG_EINVAL for an unknown mode. */

@@ -53,7 +53,19 @@ struct GroupView {
     int64_t ngroups;
     int32_t* gdone;            // [ngroups]: 1 once the group's system has finished
     int32_t spw;               // slices per wavefront (2, 4 or 8): groups hold kWaves spw slices
+    int32_t uwidth;            // every group uniform: 3, 5 or 7, the least at or above the widest; else 0
 };
+
+// The lockstep vectors one fused iteration reads or writes besides x.
+struct LsVecs {
+    double* r;
+    double* p;
+    double* s;
+};
+// Largest stencil span (largest minus smallest column offset of a group,
+// offset 0 included) of a table whose iterations may run fused: the window
+// of p' one workgroup holds in LDS is at most the group's rows plus this.
+constexpr int kFuseSpan = 1536;
 
 // Lockstep PR-CG / M-CG (variant kPR or kM): the initialisation (three
 // launches), then `iterations` iterations of three launches each and the
@@ -62,9 +74,13 @@ struct GroupView {
 hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const Vecs& v, const double* b, State* S,
                                 double* P, double tol, int maxit, int variant, int pre, int32_t* iters,
                                 int32_t* status, hipStream_t st);
+// fused: each iteration as k_ls_fused and the stage 2 (two launches; no
+// preconditioner, uniform groups (uwidth > 0) of span at most kFuseSpan, 2 or 4 slices per wavefront, an even number of iterations:
+// r, p and s alternate between (v.r, v.p, v.s) and (v.w, v.u, v.st), and the
+// initialisation leaves them in the first).
 hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, const Vecs& v, State* S, double* P,
-                                      int iterations, int variant, int pre, int32_t* iters, int32_t* status,
-                                      int32_t* active, hipStream_t st);
+                                      int iterations, int variant, int pre, bool fused, int32_t* iters,
+                                      int32_t* status, int32_t* active, hipStream_t st);
 
 // Reset the queue and launch the persistent kernel (nt threads per
 // workgroup: 256, 512 or 1024; grid workgroups; q = 1 or 2 slices

@@ -375,11 +375,13 @@ __global__ void k_batch_reset(int32_t* queue) { *queue = 0; }
 // are skipped).  Columns are clamped into the system's rows [lo, hi] as in
 // sell_row, and each row's slots are summed in stored order from 0.0: the
 // same operands in the same order.  Calls f(i, row, y, x[row]) for the valid
-// rows in slice order.
+// rows in slice order.  The group's width wg may be below W (a kernel
+// compiled for the widest group of a table): slots wg .. W - 1 are skipped
+// by wavefront-uniform branches.
 constexpr int kLsRoundLoads = 20;  // value loads per round of uniform_group
 template <int W, int D0, int R, class Pre, class F>
-__device__ __forceinline__ void uniform_group(const SellView& A, const Group& G, const double* __restrict__ x,
-                                              Pre&& pre, F&& f)
+__device__ __forceinline__ void uniform_group(const SellView& A, const Group& G, const int wg,
+                                              const double* __restrict__ x, Pre&& pre, F&& f)
 {
     constexpr int RR = W * R <= kLsRoundLoads ? R : (W * R / 2 <= kLsRoundLoads ? R / 2 : 1);
     constexpr bool SHIFT = D0 >= 1 && D0 + 1 < W;
@@ -404,7 +406,8 @@ __device__ __forceinline__ void uniform_group(const SellView& A, const Group& G,
             valid[j] = sl < G.nsl && local < G.nrows;
             row[j] = G.row0 + min(local, G.nrows - 1);
 #pragma unroll
-            for (int u = 0; u < W; ++u) a[j][u] = vb[(int64_t)(slc * W + u) * kSlice];
+            for (int u = 0; u < W; ++u)
+                if (u < wg) a[j][u] = vb[(int64_t)(slc * wg + u) * kSlice];
             xs[j] = x[row[j]];
             if constexpr (SHIFT) {
                 // the entries next to the slice, clamped into the system
@@ -419,7 +422,7 @@ __device__ __forceinline__ void uniform_group(const SellView& A, const Group& G,
         for (int j = 0; j < RR; ++j) {
 #pragma unroll
             for (int u = 0; u < W; ++u) {
-                if (!local_slot(u)) g[j][u] = x[min(max(row[j] + o[u], G.lo), G.hi)];
+                if (u < wg && !local_slot(u)) g[j][u] = x[min(max(row[j] + o[u], G.lo), G.hi)];
             }
         }
 #pragma unroll
@@ -435,7 +438,13 @@ __device__ __forceinline__ void uniform_group(const SellView& A, const Group& G,
             }
             double y = 0.0;
 #pragma unroll
-            for (int u = 0; u < W; ++u) y = fma(a[j][u], g[j][u], y);
+            for (int u = 0; u < W; ++u)
+                if (u < wg) y = fma(a[j][u], g[j][u], y);
+            // y in a register here, outside the valid rows' branch: otherwise
+            // the compiler moves a slice's loads into that branch, behind
+            // the wait for the cross-lane moves, and they no longer overlap
+            // with the other slices' loads
+            asm volatile("" : "+v"(y));
             if (valid[j]) f(i0 + j, row[j], y, xs[j]);
         }
     }
@@ -451,7 +460,10 @@ constexpr int kLockstepSpmvWaves = 4;
 // PHASE 0: the same product for an iteration of a system still running.
 // The group's slices go through sys_spmv (two slices per wavefront with
 // their loads in flight together).
-template <bool PRE, int PHASE, int SPW>
+// UW > 0: every group of the table is uniform, of width at most UW (the
+// kernel then holds that one product and needs fewer registers, so more
+// workgroups fit on a compute unit).
+template <bool PRE, int PHASE, int SPW, int UW = 0>
 __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpmvWaves) void k_ls_spmv(BatchView B, GroupView gv, const State* __restrict__ S, Vecs v,
                                                     const double* __restrict__ b, double* __restrict__ P)
 {
@@ -492,9 +504,10 @@ __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpm
         }
     };
     const double* __restrict__ xin = PHASE == 1 ? v.x : p;
-    if (G.off >= 0) {
-        constexpr int R = SPW;
-        double e0[R], e1[R], e2[R], e3[R];
+    constexpr int R = SPW;
+    double e0[R], e1[R], e2[R], e3[R];
+    // the product of a uniform group
+    auto uniform_product = [&]() {
         auto pre = [&](int i, int row) {
             if constexpr (PHASE == 1) {
                 e0[i] = b[row];
@@ -514,21 +527,31 @@ __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpm
         // -1 and +1, take the neighbours from the lanes
         auto go = [&](auto Wc) {
             constexpr int W = decltype(Wc)::value;
+            const int wg = UW > 0 ? G.width : W;
             if (W >= 3 && (G.flags & kGroupShift) && G.diag == W / 2)
-                uniform_group<W, W / 2, R>(B.A, G, xin, pre, f);
+                uniform_group<W, W / 2, R>(B.A, G, wg, xin, pre, f);
             else
-                uniform_group<W, -1, R>(B.A, G, xin, pre, f);
+                uniform_group<W, -1, R>(B.A, G, wg, xin, pre, f);
         };
-        switch (G.width) {
-        case 1: go(std::integral_constant<int, 1>{}); break;
-        case 2: go(std::integral_constant<int, 2>{}); break;
-        case 3: go(std::integral_constant<int, 3>{}); break;
-        case 4: go(std::integral_constant<int, 4>{}); break;
-        case 5: go(std::integral_constant<int, 5>{}); break;
-        case 6: go(std::integral_constant<int, 6>{}); break;
-        case 7: go(std::integral_constant<int, 7>{}); break;
-        default: go(std::integral_constant<int, kUniformMaxWidth>{}); break;
+        if constexpr (UW > 0) {
+            go(std::integral_constant<int, UW>{});
+        } else {
+            switch (G.width) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            case 4: go(std::integral_constant<int, 4>{}); break;
+            case 5: go(std::integral_constant<int, 5>{}); break;
+            case 6: go(std::integral_constant<int, 6>{}); break;
+            case 7: go(std::integral_constant<int, 7>{}); break;
+            default: go(std::integral_constant<int, kUniformMaxWidth>{}); break;
+            }
         }
+    };
+    if constexpr (UW > 0) {
+        uniform_product();
+    } else if (G.off >= 0) {
+        uniform_product();
     } else {
         sys_spmv<kBlock, 1, 2>(B, G.slice0, G.slice0 + G.nsl, G.lo, G.hi, xin, nullptr,
                             [&](int64_t row, double y0, double) {
@@ -576,6 +599,107 @@ __global__ __launch_bounds__(kBlock) void k_ls_update(GroupView gv, const State*
         r[i] = rn;
         if (PRE) rt[i] = rtn;
         p[i] = fma(beta, pi, rtn);
+    }
+}
+
+// One lockstep iteration of a uniform group with the update and the product
+// in one pass (PR-CG, M-CG without a preconditioner).  k_ls_update followed
+// by k_ls_spmv moves ten vector words per row (x, r, p, s read; x, r, p
+// written; p, r read again; s written); this kernel moves eight (x, r, p, s
+// read; x, r', p', s' written).  The product s' = A p' needs p' at every
+// column the group's rows reach, which extends past the group by the
+// stencil's span (within the system): the workgroup recomputes p' there from
+// r, s and p, which its neighbouring groups read as their own rows at about
+// the same time (the workgroup-to-group map keeps neighbouring groups on one
+// XCD, so these reads are served by its L2).  Reads r, p, s from `in` and
+// writes r', p', s' to `out`: other workgroups still read the old values.
+// x is updated in place.  Every row's arithmetic and the order of every sum
+// are those of k_ls_update then k_ls_spmv<false, 0, SPW>: the results agree
+// bit for bit.
+//   window: LDS, p' at the rows [wlo, whi] (the clamped columns of the
+//           group's rows); then r' at the group's own rows.
+template <int SPW, int W>
+__global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, const State* __restrict__ S,
+                                                     double* __restrict__ x, LsVecs in, LsVecs out,
+                                                     double* __restrict__ P)
+{
+    extern __shared__ double window[];
+    __shared__ double lds[kWaves * 5];
+    const int64_t gp = gridDim.x;  // a multiple of 8
+    const int64_t g = (blockIdx.x % 8) * (gp / 8) + blockIdx.x / 8;
+    if (g >= gv.ngroups || gv.gdone[g]) return;  // the whole workgroup
+    const Group G = gv.grp[g];
+    const double alpha = S[G.sys].alpha, beta = S[G.sys].beta;
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    // the window holds the group's own rows and every column they reach;
+    // slots wg .. W - 1 (a group narrower than the table's widest) are
+    // skipped by wavefront-uniform branches
+    const int wg = G.width;
+    int o[W];
+    int omin = 0, omax = 0;
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        o[u] = u < wg ? G.o[u] : 0;
+        omin = min(omin, o[u]);
+        omax = max(omax, o[u]);
+    }
+    const int last = G.row0 + G.nrows - 1;
+    const int wlo = min(max(G.row0 + omin, G.lo), G.hi);
+    const int whi = max(min(last + omax, G.hi), G.lo);
+    double* __restrict__ rown = window + (whi - wlo + 1);  // r' of the group's rows
+    // the product's values first: they do not depend on the update
+    const double* __restrict__ vb = B.A.val + (int64_t)G.vrow * kSlice + lane;
+    double a[SPW][W];
+    int row[SPW];
+    bool valid[SPW];
+#pragma unroll
+    for (int j = 0; j < SPW; ++j) {
+        const int sl = w + kWaves * j;
+        const int slc = min(sl, G.nsl - 1);
+        const int local = slc * kSlice + lane;
+        valid[j] = sl < G.nsl && local < G.nrows;
+        row[j] = G.row0 + min(local, G.nrows - 1);
+#pragma unroll
+        for (int u = 0; u < W; ++u)
+            if (u < wg) a[j][u] = vb[(int64_t)(slc * wg + u) * kSlice];
+    }
+    // p' over the window (r' and x as well at the group's own rows)
+#pragma unroll 4
+    for (int i = wlo + (int)threadIdx.x; i <= whi; i += kBlock) {
+        const double si = in.s[i], pi = in.p[i], ri = in.r[i];
+        const double rn = fma(-alpha, si, ri);
+        const double pn = fma(beta, pi, rn);
+        window[i - wlo] = pn;
+        if (i >= G.row0 && i <= last) {
+            x[i] = fma(alpha, pi, x[i]);
+            out.r[i] = rn;
+            out.p[i] = pn;
+            rown[i - G.row0] = rn;
+        }
+    }
+    __syncthreads();
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < SPW; ++j) {
+        double y = 0.0;
+#pragma unroll
+        for (int u = 0; u < W; ++u)
+            if (u < wg) y = fma(a[j][u], window[min(max(row[j] + o[u], G.lo), G.hi) - wlo], y);
+        if (valid[j]) {
+            const double pi = window[row[j] - wlo], ri = rown[row[j] - G.row0];
+            out.s[row[j]] = y;
+            q[0] = fma(pi, y, q[0]);
+            q[1] = fma(ri, y, q[1]);
+            q[2] = fma(y, y, q[2]);
+            q[3] = fma(ri, ri, q[3]);
+        }
+    }
+    block_sum<5, kWaves>(q, lds);
+    if (threadIdx.x == 0) {
+        const int64_t ng = gv.ngroups;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) P[i * ng + g] = q[i];
     }
 }
 
@@ -726,11 +850,40 @@ hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const V
 }
 
 hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, const Vecs& v, State* S, double* P,
-                                      int iterations, int variant, int pre, int32_t* iters, int32_t* status,
-                                      int32_t* active, hipStream_t st)
+                                      int iterations, int variant, int pre, bool fused, int32_t* iters,
+                                      int32_t* status, int32_t* active, hipStream_t st)
 {
     const int form = nu_form(variant);
     const dim3 grid((unsigned)gv.ngroups), nsys((unsigned)B.nsys), blk(kBlock);
+    if (fused) {
+        if (pre || iterations % 2 != 0 || (gv.spw != 2 && gv.spw != 4) ||
+            (gv.uwidth != 3 && gv.uwidth != 5 && gv.uwidth != 7))
+            return hipErrorInvalidValue;
+        const dim3 fgrid((unsigned)((gv.ngroups + 7) / 8 * 8));
+        const size_t lds = sizeof(double) * (2 * (size_t)kWaves * gv.spw * kSlice + kFuseSpan);
+        const LsVecs A{v.r, v.p, v.s}, A2{v.w, v.u, v.st};
+        auto go = [&](auto SPWc, auto Wc) -> hipError_t {
+            constexpr int SPW = decltype(SPWc)::value, W = decltype(Wc)::value;
+            for (int k = 0; k < iterations; ++k) {
+                hipLaunchKernelGGL((k_ls_fused<SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, k % 2 ? A2 : A,
+                                   k % 2 ? A : A2, P);
+                hipLaunchKernelGGL((k_ls_finish<false, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form,
+                                   iters, status);
+            }
+            return hipGetLastError();
+        };
+        auto gow = [&](auto SPWc) -> hipError_t {
+            switch (gv.uwidth) {
+            case 3: return go(SPWc, std::integral_constant<int, 3>{});
+            case 5: return go(SPWc, std::integral_constant<int, 5>{});
+            default: return go(SPWc, std::integral_constant<int, 7>{});
+            }
+        };
+        hipError_t e = gv.spw == 2 ? gow(std::integral_constant<int, 2>{}) : gow(std::integral_constant<int, 4>{});
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_ls_count, dim3(1), blk, 0, st, S, B.nsys, active);
+        return hipGetLastError();
+    }
     hipError_t e = with_spw(gv, [&](auto SPWc) -> hipError_t {
         constexpr int SPW = decltype(SPWc)::value;
         for (int k = 0; k < iterations; ++k) {
@@ -741,7 +894,12 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
                                    iters, status);
             } else {
                 hipLaunchKernelGGL((k_ls_update<false>), grid, blk, 0, st, gv, S, v);
-                hipLaunchKernelGGL((k_ls_spmv<false, 0, SPW>), grid, blk, 0, st, B, gv, S, v, nullptr, P);
+                switch (gv.uwidth) {
+                case 3: hipLaunchKernelGGL((k_ls_spmv<false, 0, SPW, 3>), grid, blk, 0, st, B, gv, S, v, nullptr, P); break;
+                case 5: hipLaunchKernelGGL((k_ls_spmv<false, 0, SPW, 5>), grid, blk, 0, st, B, gv, S, v, nullptr, P); break;
+                case 7: hipLaunchKernelGGL((k_ls_spmv<false, 0, SPW, 7>), grid, blk, 0, st, B, gv, S, v, nullptr, P); break;
+                default: hipLaunchKernelGGL((k_ls_spmv<false, 0, SPW>), grid, blk, 0, st, B, gv, S, v, nullptr, P); break;
+                }
                 hipLaunchKernelGGL((k_ls_finish<false, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form,
                                    iters, status);
             }

@@ -221,6 +221,7 @@ struct prcg_batch_s {
     int tuned_q[3] = {0, 0, 0};
     // configuration fixed by prcg_batch_set_config (0: autotuned)
     int force_nt = 0, force_per_cu = 0, force_q = 0, force_group = 0;
+    int force_fusion = PRCG_BATCH_FUSION_AUTO;
     hipGraphExec_t graph[kNumVariants] = {};
     double graph_tol[kNumVariants] = {};
     int32_t graph_maxit[kNumVariants] = {};
@@ -235,10 +236,13 @@ struct prcg_batch_s {
         int64_t* sys_grp0 = nullptr;
         int32_t* gdone = nullptr;
         int32_t spw = 0;
+        int32_t uwidth = 0;  // every group uniform: 3, 5 or 7 slots, the least at or above the widest; else 0
+        bool fuse_ok = false;  // iterations may run fused (launch_lockstep_iterations)
     };
     static constexpr int kTables = 3;
     GroupTable tab[kTables];
     int ls_table = -1;         // table in use (-1: not tuned yet)
+    bool ls_fused = false;     // its iterations run fused
     State* lstate = nullptr;
     double* lpart = nullptr;   // 6 * the largest table's ngroups
     int32_t* lactive = nullptr;
@@ -250,7 +254,7 @@ struct prcg_batch_s {
 
     GroupView groups(int t) const
     {
-        return GroupView{tab[t].grp, tab[t].sys_grp0, tab[t].ngroups, tab[t].gdone, tab[t].spw};
+        return GroupView{tab[t].grp, tab[t].sys_grp0, tab[t].ngroups, tab[t].gdone, tab[t].spw, tab[t].uwidth};
     }
 
     Vecs vecs_view() const
@@ -1197,6 +1201,24 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         T.spw = spw;
         T.ngroups = sys_grp0[t][nsys];
         for (const Group& G : grp[t]) T.uniform_groups += G.off >= 0;
+        // every group uniform: the lockstep product (and the fused
+        // iteration) launch the kernel compiled for the least of 3, 5, 7
+        // slots at or above the widest group
+        int32_t wmax = 0;
+        for (const Group& G : grp[t]) wmax = std::max(wmax, G.width);
+        T.uwidth = 0;
+        if (T.ngroups > 0 && T.uniform_groups == T.ngroups)
+            T.uwidth = wmax <= 3 ? 3 : wmax <= 5 ? 5 : wmax <= 7 ? 7 : 0;
+        T.fuse_ok = T.uwidth > 0 && (spw == 2 || spw == 4);
+        for (const Group& G : grp[t]) {
+            if (!T.fuse_ok) break;
+            int omin = 0, omax = 0;  // the span includes offset 0 (the group's own rows)
+            for (int u = 0; u < G.width; ++u) {
+                omin = std::min(omin, G.o[u]);
+                omax = std::max(omax, G.o[u]);
+            }
+            if (omax - omin > kFuseSpan) T.fuse_ok = false;
+        }
         max_groups = std::max(max_groups, T.ngroups);
         BTRY(hipMalloc(&T.grp, sizeof(Group) * T.ngroups));
         BTRY(hipMalloc(&T.sys_grp0, sizeof(int64_t) * (nsys + 1)));
@@ -1265,7 +1287,8 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
             e = hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return e;
             hipError_t e1 = launch_lockstep_iterations(view, gv, vv, B->lstate, B->lpart, kLockstepChunk, v,
-                                                       A->precond, B->iters, B->status, B->lactive, A->capture);
+                                                       A->precond, B->ls_fused, B->iters, B->status, B->lactive,
+                                                       A->capture);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(A->capture, &g);
             hipError_t e3 = (e1 == hipSuccess && e2 == hipSuccess) ? hipGraphInstantiate(&B->ls_graph[v], g, nullptr,
@@ -1372,14 +1395,22 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
         }
     }
     // Lockstep group size (PR-CG and M-CG): groups of 8, 16 and 32 slices,
-    // each timed on the initialisation and 32 iterations of this batch
-    // (tol = 0); fixed by prcg_batch_set_config.
+    // each with three launches per iteration and, where the table allows and
+    // no preconditioner is applied, with the fused iteration; each candidate
+    // timed on the initialisation and 32 iterations of this batch (tol = 0).
+    // The group size is fixed by prcg_batch_set_config, the fusion by
+    // prcg_batch_set_fusion.
     if (kind == 1 && B->mode_req != PRCG_BATCH_PERSISTENT && B->ls_table < 0) {
         float best = 1e30f;
+        int ncand = 0;
         for (int t = 0; t < prcg_batch_s::kTables; ++t) {
             if (B->force_group && kWaves * B->tab[t].spw != B->force_group) continue;
-            float ms = 0.f;
-            if (!B->force_group) {
+            for (int f = 0; f < 2; ++f) {
+                const bool fused = f == 1;
+                if (fused && (A->precond || !B->tab[t].fuse_ok || B->force_fusion == PRCG_BATCH_FUSION_OFF)) continue;
+                if (!fused && B->force_fusion == PRCG_BATCH_FUSION_ON) continue;
+                ++ncand;
+                float ms = 0.f;
                 const GroupView gv = B->groups(t);
                 prcg_status s = elapsed(
                     [&] {
@@ -1388,7 +1419,7 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
                                                             B->status, st);
                         if (e == hipSuccess)
                             e = launch_lockstep_iterations(view, gv, vv, B->lstate, B->lpart, 32, v, A->precond,
-                                                           B->iters, B->status, B->lactive, st);
+                                                           fused, B->iters, B->status, B->lactive, st);
                         return e;
                     },
                     ms);
@@ -1396,11 +1427,16 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
                     release_events();
                     return s;
                 }
+                if (ms < best) {
+                    best = ms;
+                    B->ls_table = t;
+                    B->ls_fused = fused;
+                }
             }
-            if (ms < best) {
-                best = ms;
-                B->ls_table = t;
-            }
+        }
+        if (ncand == 0) {
+            release_events();
+            return fail(PRCG_EINVAL, "no lockstep group table allows the fused iteration with this configuration");
         }
         for (auto& g : B->ls_graph) {
             if (g) (void)hipGraphExecDestroy(g);
@@ -1535,7 +1571,26 @@ prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props*
     p.group_slices = t >= 0 ? kWaves * B->tab[t].spw : 0;
     p.groups = t >= 0 ? B->tab[t].ngroups : 0;
     p.uniform_groups = t >= 0 ? B->tab[t].uniform_groups : 0;
+    p.fused = t >= 0 && B->ls_fused ? 1 : 0;
     *props = p;
+    return PRCG_OK;
+}
+
+prcg_status prcg_batch_set_fusion(prcg_batch B, int32_t fusion)
+{
+    if (!B) return fail(PRCG_EINVAL, "null batch");
+    if (fusion < PRCG_BATCH_FUSION_AUTO || fusion > PRCG_BATCH_FUSION_ON)
+        return fail(PRCG_EINVAL, "unknown fusion setting");
+    HIP_TRY(hipSetDevice(B->A->device));
+    HIP_TRY(hipStreamSynchronize(B->A->stream));
+    B->force_fusion = fusion;
+    B->ls_table = -1;
+    B->ls_fused = false;
+    for (auto& m : B->mode) m = 0;
+    for (auto& g : B->ls_graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     return PRCG_OK;
 }
 

@@ -31,12 +31,13 @@ KERNELS = {"fused": 0, "two_pass": 1, "two_pass_stage2": 2, "textbook": 3, "two_
            "two_pass_redundant": 5, "auto": 6}
 OPT_KERNELS, OPT_GRID = 0, 1
 BATCH_MODES = {"auto": 0, "persistent": 1, "lockstep": 2}
+BATCH_FUSION = {"auto": 0, "off": 1, "on": 2}
 
 EXPORTED = ("prcg_create_csr", "prcg_set_values", "prcg_set_option", "prcg_set_stream", "prcg_spmv", "prcg_solve",
             "prcg_time_kernels", "prcg_get_props", "prcg_create_batch", "prcg_solve_batched",
             "prcg_adjoint", "prcg_destroy", "prcg_batch_destroy", "prcg_last_error", "prcg_batch_config",
             "prcg_batch_set_mode", "prcg_batch_mode", "prcg_solve_noalloc", "prcg_batch_set_config",
-            "prcg_batch_get_props")
+            "prcg_batch_get_props", "prcg_batch_set_fusion")
 NOALLOC_MAX_ITERS = 65536  # PRCG_NOALLOC_MAX_ITERS
 
 
@@ -63,7 +64,7 @@ class prcg_batch_props(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("stored_entries", ctypes.c_int64), ("matrix_bytes", ctypes.c_int64),
                 ("groups", ctypes.c_int64), ("uniform_groups", ctypes.c_int64), ("nsys", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("threads", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("slices_in_flight", ctypes.c_int32), ("group_slices", ctypes.c_int32)]
+                ("slices_in_flight", ctypes.c_int32), ("group_slices", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "prcg_batch_mode": (i32, [_VP, i32, ctypes.POINTER(i32)]),
         "prcg_batch_set_config": (i32, [_VP, i32, i32, i32, i32]),
         "prcg_batch_get_props": (i32, [_VP, i32, ctypes.POINTER(prcg_batch_props)]),
+        "prcg_batch_set_fusion": (i32, [_VP, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -197,6 +199,10 @@ def prcg_batch_set_mode(B, mode):
 
 def prcg_batch_set_config(B, threads=0, per_cu=0, slices_in_flight=0, group_slices=0):
     _check(load_library().prcg_batch_set_config(B, threads, per_cu, slices_in_flight, group_slices))
+
+
+def prcg_batch_set_fusion(B, fusion):
+    _check(load_library().prcg_batch_set_fusion(B, fusion))
 
 
 def prcg_batch_get_props(B, variant) -> prcg_batch_props:
@@ -401,6 +407,11 @@ class Batch:
     def set_config(self, threads: int = 0, per_cu: int = 0, slices_in_flight: int = 0, group_slices: int = 0):
         """Fix parts of the configuration (0: left to the autotuner)."""
         prcg_batch_set_config(self.handle, threads, per_cu, slices_in_flight, group_slices)
+
+    def set_fusion(self, fusion: str):
+        """'auto' (timed by the autotuner), 'off' (three launches per lockstep
+        iteration) or 'on' (the fused iteration only)."""
+        prcg_batch_set_fusion(self.handle, BATCH_FUSION[fusion])
 
     def props(self, variant: str = "pr") -> dict:
         """Storage and the configuration in use for a variant."""

@@ -64,6 +64,8 @@ def test_binding_constants_match_the_header():
         assert variants["PRCG_" + key.upper()] == code, key
     assert header_enum("prcg_precond") == {"PRCG_PRECOND_" + k.upper(): v for k, v in prcg.PRECONDS.items()}
     assert header_enum("prcg_batch_mode_t") == {"PRCG_BATCH_" + k.upper(): v for k, v in prcg.BATCH_MODES.items()}
+    assert header_enum("prcg_batch_fusion_t") == {"PRCG_BATCH_FUSION_" + k.upper(): v
+                                                  for k, v in prcg.BATCH_FUSION.items()}
 
 
 def header_struct(name):

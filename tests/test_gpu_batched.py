@@ -194,8 +194,8 @@ def batch512():
     return P.config4()
 
 
-@pytest.mark.parametrize("mode", ["persistent", "lockstep"])
-def test_full_batched_workload_sampled(prcg, batch512, mode):
+@pytest.mark.parametrize("mode,fusion", [("persistent", "auto"), ("lockstep", "off"), ("lockstep", "on")])
+def test_full_batched_workload_sampled(prcg, batch512, mode, fusion):
     """All 512 systems (n from 1k to 64k) in one solve; the oracle checks the
     largest, the smallest and two more systems; every system's true residual
     is checked on the host."""
@@ -203,8 +203,11 @@ def test_full_batched_workload_sampled(prcg, batch512, mode):
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
     B.set_mode(mode)
+    B.set_fusion(fusion)
     x, iters, status = B.solve(b, "pr", 1e-10, 20000)
     assert B.mode("pr") == mode
+    if mode == "lockstep":
+        assert B.props("pr")["fused"] == (fusion == "on")
     x = x.cpu().numpy()
     assert all(st == "ok" for st in status)
     sizes = np.diff(offs)
@@ -223,12 +226,13 @@ def test_full_batched_workload_sampled(prcg, batch512, mode):
         assert np.linalg.norm(res[sl]) <= 2e-10 * np.linalg.norm(b[sl]), s
 
 
-@pytest.mark.parametrize("mode,config", [("persistent", "256,1"), ("persistent", "512,2"), ("lockstep", None)])
+@pytest.mark.parametrize("mode,config", [("persistent", "256,1"), ("persistent", "512,2"), ("lockstep", "off"),
+                                         ("lockstep", "on")])
 def test_nan_system_leaves_neighbours_alone(prcg, mode, config, monkeypatch):
     """A system whose right-hand side holds NaN breaks down on its own: the
     zero slots of its neighbours' boundary rows read only their own system's
     vectors, so every other system still matches the oracle."""
-    if config:
+    if mode == "persistent":
         monkeypatch.setenv("PRCG_BATCH_CONFIG", config)
     A, offs, b, mats, bs = small_batch(6)
     b = b.copy()
@@ -240,6 +244,8 @@ def test_nan_system_leaves_neighbours_alone(prcg, mode, config, monkeypatch):
     M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
     B = prcg.Batch(M, offs)
     B.set_mode(mode)
+    if mode == "lockstep":
+        B.set_fusion(config)  # fused: the recomputed p' of the window reads the NaN system's rows only
     x, iters, status = B.solve(b, "pr", 1e-10, 5000)
     x = x.cpu().numpy()
     ref = oracle.solve(mats[bad].row_ptr, mats[bad].col_idx, mats[bad].values, bs[bad], "pr", "none", 1e-10, 5000)
@@ -317,3 +323,73 @@ def test_autotuned_configuration_is_reported(prcg):
     for bad in [(300, 0, 0, 0), (1024, 4, 0, 0), (0, 9, 0, 0), (0, 0, 3, 0), (0, 0, 0, 12)]:
         with pytest.raises(prcg.PrcgError):
             B.set_config(*bad)
+
+
+def stencil_batch():
+    """Systems whose row groups are all offset-aligned of width 5 (2D
+    5-point stencils, anisotropic and not): sizes from one partial slice to
+    about 6,000 rows, so groups end ragged and some systems hold one group."""
+    mats = [P.batch_system(s, 64, 6000)[0] for s in range(9)]
+    mats += [P.poisson2d(3), P.poisson2d(5, 7), P.aniso2d(40, 3, 0.01), P.poisson2d(70, 2)]
+    bs = [P.uniform_vector(A.n, 70 + s) for s, A in enumerate(mats)]
+    A, offs = P.block_diag(mats)
+    return A, offs, np.concatenate(bs), mats, bs
+
+
+@pytest.mark.parametrize("group_slices", [8, 16])
+@pytest.mark.parametrize("variant", ["pr", "m"])
+def test_fused_lockstep_equals_three_launches(prcg, group_slices, variant):
+    """The fused lockstep iteration (update and product in one launch, p'
+    recomputed past the group's edges) gives the bits of three launches per
+    iteration: from x0 = 0 to convergence, from x0 != 0, and for a maxit
+    that is not a multiple of the 16-iteration chunk; every system of the
+    fused run against the oracle."""
+    A, offs, b, mats, bs = stencil_batch()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    x0 = P.uniform_vector(A.n, 99)
+    runs = {}
+    for fusion in ("off", "on"):
+        B = prcg.Batch(M, offs)
+        B.set_config(0, 0, 0, group_slices)
+        B.set_mode("lockstep")
+        B.set_fusion(fusion)
+        out = [B.solve(b, variant, 1e-10, 5000), B.solve(b, variant, 1e-10, 5000, x0=x0),
+               B.solve(b, variant, 0.0, 23)]
+        p = B.props(variant)
+        assert p["fused"] == (fusion == "on") and p["group_slices"] == group_slices
+        assert p["uniform_groups"] == p["groups"]
+        runs[fusion] = [(x.cpu().numpy(), iters, status) for x, iters, status in out]
+        B.close()
+    for (xa, ia, sa), (xb, ib, sb) in zip(runs["off"], runs["on"]):
+        assert np.array_equal(xa, xb) and np.array_equal(ia, ib) and sa == sb
+    x, iters, status = runs["on"][0]
+    check_systems(x, iters, status, mats, bs, offs, variant, "none", 1e-10)
+    big = np.diff(offs) > 200  # the 9-row system terminates (exactly) sooner
+    assert np.all(runs["on"][2][1][big] == 23) and np.all(runs["on"][2][1] <= 23)
+
+
+def test_fusion_settings_are_checked(prcg):
+    """The fused iteration needs uniform groups and no preconditioner:
+    asking for it elsewhere fails with PRCG_EINVAL at the solve, as does an
+    unknown setting; 'auto' picks three launches there."""
+    A, offs, b, mats, bs = stencil_batch()
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
+    B = prcg.Batch(M, offs)
+    B.set_mode("lockstep")
+    B.set_fusion("on")
+    with pytest.raises(prcg.PrcgError):
+        B.solve(b, "pr", 1e-10, 5000)
+    B.set_fusion("auto")
+    x, iters, status = B.solve(b, "pr", 1e-10, 5000)
+    assert B.props("pr")["fused"] == 0
+    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", "jacobi", 1e-10)
+    mixed = [P.random_spd(900, 5.0, 3), P.batch_system(0, 64, 3000)[0]]
+    Am, offm = P.block_diag(mixed)
+    Mm = prcg.Matrix(Am.row_ptr, Am.col_idx, Am.values, "none")
+    Bm = prcg.Batch(Mm, offm)
+    Bm.set_mode("lockstep")
+    Bm.set_fusion("on")
+    with pytest.raises(prcg.PrcgError):
+        Bm.solve(P.uniform_vector(Am.n, 5), "pr", 1e-10, 5000)
+    with pytest.raises(prcg.PrcgError):
+        prcg.prcg_batch_set_fusion(Bm.handle, 3)
