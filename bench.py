@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--batched-config", default="",
                     help="threads,per_cu,slices_in_flight,group_slices fixed instead of autotuned "
                          "(0 leaves a part to the autotuner), so that profiled runs launch the same kernels")
+    ap.add_argument("--batched-fusion", default="auto", choices=("auto", "off", "on"),
+                    help="fused lockstep iterations: timed by the autotuner, never, or always")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the 512 one-at-a-time solves of the batched comparison (profiling runs)")
     ap.add_argument("--suite", action="store_true",
@@ -159,7 +161,7 @@ def device_facts(torch):
     return facts
 
 
-def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, config=""):
+def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, config="", fusion="auto"):
     """512 anisotropic systems in one batched solve (the mode the solver picks;
     both modes are timed) vs one prcg_solve per system."""
     A, offs, b, xs, eps = problems.config4()
@@ -167,6 +169,7 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, con
     B = prcg.Batch(M, offs)
     if config:
         B.set_config(*[int(v) for v in config.split(",")])
+    B.set_fusion(fusion)
     bt = torch.as_tensor(b, device="cuda")
     x, iters, status = B.solve(bt, "pr", 1e-10, 20000)  # includes the autotuner's trial runs
     assert all(st == "ok" for st in status)
@@ -465,7 +468,7 @@ def main():
     if args.batched_only:
         calibration_copy(torch)
         print(json.dumps(batched_section(torch, prcg, problems, traffic, args.batched_reps, not args.no_sequential,
-                                         args.batched_config)),
+                                         args.batched_config, args.batched_fusion)),
               flush=True)
         return
     if args.kernels_only and args.workload == "varcoef27_160":

@@ -54,6 +54,7 @@ struct GroupView {
     int32_t* gdone;            // [ngroups]: 1 once the group's system has finished
     int32_t spw;               // slices per wavefront (2, 4 or 8): groups hold kWaves spw slices
     int32_t uwidth;            // every group uniform: 3, 5 or 7, the least at or above the widest; else 0
+    int32_t* ticket;           // [nsys]: the fused iteration's stage-2 tickets (0 between launches)
 };
 
 // The lockstep vectors one fused iteration reads or writes besides x.
@@ -74,7 +75,8 @@ constexpr int kFuseSpan = 1536;
 hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const Vecs& v, const double* b, State* S,
                                 double* P, double tol, int maxit, int variant, int pre, int32_t* iters,
                                 int32_t* status, hipStream_t st);
-// fused: each iteration as k_ls_fused and the stage 2 (two launches; no
+// fused: each iteration as one launch of k_ls_fused, whose last workgroup
+// of each system takes the system's stage 2 (no
 // preconditioner, uniform groups (uwidth > 0) of span at most kFuseSpan, 2 or 4 slices per wavefront, an even number of iterations:
 // r, p and s alternate between (v.r, v.p, v.s) and (v.w, v.u, v.st), and the
 // initialisation leaves them in the first).

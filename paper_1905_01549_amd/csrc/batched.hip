@@ -602,6 +602,40 @@ __global__ __launch_bounds__(kBlock) void k_ls_update(GroupView gv, const State*
     }
 }
 
+// Stage 2 and the scalar step of one running system by one workgroup:
+// thread t adds the partials of groups g0 + t, g0 + t + kBlock, ... in that
+// order from 0.0, the thread sums go through block_sum, then the scalar
+// step; the groups' done flags are set when the system ends.
+// COHERENT: the partials were written in the same launch, by workgroups on
+// other XCDs, with agent-scope atomic stores; they are read the same way.
+template <bool PRE, bool COHERENT = false>
+__device__ __forceinline__ void finish_system(const GroupView& gv, State* __restrict__ S,
+                                              const double* __restrict__ P, int sys, int form,
+                                              int32_t* __restrict__ iters, int32_t* __restrict__ status)
+{
+    __shared__ double lds[kWaves * 5];
+    State st = load_state(S + sys);
+    if (st.done) return;
+    const int64_t g0 = gv.sys_grp0[sys], g1 = gv.sys_grp0[sys + 1], ng = gv.ngroups;
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            t[i] += COHERENT ? __hip_atomic_load(P + i * ng + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : P[i * ng + g];
+    }
+    block_sum<5, kWaves>(t, lds);
+    step_one_reduction(st, t, PRE, form, nullptr, false);
+    if (threadIdx.x == 0) {
+        store_state(S + sys, st);
+        iters[sys] = st.k < 0 ? 0 : st.k;
+        status[sys] = st.status;
+    }
+    if (st.done) {
+        for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) gv.gdone[g] = 1;
+    }
+}
+
 // One lockstep iteration of a uniform group with the update and the product
 // in one pass (PR-CG, M-CG without a preconditioner).  k_ls_update followed
 // by k_ls_spmv moves ten vector words per row (x, r, p, s read; x, r, p
@@ -614,14 +648,19 @@ __global__ __launch_bounds__(kBlock) void k_ls_update(GroupView gv, const State*
 // XCD, so these reads are served by its L2).  Reads r, p, s from `in` and
 // writes r', p', s' to `out`: other workgroups still read the old values.
 // x is updated in place.  Every row's arithmetic and the order of every sum
-// are those of k_ls_update then k_ls_spmv<false, 0, SPW>: the results agree
-// bit for bit.
+// are those of k_ls_update then k_ls_spmv<false, 0, SPW>, and the last
+// workgroup of each system (by a ticket) then runs the stage 2 and scalar
+// step of k_ls_finish: the results agree bit for bit with those three
+// launches.  (The other workgroups of the system have read alpha and beta
+// before they took their tickets, so the state may change then.)
 //   window: LDS, p' at the rows [wlo, whi] (the clamped columns of the
 //           group's rows); then r' at the group's own rows.
+constexpr int kWindowRows = 4;  // window rows per thread whose loads k_ls_fused issues together
 template <int SPW, int W>
-__global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, const State* __restrict__ S,
+__global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, State* __restrict__ S,
                                                      double* __restrict__ x, LsVecs in, LsVecs out,
-                                                     double* __restrict__ P)
+                                                     double* __restrict__ P, int form, int32_t* __restrict__ iters,
+                                                     int32_t* __restrict__ status)
 {
     extern __shared__ double window[];
     __shared__ double lds[kWaves * 5];
@@ -662,20 +701,42 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
         row[j] = G.row0 + min(local, G.nrows - 1);
 #pragma unroll
         for (int u = 0; u < W; ++u)
-            if (u < wg) a[j][u] = vb[(int64_t)(slc * wg + u) * kSlice];
+            if (u < wg) a[j][u] = __builtin_nontemporal_load(&vb[(int64_t)(slc * wg + u) * kSlice]);
     }
-    // p' over the window (r' and x as well at the group's own rows)
-#pragma unroll 4
-    for (int i = wlo + (int)threadIdx.x; i <= whi; i += kBlock) {
-        const double si = in.s[i], pi = in.p[i], ri = in.r[i];
-        const double rn = fma(-alpha, si, ri);
-        const double pn = fma(beta, pi, rn);
-        window[i - wlo] = pn;
-        if (i >= G.row0 && i <= last) {
-            x[i] = fma(alpha, pi, x[i]);
-            out.r[i] = rn;
-            out.p[i] = pn;
-            rown[i - G.row0] = rn;
+    // p' over the window (r' and x as well at the group's own rows); the
+    // two buffer sets never overlap
+    const double* __restrict__ in_r = in.r;
+    const double* __restrict__ in_p = in.p;
+    const double* __restrict__ in_s = in.s;
+    double* __restrict__ out_r = out.r;
+    double* __restrict__ out_p = out.p;
+    double* __restrict__ out_s = out.s;
+    // kWindowRows rows per thread at a time: their loads are issued
+    // together (rows past the window load its last row and are skipped)
+    constexpr int U = kWindowRows;
+    for (int i0 = wlo + (int)threadIdx.x; i0 <= whi; i0 += U * kBlock) {
+        double sv[U], pv[U], rv[U], xv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = min(i0 + k * kBlock, whi);
+            sv[k] = in_s[i];
+            pv[k] = in_p[i];
+            rv[k] = in_r[i];
+            xv[k] = i >= G.row0 && i <= last ? x[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = i0 + k * kBlock;
+            if (i > whi) break;
+            const double rn = fma(-alpha, sv[k], rv[k]);
+            const double pn = fma(beta, pv[k], rn);
+            window[i - wlo] = pn;
+            if (i >= G.row0 && i <= last) {
+                __builtin_nontemporal_store(fma(alpha, pv[k], xv[k]), &x[i]);
+                __builtin_nontemporal_store(rn, &out_r[i]);
+                __builtin_nontemporal_store(pn, &out_p[i]);
+                rown[i - G.row0] = rn;
+            }
         }
     }
     __syncthreads();
@@ -688,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
             if (u < wg) y = fma(a[j][u], window[min(max(row[j] + o[u], G.lo), G.hi) - wlo], y);
         if (valid[j]) {
             const double pi = window[row[j] - wlo], ri = rown[row[j] - G.row0];
-            out.s[row[j]] = y;
+            __builtin_nontemporal_store(y, &out_s[row[j]]);
             q[0] = fma(pi, y, q[0]);
             q[1] = fma(ri, y, q[1]);
             q[2] = fma(y, y, q[2]);
@@ -696,11 +757,26 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
         }
     }
     block_sum<5, kWaves>(q, lds);
+    // The system's last workgroup to finish takes its stage 2 and scalar
+    // step.  The partials go out as agent-scope atomic stores (coherent
+    // across the XCDs' L2 caches) and thread 0 waits for them to complete
+    // before it takes its ticket, so the workgroup that draws the last
+    // ticket reads every partial of its system with agent-scope atomic
+    // loads; no fence has to write back an L2.
+    __shared__ int is_last;
+    const int sys = G.sys;
     if (threadIdx.x == 0) {
         const int64_t ng = gv.ngroups;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) P[i * ng + g] = q[i];
+        for (int i = 0; i < 5; ++i) __hip_atomic_store(P + i * ng + g, q[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        const int nsg = (int)(gv.sys_grp0[sys + 1] - gv.sys_grp0[sys]);
+        const int t = __hip_atomic_fetch_add(gv.ticket + sys, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = t == nsg - 1;
+        if (is_last) __hip_atomic_store(gv.ticket + sys, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
+    if (is_last) finish_system<false, true>(gv, S, P, sys, form, iters, status);
 }
 
 // Stage 2 and the scalar step of one system (one workgroup per system):
@@ -713,31 +789,27 @@ __global__ __launch_bounds__(kBlock) void k_ls_finish(BatchView B, GroupView gv,
                                                       int maxit, int form, int32_t* __restrict__ iters,
                                                       int32_t* __restrict__ status)
 {
-    constexpr int NV = INIT ? 6 : 5;
-    __shared__ double lds[kWaves * NV];
     const int sys = blockIdx.x;
-    State st;
-    if (INIT) {
-        st = State{};
+    if constexpr (!INIT) {
+        finish_system<PRE>(gv, S, P, sys, form, iters, status);
+    } else {
+        constexpr int NV = 6;
+        __shared__ double lds[kWaves * NV];
+        State st = State{};
         st.tol = tol;
         st.maxit = maxit;
         st.k = -1;
         st.status = kNotConverged;
-    } else {
-        st = load_state(S + sys);
-        if (st.done) return;
-    }
-    const int64_t g0 = gv.sys_grp0[sys], g1 = gv.sys_grp0[sys + 1], ng = gv.ngroups;
-    double t[NV];
+        const int64_t g0 = gv.sys_grp0[sys], g1 = gv.sys_grp0[sys + 1], ng = gv.ngroups;
+        double t[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) t[i] = 0.0;
-    for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) {
+        for (int i = 0; i < NV; ++i) t[i] = 0.0;
+        for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) t[i] += P[i * ng + g];
-    }
-    block_sum<NV, kWaves>(t, lds);
-    const double t5[5] = {t[0], t[1], t[2], t[3], t[4]};
-    if (INIT) {
+            for (int i = 0; i < NV; ++i) t[i] += P[i * ng + g];
+        }
+        block_sum<NV, kWaves>(t, lds);
+        const double t5[5] = {t[0], t[1], t[2], t[3], t[4]};
         st.bnorm = sqrt(t[NV - 1]);
         if (t[NV - 1] == 0.0) {
             for (int64_t i = B.sys_row0[sys] + threadIdx.x; i < B.sys_row0[sys + 1]; i += kBlock) x[i] = 0.0;
@@ -747,17 +819,14 @@ __global__ __launch_bounds__(kBlock) void k_ls_finish(BatchView B, GroupView gv,
         } else {
             step_one_reduction(st, t5, PRE, form, nullptr, false);
         }
-    } else {
-        step_one_reduction(st, t5, PRE, form, nullptr, false);
-    }
-    if (threadIdx.x == 0) {
-        store_state(S + sys, st);
-        iters[sys] = st.k < 0 ? 0 : st.k;
-        status[sys] = st.status;
-    }
-    // the groups' copies of the flag (the next kernels read them instead of
-    // the state, with no load before)
-    if (INIT || st.done) {
+        if (threadIdx.x == 0) {
+            store_state(S + sys, st);
+            iters[sys] = st.k < 0 ? 0 : st.k;
+            status[sys] = st.status;
+            gv.ticket[sys] = 0;  // the fused iteration's stage-2 ticket
+        }
+        // the groups' copies of the flag (the next kernels read them instead
+        // of the state, with no load before)
         for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) gv.gdone[g] = st.done;
     }
 }
@@ -866,9 +935,7 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
             constexpr int SPW = decltype(SPWc)::value, W = decltype(Wc)::value;
             for (int k = 0; k < iterations; ++k) {
                 hipLaunchKernelGGL((k_ls_fused<SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, k % 2 ? A2 : A,
-                                   k % 2 ? A : A2, P);
-                hipLaunchKernelGGL((k_ls_finish<false, false>), nsys, blk, 0, st, B, gv, S, P, v.x, 0.0, 0, form,
-                                   iters, status);
+                                   k % 2 ? A : A2, P, form, iters, status);
             }
             return hipGetLastError();
         };

@@ -246,6 +246,7 @@ struct prcg_batch_s {
     State* lstate = nullptr;
     double* lpart = nullptr;   // 6 * the largest table's ngroups
     int32_t* lactive = nullptr;
+    int32_t* lticket = nullptr;  // [nsys]: stage-2 tickets of the fused lockstep iteration
     int32_t* hactive = nullptr;  // pinned, two slots
     hipEvent_t lev[2] = {nullptr, nullptr};
     hipGraphExec_t ls_graph[kNumVariants] = {};
@@ -254,7 +255,8 @@ struct prcg_batch_s {
 
     GroupView groups(int t) const
     {
-        return GroupView{tab[t].grp, tab[t].sys_grp0, tab[t].ngroups, tab[t].gdone, tab[t].spw, tab[t].uwidth};
+        return GroupView{tab[t].grp, tab[t].sys_grp0, tab[t].ngroups, tab[t].gdone, tab[t].spw, tab[t].uwidth,
+                         lticket};
     }
 
     Vecs vecs_view() const
@@ -306,7 +308,7 @@ void free_batch(prcg_batch B)
     if (B->hactive) (void)hipHostFree(B->hactive);
     void* dev[] = {B->slice_row0, B->slice_nrows, B->sys_row0, B->sys_slice0, B->order, B->slice_ptr,
                    B->slice_meta, B->slice_shape, B->soff, B->scol, B->sval, B->vecs, B->queue, B->iters, B->status,
-                   B->lstate, B->lpart, B->lactive};
+                   B->lstate, B->lpart, B->lactive, B->lticket};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     for (auto& t : B->tab) {
@@ -1230,6 +1232,8 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     BTRY(hipMalloc(&B->lstate, sizeof(State) * nsys));
     BTRY(hipMalloc(&B->lpart, sizeof(double) * 6 * max_groups));
     BTRY(hipMalloc(&B->lactive, sizeof(int32_t) * 4));
+    BTRY(hipMalloc(&B->lticket, sizeof(int32_t) * nsys));
+    BTRY(hipMemsetAsync(B->lticket, 0, sizeof(int32_t) * nsys, st));
     BTRY(hipHostMalloc(&B->hactive, sizeof(int32_t) * 2, hipHostMallocDefault));
     BTRY(hipEventCreateWithFlags(&B->lev[0], hipEventDisableTiming));
     BTRY(hipEventCreateWithFlags(&B->lev[1], hipEventDisableTiming));
