@@ -595,9 +595,14 @@ def main():
                     "one_thread_sample": f"{one['iters']} iterations from x0 = 0 ({dt1:.1f} s, incl. setup)"}
 
     triad = stream_triad(torch)
-    batched = None if args.no_batched else batched_section(torch, prcg, problems, traffic)
-    adjoint = None if args.no_adjoint else adjoint_section(torch, prcg, problems)
+    # the HBM-bound 27-point workload first, on a device whose memory the
+    # later sections have not fragmented (the adjoint's unrolled autograd
+    # holds up to ~150 GB in torch's cache)
     varcoef27 = None if args.no_27pt else varcoef27_section(torch, prcg, problems, traffic)
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else batched_section(torch, prcg, problems, traffic)
+    torch.cuda.empty_cache()
+    adjoint = None if args.no_adjoint else adjoint_section(torch, prcg, problems)
 
     out = {
         "metric": "CG iterations/sec (FP64 PR-CG solve to 1e-10 relative residual)",

@@ -370,7 +370,7 @@ prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props*
 /* How the batched solver runs PR-CG and M-CG (HS-CG and the pipelined
  * variants always run persistent):
  *   PRCG_BATCH_PERSISTENT  one persistent kernel, a workgroup per system;
- *   PRCG_BATCH_LOCKSTEP    three launches per iteration (two when fused:
+ *   PRCG_BATCH_LOCKSTEP    three launches per iteration (one when fused:
  *     prcg_batch_set_fusion) over the row groups
  *     (8, 16 or 32 slices of 64 rows of one system) of every system still
  *     running: the
@@ -382,14 +382,16 @@ prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props*
 typedef enum { PRCG_BATCH_AUTO = 0, PRCG_BATCH_PERSISTENT = 1, PRCG_BATCH_LOCKSTEP = 2 } prcg_batch_mode_t;
 
 /* Lockstep iterations of PR-CG and M-CG without a preconditioner may run
- * fused: one launch updates x, r and p of a row group and multiplies the
- * new p, recomputing p at the rows outside the group that its stencil
- * reaches, then the per-system stage 2 (two launches per iteration; eight
- * vector words per row move instead of ten).  Allowed for a group table
- * whose groups are all offset-aligned with one offset list each, of at most
- * 7 slots and a span (largest minus smallest column offset, 0 included) of
- * at most 1536, at 8 or 16 slices per group.  The results equal those of three
- * launches bit for bit.
+ * fused, one launch per iteration: a workgroup updates x, r and p of its
+ * row group, multiplies the new p (recomputing it at the rows outside the
+ * group that the stencil reaches) and writes its partials; the last
+ * workgroup of each system to finish (an atomic ticket per system) takes
+ * the system's stage 2 and scalar step.  Eight vector words per row move
+ * instead of ten.  Allowed for a group table whose groups are all
+ * offset-aligned with one offset list each, of at most 7 slots and a span
+ * (largest minus smallest column offset, 0 included) of at most 1536, at 8
+ * or 16 slices per group.  The results equal those of three launches bit
+ * for bit.
  *   PRCG_BATCH_FUSION_AUTO  the autotuner times both (default);
  *   PRCG_BATCH_FUSION_OFF   three launches per iteration;
  *   PRCG_BATCH_FUSION_ON    fused only: where no group table allows it, a
