@@ -195,11 +195,17 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, con
         per_mode[m] = {"solves_per_s": (len(offs) - 1) / ((time.perf_counter() - t) / reps),
                        "iterations_total": int(it_m.sum())}
     sizes = np.diff(offs)
-    # algorithmic bytes: per system-iteration 10 vectors (PR-CG: the update reads
-    # x, r, p, s and writes x, r, p; the product reads p, r and writes s) and
-    # the system's share of the batch's SELL-64 bytes (taken per row)
-    per_row_matrix = props["matrix_bytes"] / float(A.n)
-    moved = float(np.sum(iters * sizes * (80.0 + per_row_matrix)))
+    # algorithmic bytes per system-iteration: the vector words per row of the
+    # structure that ran (8 for the fused lockstep iteration: x, r, p, s read
+    # and written, p recomputed at the neighbouring rows; 10 otherwise: the
+    # update reads x, r, p, s and writes x, r, p, the product reads p, r and
+    # writes s) plus the system's share of the matrix, taken per row: the
+    # batch's SELL-64 bytes (format basis) or the CSR count 12 nnz + 4 (n + 1)
+    # of the byte model
+    words = 8 if (mode == "lockstep" and props["fused"]) else 10
+    row_iters = float(np.sum(iters * sizes))
+    moved = row_iters * (8.0 * words + props["matrix_bytes"] / float(A.n))
+    moved_csr = row_iters * (8.0 * words + (12.0 * A.nnz + 4.0 * (A.n + 1)) / float(A.n))
     # sequential: one handle and one solve per system (handles created before timing)
     t_seq, seq_iters = float("nan"), 0
     if sequential:
@@ -222,9 +228,11 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, con
             "sequential_solves_per_s": len(sizes) / t_seq if sequential else None,
             "sequential_ms": t_seq * 1e3 if sequential else None,
             "speedup": t_seq / t_batch if sequential else None, "iterations_total": int(iters.sum()), "sequential_iterations": seq_iters,
-            "algorithmic_GBps": moved / t_batch / 1e9, "hbm_frac": moved / t_batch / 1e9 / HBM_PEAK_GBS,
-            "bytes_moved": moved, "mode": mode, "modes": per_mode, "threads_per_workgroup": nt, "workgroups": grid,
-            "tuned": props}
+            "words_per_row": words, "algorithmic_GBps": moved / t_batch / 1e9,
+            "hbm_frac": moved / t_batch / 1e9 / HBM_PEAK_GBS, "bytes_moved": moved,
+            "algorithmic_GBps_csr_model": moved_csr / t_batch / 1e9,
+            "hbm_frac_csr_model": moved_csr / t_batch / 1e9 / HBM_PEAK_GBS, "bytes_moved_csr_model": moved_csr,
+            "mode": mode, "modes": per_mode, "threads_per_workgroup": nt, "workgroups": grid, "tuned": props}
 
 
 def roofline_of(kernel_us, fmt_bytes, csr_bytes):

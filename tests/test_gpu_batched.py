@@ -393,3 +393,18 @@ def test_fusion_settings_are_checked(prcg):
         Bm.solve(P.uniform_vector(Am.n, 5), "pr", 1e-10, 5000)
     with pytest.raises(prcg.PrcgError):
         prcg.prcg_batch_set_fusion(Bm.handle, 3)
+    # a stencil whose span (2 x 800 rows) exceeds what the window holds:
+    # 'on' fails, 'auto' runs three launches and matches the oracle
+    wide = [P.poisson2d(800, 3), P.batch_system(1, 64, 3000)[0]]
+    bw = [P.uniform_vector(A_.n, 40 + s) for s, A_ in enumerate(wide)]
+    Aw, offw = P.block_diag(wide)
+    Mw = prcg.Matrix(Aw.row_ptr, Aw.col_idx, Aw.values, "none")
+    Bw = prcg.Batch(Mw, offw)
+    Bw.set_mode("lockstep")
+    Bw.set_fusion("on")
+    with pytest.raises(prcg.PrcgError):
+        Bw.solve(np.concatenate(bw), "pr", 1e-10, 5000)
+    Bw.set_fusion("auto")
+    x, iters, status = Bw.solve(np.concatenate(bw), "pr", 1e-10, 5000)
+    assert Bw.props("pr")["fused"] == 0
+    check_systems(x.cpu().numpy(), iters, status, wide, bw, offw, "pr", "none", 1e-10)
