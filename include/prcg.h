@@ -381,13 +381,14 @@ prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props*
  *   PRCG_BATCH_AUTO (default)  the faster of the two on the first solve. */
 typedef enum { PRCG_BATCH_AUTO = 0, PRCG_BATCH_PERSISTENT = 1, PRCG_BATCH_LOCKSTEP = 2 } prcg_batch_mode_t;
 
-/* Lockstep iterations of PR-CG and M-CG without a preconditioner may run
- * fused, one launch per iteration: a workgroup updates x, r and p of its
+/* Lockstep iterations of PR-CG and M-CG (with or without the Jacobi
+ * preconditioner) may run fused, one launch per iteration: a workgroup updates x, r and p of its
  * row group, multiplies the new p (recomputing it at the rows outside the
  * group that the stencil reaches) and writes its partials; the last
  * workgroup of each system to finish (an atomic ticket per system) takes
- * the system's stage 2 and scalar step.  Eight vector words per row move
- * instead of ten.  Allowed for a group table whose groups are all
+ * the system's stage 2 and scalar step.  Without a preconditioner eight
+ * vector words per row move instead of ten (with Jacobi, twelve instead of
+ * fifteen).  Allowed for a group table whose groups are all
  * offset-aligned with one offset list each, of at most 7 slots and a span
  * (largest minus smallest column offset, 0 included) of at most 1536, at 8
  * or 16 slices per group.  The results equal those of three launches bit

@@ -57,11 +57,13 @@ struct GroupView {
     int32_t* ticket;           // [nsys]: the fused iteration's stage-2 tickets (0 between launches)
 };
 
-// The lockstep vectors one fused iteration reads or writes besides x.
+// The lockstep vectors one fused iteration reads or writes besides x
+// (rt: r~, with a preconditioner only).
 struct LsVecs {
     double* r;
     double* p;
     double* s;
+    double* rt;
 };
 // Largest stencil span (largest minus smallest column offset of a group,
 // offset 0 included) of a table whose iterations may run fused: the window
@@ -76,10 +78,11 @@ hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const V
                                 double* P, double tol, int maxit, int variant, int pre, int32_t* iters,
                                 int32_t* status, hipStream_t st);
 // fused: each iteration as one launch of k_ls_fused, whose last workgroup
-// of each system takes the system's stage 2 (no
-// preconditioner, uniform groups (uwidth > 0) of span at most kFuseSpan, 2 or 4 slices per wavefront, an even number of iterations:
-// r, p and s alternate between (v.r, v.p, v.s) and (v.w, v.u, v.st), and the
-// initialisation leaves them in the first).
+// of each system takes the system's stage 2 (uniform groups (uwidth > 0)
+// of span at most kFuseSpan, 2 or 4 slices per wavefront, an even number
+// of iterations: r (r~ with a preconditioner, r then staying in place), p
+// and s alternate between (v.r or v.rt, v.p, v.s) and (v.w, v.u, v.st), and
+// the initialisation leaves them in the first).
 hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, const Vecs& v, State* S, double* P,
                                       int iterations, int variant, int pre, bool fused, int32_t* iters,
                                       int32_t* status, int32_t* active, hipStream_t st);

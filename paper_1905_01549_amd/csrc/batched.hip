@@ -637,30 +637,32 @@ __device__ __forceinline__ void finish_system(const GroupView& gv, State* __rest
 }
 
 // One lockstep iteration of a uniform group with the update and the product
-// in one pass (PR-CG, M-CG without a preconditioner).  k_ls_update followed
-// by k_ls_spmv moves ten vector words per row (x, r, p, s read; x, r, p
+// in one pass (PR-CG, M-CG).  k_ls_update followed by k_ls_spmv moves ten
+// vector words per row without a preconditioner (x, r, p, s read; x, r, p
 // written; p, r read again; s written); this kernel moves eight (x, r, p, s
-// read; x, r', p', s' written).  The product s' = A p' needs p' at every
-// column the group's rows reach, which extends past the group by the
-// stencil's span (within the system): the workgroup recomputes p' there from
-// r, s and p, which its neighbouring groups read as their own rows at about
-// the same time (the workgroup-to-group map keeps neighbouring groups on one
-// XCD, so these reads are served by its L2).  Reads r, p, s from `in` and
-// writes r', p', s' to `out`: other workgroups still read the old values.
-// x is updated in place.  Every row's arithmetic and the order of every sum
-// are those of k_ls_update then k_ls_spmv<false, 0, SPW>, and the last
-// workgroup of each system (by a ticket) then runs the stage 2 and scalar
-// step of k_ls_finish: the results agree bit for bit with those three
-// launches.  (The other workgroups of the system have read alpha and beta
-// before they took their tickets, so the state may change then.)
+// read; x, r', p', s' written; with Jacobi also r~ and d read and r~'
+// written).  The product s' = A p' needs p' at every column the group's
+// rows reach, which extends past the group by the stencil's span (within
+// the system): the workgroup recomputes p' there from r~, s and p (and d),
+// which its neighbouring groups read as their own rows at about the same
+// time (the workgroup-to-group map keeps neighbouring groups on one XCD, so
+// these reads are served by its L2).  Reads r~, p, s from `in` and writes
+// r~', p', s' to `out`: other workgroups still read the old values.  x (and
+// r, with a preconditioner) is updated in place.  Every row's arithmetic
+// and the order of every sum are those of k_ls_update then
+// k_ls_spmv<PRE, 0, SPW>, and the last workgroup of each system (by a
+// ticket) then runs the stage 2 and scalar step of k_ls_finish: the results
+// agree bit for bit with those three launches.  (The other workgroups of
+// the system have read alpha and beta before they took their tickets, so
+// the state may change then.)
 //   window: LDS, p' at the rows [wlo, whi] (the clamped columns of the
-//           group's rows); then r' at the group's own rows.
+//           group's rows); then r' and (PRE) r~' at the group's own rows.
 constexpr int kWindowRows = 4;  // window rows per thread whose loads k_ls_fused issues together
-template <int SPW, int W>
+template <bool PRE, int SPW, int W>
 __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, State* __restrict__ S,
-                                                     double* __restrict__ x, LsVecs in, LsVecs out,
-                                                     double* __restrict__ P, int form, int32_t* __restrict__ iters,
-                                                     int32_t* __restrict__ status)
+                                                     double* __restrict__ x, const double* __restrict__ d,
+                                                     LsVecs in, LsVecs out, double* __restrict__ P, int form,
+                                                     int32_t* __restrict__ iters, int32_t* __restrict__ status)
 {
     extern __shared__ double window[];
     __shared__ double lds[kWaves * 5];
@@ -687,9 +689,10 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
     const int wlo = min(max(G.row0 + omin, G.lo), G.hi);
     const int whi = max(min(last + omax, G.hi), G.lo);
     double* __restrict__ rown = window + (whi - wlo + 1);  // r' of the group's rows
+    double* __restrict__ rtown = rown + G.nrows;           // with PRE: r~' of the group's rows
     // the product's values first: they do not depend on the update
     const double* __restrict__ vb = B.A.val + (int64_t)G.vrow * kSlice + lane;
-    double a[SPW][W];
+    double a[SPW][W], dr[SPW];
     int row[SPW];
     bool valid[SPW];
 #pragma unroll
@@ -702,40 +705,57 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
 #pragma unroll
         for (int u = 0; u < W; ++u)
             if (u < wg) a[j][u] = __builtin_nontemporal_load(&vb[(int64_t)(slc * wg + u) * kSlice]);
+        dr[j] = PRE ? d[row[j]] : 1.0;
     }
-    // p' over the window (r' and x as well at the group's own rows); the
-    // two buffer sets never overlap
-    const double* __restrict__ in_r = in.r;
+    // p' over the window (r', r~' and x as well at the group's own rows);
+    // the two buffer sets never overlap.  Without a preconditioner p' is
+    // formed from r (= r~), which alternates between the sets; with one,
+    // from r~ and d, which alternate, while r is read and written at the
+    // group's own rows only and stays in place (r_io).
+    const double* __restrict__ in_t = PRE ? in.rt : in.r;  // r~ (old)
     const double* __restrict__ in_p = in.p;
     const double* __restrict__ in_s = in.s;
-    double* __restrict__ out_r = out.r;
+    double* __restrict__ out_t = PRE ? out.rt : out.r;     // r~ (new)
     double* __restrict__ out_p = out.p;
     double* __restrict__ out_s = out.s;
+    double* __restrict__ r_io = in.r;                      // PRE: r, updated in place
     // kWindowRows rows per thread at a time: their loads are issued
     // together (rows past the window load its last row and are skipped)
     constexpr int U = kWindowRows;
     for (int i0 = wlo + (int)threadIdx.x; i0 <= whi; i0 += U * kBlock) {
-        double sv[U], pv[U], rv[U], xv[U];
+        double sv[U], pv[U], tv[U], xv[U], dv[U], rv[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int i = min(i0 + k * kBlock, whi);
+            const bool own = i >= G.row0 && i <= last;
             sv[k] = in_s[i];
             pv[k] = in_p[i];
-            rv[k] = in_r[i];
-            xv[k] = i >= G.row0 && i <= last ? x[i] : 0.0;
+            tv[k] = in_t[i];
+            xv[k] = own ? x[i] : 0.0;
+            dv[k] = PRE ? d[i] : 1.0;
+            rv[k] = PRE && own ? r_io[i] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int i = i0 + k * kBlock;
             if (i > whi) break;
-            const double rn = fma(-alpha, sv[k], rv[k]);
-            const double pn = fma(beta, pv[k], rn);
+            // k_ls_update's expressions: r' = r - alpha s, r~' = r~ - alpha
+            // d s (= r' without a preconditioner), p' = r~' + beta p
+            const double tn = PRE ? fma(-alpha, dv[k] * sv[k], tv[k]) : fma(-alpha, sv[k], tv[k]);
+            const double pn = fma(beta, pv[k], tn);
             window[i - wlo] = pn;
             if (i >= G.row0 && i <= last) {
                 __builtin_nontemporal_store(fma(alpha, pv[k], xv[k]), &x[i]);
-                __builtin_nontemporal_store(rn, &out_r[i]);
+                __builtin_nontemporal_store(tn, &out_t[i]);
                 __builtin_nontemporal_store(pn, &out_p[i]);
-                rown[i - G.row0] = rn;
+                if constexpr (PRE) {
+                    const double rn = fma(-alpha, sv[k], rv[k]);
+                    __builtin_nontemporal_store(rn, &r_io[i]);
+                    rown[i - G.row0] = rn;
+                    rtown[i - G.row0] = tn;
+                } else {
+                    rown[i - G.row0] = tn;
+                }
             }
         }
     }
@@ -748,12 +768,17 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
         for (int u = 0; u < W; ++u)
             if (u < wg) y = fma(a[j][u], window[min(max(row[j] + o[u], G.lo), G.hi) - wlo], y);
         if (valid[j]) {
+            // k_ls_spmv's inner products: <p, s>, <r~, s>, <s~, s>, <r~, r>
+            // and, with a preconditioner, <r, r>
             const double pi = window[row[j] - wlo], ri = rown[row[j] - G.row0];
+            const double ti = PRE ? rtown[row[j] - G.row0] : ri;
+            const double sti = PRE ? dr[j] * y : y;
             __builtin_nontemporal_store(y, &out_s[row[j]]);
             q[0] = fma(pi, y, q[0]);
-            q[1] = fma(ri, y, q[1]);
-            q[2] = fma(y, y, q[2]);
-            q[3] = fma(ri, ri, q[3]);
+            q[1] = fma(ti, y, q[1]);
+            q[2] = fma(sti, y, q[2]);
+            q[3] = fma(ti, ri, q[3]);
+            if (PRE) q[4] = fma(ri, ri, q[4]);
         }
     }
     block_sum<5, kWaves>(q, lds);
@@ -776,7 +801,7 @@ __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, 
         if (is_last) __hip_atomic_store(gv.ticket + sys, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (is_last) finish_system<false, true>(gv, S, P, sys, form, iters, status);
+    if (is_last) finish_system<PRE, true>(gv, S, P, sys, form, iters, status);
 }
 
 // Stage 2 and the scalar step of one system (one workgroup per system):
@@ -925,17 +950,24 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
     const int form = nu_form(variant);
     const dim3 grid((unsigned)gv.ngroups), nsys((unsigned)B.nsys), blk(kBlock);
     if (fused) {
-        if (pre || iterations % 2 != 0 || (gv.spw != 2 && gv.spw != 4) ||
+        if (iterations % 2 != 0 || (gv.spw != 2 && gv.spw != 4) ||
             (gv.uwidth != 3 && gv.uwidth != 5 && gv.uwidth != 7))
             return hipErrorInvalidValue;
         const dim3 fgrid((unsigned)((gv.ngroups + 7) / 8 * 8));
-        const size_t lds = sizeof(double) * (2 * (size_t)kWaves * gv.spw * kSlice + kFuseSpan);
-        const LsVecs A{v.r, v.p, v.s}, A2{v.w, v.u, v.st};
+        const size_t lds = sizeof(double) * ((pre ? 3 : 2) * (size_t)kWaves * gv.spw * kSlice + kFuseSpan);
+        // the two buffer sets: r (without a preconditioner), r~ (with one),
+        // p and s alternate; with one, r stays in place
+        const LsVecs A = pre ? LsVecs{v.r, v.p, v.s, v.rt} : LsVecs{v.r, v.p, v.s, nullptr};
+        const LsVecs A2 = pre ? LsVecs{v.r, v.u, v.st, v.w} : LsVecs{v.w, v.u, v.st, nullptr};
         auto go = [&](auto SPWc, auto Wc) -> hipError_t {
             constexpr int SPW = decltype(SPWc)::value, W = decltype(Wc)::value;
             for (int k = 0; k < iterations; ++k) {
-                hipLaunchKernelGGL((k_ls_fused<SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, k % 2 ? A2 : A,
-                                   k % 2 ? A : A2, P, form, iters, status);
+                if (pre)
+                    hipLaunchKernelGGL((k_ls_fused<true, SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, v.d,
+                                       k % 2 ? A2 : A, k % 2 ? A : A2, P, form, iters, status);
+                else
+                    hipLaunchKernelGGL((k_ls_fused<false, SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, v.d,
+                                       k % 2 ? A2 : A, k % 2 ? A : A2, P, form, iters, status);
             }
             return hipGetLastError();
         };

@@ -1399,8 +1399,8 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
         }
     }
     // Lockstep group size (PR-CG and M-CG): groups of 8, 16 and 32 slices,
-    // each with three launches per iteration and, where the table allows and
-    // no preconditioner is applied, with the fused iteration; each candidate
+    // each with three launches per iteration and, where the table allows,
+    // with the fused iteration; each candidate
     // timed on the initialisation and 32 iterations of this batch (tol = 0).
     // The group size is fixed by prcg_batch_set_config, the fusion by
     // prcg_batch_set_fusion.
@@ -1411,7 +1411,7 @@ prcg_status prcg_solve_batched(prcg_batch B, prcg_variant v, const double* b, do
             if (B->force_group && kWaves * B->tab[t].spw != B->force_group) continue;
             for (int f = 0; f < 2; ++f) {
                 const bool fused = f == 1;
-                if (fused && (A->precond || !B->tab[t].fuse_ok || B->force_fusion == PRCG_BATCH_FUSION_OFF)) continue;
+                if (fused && (!B->tab[t].fuse_ok || B->force_fusion == PRCG_BATCH_FUSION_OFF)) continue;
                 if (!fused && B->force_fusion == PRCG_BATCH_FUSION_ON) continue;
                 ++ncand;
                 float ms = 0.f;

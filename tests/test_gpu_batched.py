@@ -194,13 +194,14 @@ def batch512():
     return P.config4()
 
 
-@pytest.mark.parametrize("mode,fusion", [("persistent", "auto"), ("lockstep", "off"), ("lockstep", "on")])
-def test_full_batched_workload_sampled(prcg, batch512, mode, fusion):
+@pytest.mark.parametrize("mode,fusion,precond", [("persistent", "auto", "none"), ("lockstep", "off", "none"),
+                                                 ("lockstep", "on", "none"), ("lockstep", "on", "jacobi")])
+def test_full_batched_workload_sampled(prcg, batch512, mode, fusion, precond):
     """All 512 systems (n from 1k to 64k) in one solve; the oracle checks the
     largest, the smallest and two more systems; every system's true residual
     is checked on the host."""
     A, offs, b, xstar, eps = batch512
-    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
     B = prcg.Batch(M, offs)
     B.set_mode(mode)
     B.set_fusion(fusion)
@@ -216,7 +217,7 @@ def test_full_batched_workload_sampled(prcg, batch512, mode, fusion):
     for s in sample:
         As = mats[s]
         bsys = b[offs[s]:offs[s + 1]]
-        ref = oracle.solve(As.row_ptr, As.col_idx, As.values, bsys, "pr", "none", 0.0, int(iters[s]))
+        ref = oracle.solve(As.row_ptr, As.col_idx, As.values, bsys, "pr", precond, 0.0, int(iters[s]))
         xs = x[offs[s]:offs[s + 1]]
         assert np.linalg.norm(xs - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"]), s
     S = A.scipy()
@@ -336,16 +337,17 @@ def stencil_batch():
     return A, offs, np.concatenate(bs), mats, bs
 
 
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
 @pytest.mark.parametrize("group_slices", [8, 16])
 @pytest.mark.parametrize("variant", ["pr", "m"])
-def test_fused_lockstep_equals_three_launches(prcg, group_slices, variant):
+def test_fused_lockstep_equals_three_launches(prcg, group_slices, variant, precond):
     """The fused lockstep iteration (update and product in one launch, p'
     recomputed past the group's edges) gives the bits of three launches per
-    iteration: from x0 = 0 to convergence, from x0 != 0, and for a maxit
-    that is not a multiple of the 16-iteration chunk; every system of the
-    fused run against the oracle."""
+    iteration, with and without Jacobi: from x0 = 0 to convergence, from
+    x0 != 0, and for a maxit that is not a multiple of the 16-iteration
+    chunk; every system of the fused run against the oracle."""
     A, offs, b, mats, bs = stencil_batch()
-    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "none")
+    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, precond)
     x0 = P.uniform_vector(A.n, 99)
     runs = {}
     for fusion in ("off", "on"):
@@ -363,26 +365,15 @@ def test_fused_lockstep_equals_three_launches(prcg, group_slices, variant):
     for (xa, ia, sa), (xb, ib, sb) in zip(runs["off"], runs["on"]):
         assert np.array_equal(xa, xb) and np.array_equal(ia, ib) and sa == sb
     x, iters, status = runs["on"][0]
-    check_systems(x, iters, status, mats, bs, offs, variant, "none", 1e-10)
+    check_systems(x, iters, status, mats, bs, offs, variant, precond, 1e-10)
     big = np.diff(offs) > 200  # the 9-row system terminates (exactly) sooner
     assert np.all(runs["on"][2][1][big] == 23) and np.all(runs["on"][2][1] <= 23)
 
 
 def test_fusion_settings_are_checked(prcg):
-    """The fused iteration needs uniform groups and no preconditioner:
-    asking for it elsewhere fails with PRCG_EINVAL at the solve, as does an
-    unknown setting; 'auto' picks three launches there."""
-    A, offs, b, mats, bs = stencil_batch()
-    M = prcg.Matrix(A.row_ptr, A.col_idx, A.values, "jacobi")
-    B = prcg.Batch(M, offs)
-    B.set_mode("lockstep")
-    B.set_fusion("on")
-    with pytest.raises(prcg.PrcgError):
-        B.solve(b, "pr", 1e-10, 5000)
-    B.set_fusion("auto")
-    x, iters, status = B.solve(b, "pr", 1e-10, 5000)
-    assert B.props("pr")["fused"] == 0
-    check_systems(x.cpu().numpy(), iters, status, mats, bs, offs, "pr", "jacobi", 1e-10)
+    """The fused iteration needs uniform groups of a bounded span: asking
+    for it elsewhere fails with PRCG_EINVAL at the solve, as does an unknown
+    setting; 'auto' picks three launches there."""
     mixed = [P.random_spd(900, 5.0, 3), P.batch_system(0, 64, 3000)[0]]
     Am, offm = P.block_diag(mixed)
     Mm = prcg.Matrix(Am.row_ptr, Am.col_idx, Am.values, "none")
