@@ -327,11 +327,13 @@ def test_autotuned_configuration_is_reported(prcg):
 
 
 def stencil_batch():
-    """Systems whose row groups are all offset-aligned of width 5 (2D
-    5-point stencils, anisotropic and not): sizes from one partial slice to
-    about 6,000 rows, so groups end ragged and some systems hold one group."""
+    """Systems whose row groups are all offset-aligned (2D 5-point stencils,
+    anisotropic and not, whose boundary slices hold 3 or 4 slots, a 1D
+    3-point system and a one-row system): sizes from one row to about 6,000
+    rows, so groups end ragged and some systems hold one group."""
     mats = [P.batch_system(s, 64, 6000)[0] for s in range(9)]
-    mats += [P.poisson2d(3), P.poisson2d(5, 7), P.aniso2d(40, 3, 0.01), P.poisson2d(70, 2)]
+    mats += [P.poisson2d(3), P.poisson2d(5, 7), P.aniso2d(40, 3, 0.01), P.poisson2d(70, 2), P.poisson2d(1, 1),
+             P.poisson2d(50, 1)]
     bs = [P.uniform_vector(A.n, 70 + s) for s, A in enumerate(mats)]
     A, offs = P.block_diag(mats)
     return A, offs, np.concatenate(bs), mats, bs
