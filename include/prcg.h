@@ -382,17 +382,18 @@ prcg_status prcg_batch_get_props(prcg_batch B, prcg_variant v, prcg_batch_props*
 typedef enum { PRCG_BATCH_AUTO = 0, PRCG_BATCH_PERSISTENT = 1, PRCG_BATCH_LOCKSTEP = 2 } prcg_batch_mode_t;
 
 /* Lockstep iterations of PR-CG and M-CG (with or without the Jacobi
- * preconditioner) may run fused, one launch per iteration: a workgroup updates x, r and p of its
- * row group, multiplies the new p (recomputing it at the rows outside the
- * group that the stencil reaches) and writes its partials; the last
- * workgroup of each system to finish (an atomic ticket per system) takes
- * the system's stage 2 and scalar step.  Without a preconditioner eight
- * vector words per row move instead of ten (with Jacobi, twelve instead of
- * fifteen).  Allowed for a group table whose groups are all
- * offset-aligned with one offset list each, of at most 7 slots and a span
- * (largest minus smallest column offset, 0 included) of at most 1536, at 8
- * or 16 slices per group.  The results equal those of three launches bit
- * for bit.
+ * preconditioner) may run fused, one launch per iteration: a workgroup
+ * updates x, r and p of its row group, multiplies the new p (recomputing it
+ * at the rows outside the group that the stencil reaches, held in LDS) and
+ * writes its partials; the last workgroup of each system to finish (an
+ * atomic ticket per system) takes the system's stage 2 and scalar step.
+ * Without a preconditioner eight vector words per row move instead of ten
+ * (with Jacobi, twelve instead of fifteen).  Allowed for a group table
+ * whose groups are all offset-aligned with one offset list each, of at most
+ * 7 slots, at 8 or 16 slices per group, when the stencil span (largest
+ * minus smallest column offset, 0 included) is at most 6656 rows (8 slices)
+ * or 5120 (16 slices), so that a workgroup's LDS stays within 64 KB.  The
+ * results equal those of three launches bit for bit.
  *   PRCG_BATCH_FUSION_AUTO  the autotuner times both (default);
  *   PRCG_BATCH_FUSION_OFF   three launches per iteration;
  *   PRCG_BATCH_FUSION_ON    fused only: where no group table allows it, a

@@ -55,6 +55,7 @@ struct GroupView {
     int32_t spw;               // slices per wavefront (2, 4 or 8): groups hold kWaves spw slices
     int32_t uwidth;            // every group uniform: 3, 5 or 7, the least at or above the widest; else 0
     int32_t* ticket;           // [nsys]: the fused iteration's stage-2 tickets (0 between launches)
+    int32_t span;              // the largest stencil span of a group (offset 0 included)
 };
 
 // The lockstep vectors one fused iteration reads or writes besides x
@@ -65,10 +66,16 @@ struct LsVecs {
     double* s;
     double* rt;
 };
-// Largest stencil span (largest minus smallest column offset of a group,
-// offset 0 included) of a table whose iterations may run fused: the window
-// of p' one workgroup holds in LDS is at most the group's rows plus this.
-constexpr int kFuseSpan = 1536;
+// LDS of one fused workgroup, in doubles: the window of p' (the group's
+// rows plus the table's largest stencil span, i.e. largest minus smallest
+// column offset of a group, offset 0 included) and r' (and r~' with a
+// preconditioner) of the group's rows.  A table may run fused when this
+// fits the 64 KB a workgroup may hold with a preconditioner.
+__host__ __device__ constexpr int fused_lds_doubles(int group_rows, int span, bool pre)
+{
+    return group_rows * (pre ? 3 : 2) + span;
+}
+constexpr int kFuseLdsDoubles = 65536 / 8;
 
 // Lockstep PR-CG / M-CG (variant kPR or kM): the initialisation (three
 // launches), then `iterations` iterations of three launches each and the
@@ -79,7 +86,7 @@ hipError_t launch_lockstep_init(const BatchView& B, const GroupView& gv, const V
                                 int32_t* status, hipStream_t st);
 // fused: each iteration as one launch of k_ls_fused, whose last workgroup
 // of each system takes the system's stage 2 (uniform groups (uwidth > 0)
-// of span at most kFuseSpan, 2 or 4 slices per wavefront, an even number
+// whose window fits kFuseLdsDoubles, 2 or 4 slices per wavefront, an even number
 // of iterations: r (r~ with a preconditioner, r then staying in place), p
 // and s alternate between (v.r or v.rt, v.p, v.s) and (v.w, v.u, v.st), and
 // the initialisation leaves them in the first).

@@ -954,7 +954,8 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
             (gv.uwidth != 3 && gv.uwidth != 5 && gv.uwidth != 7))
             return hipErrorInvalidValue;
         const dim3 fgrid((unsigned)((gv.ngroups + 7) / 8 * 8));
-        const size_t lds = sizeof(double) * ((pre ? 3 : 2) * (size_t)kWaves * gv.spw * kSlice + kFuseSpan);
+        const size_t lds = sizeof(double) * (size_t)fused_lds_doubles(kWaves * gv.spw * kSlice, gv.span, pre != 0);
+        if (lds > sizeof(double) * (size_t)kFuseLdsDoubles) return hipErrorInvalidValue;
         // the two buffer sets: r (without a preconditioner), r~ (with one),
         // p and s alternate; with one, r stays in place
         const LsVecs A = pre ? LsVecs{v.r, v.p, v.s, v.rt} : LsVecs{v.r, v.p, v.s, nullptr};

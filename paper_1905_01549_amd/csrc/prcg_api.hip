@@ -238,6 +238,7 @@ struct prcg_batch_s {
         int32_t spw = 0;
         int32_t uwidth = 0;  // every group uniform: 3, 5 or 7 slots, the least at or above the widest; else 0
         bool fuse_ok = false;  // iterations may run fused (launch_lockstep_iterations)
+        int32_t span = 0;      // the largest stencil span of a uniform group
     };
     static constexpr int kTables = 3;
     GroupTable tab[kTables];
@@ -256,7 +257,7 @@ struct prcg_batch_s {
     GroupView groups(int t) const
     {
         return GroupView{tab[t].grp, tab[t].sys_grp0, tab[t].ngroups, tab[t].gdone, tab[t].spw, tab[t].uwidth,
-                         lticket};
+                         lticket, tab[t].span};
     }
 
     Vecs vecs_view() const
@@ -1211,16 +1212,18 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
         T.uwidth = 0;
         if (T.ngroups > 0 && T.uniform_groups == T.ngroups)
             T.uwidth = wmax <= 3 ? 3 : wmax <= 5 ? 5 : wmax <= 7 ? 7 : 0;
-        T.fuse_ok = T.uwidth > 0 && (spw == 2 || spw == 4);
+        T.span = 0;
         for (const Group& G : grp[t]) {
-            if (!T.fuse_ok) break;
+            if (G.off < 0) continue;
             int omin = 0, omax = 0;  // the span includes offset 0 (the group's own rows)
             for (int u = 0; u < G.width; ++u) {
                 omin = std::min(omin, G.o[u]);
                 omax = std::max(omax, G.o[u]);
             }
-            if (omax - omin > kFuseSpan) T.fuse_ok = false;
+            T.span = std::max(T.span, omax - omin);
         }
+        T.fuse_ok = T.uwidth > 0 && (spw == 2 || spw == 4) &&
+                    fused_lds_doubles(kWaves * spw * kSlice, T.span, true) <= kFuseLdsDoubles;
         max_groups = std::max(max_groups, T.ngroups);
         BTRY(hipMalloc(&T.grp, sizeof(Group) * T.ngroups));
         BTRY(hipMalloc(&T.sys_grp0, sizeof(int64_t) * (nsys + 1)));

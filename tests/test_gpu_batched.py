@@ -329,11 +329,12 @@ def test_autotuned_configuration_is_reported(prcg):
 def stencil_batch():
     """Systems whose row groups are all offset-aligned (2D 5-point stencils,
     anisotropic and not, whose boundary slices hold 3 or 4 slots, a 1D
-    3-point system and a one-row system): sizes from one row to about 6,000
-    rows, so groups end ragged and some systems hold one group."""
+    3-point system, a one-row system and a 2000 x 2 grid whose span of 4000
+    rows needs a window eight times the group's rows): sizes from one row to
+    about 6,000 rows, so groups end ragged and some systems hold one group."""
     mats = [P.batch_system(s, 64, 6000)[0] for s in range(9)]
     mats += [P.poisson2d(3), P.poisson2d(5, 7), P.aniso2d(40, 3, 0.01), P.poisson2d(70, 2), P.poisson2d(1, 1),
-             P.poisson2d(50, 1)]
+             P.poisson2d(50, 1), P.poisson2d(2000, 2)]
     bs = [P.uniform_vector(A.n, 70 + s) for s, A in enumerate(mats)]
     A, offs = P.block_diag(mats)
     return A, offs, np.concatenate(bs), mats, bs
@@ -386,9 +387,9 @@ def test_fusion_settings_are_checked(prcg):
         Bm.solve(P.uniform_vector(Am.n, 5), "pr", 1e-10, 5000)
     with pytest.raises(prcg.PrcgError):
         prcg.prcg_batch_set_fusion(Bm.handle, 3)
-    # a stencil whose span (2 x 800 rows) exceeds what the window holds:
+    # a stencil whose span (2 x 7000 rows) exceeds what the LDS window holds:
     # 'on' fails, 'auto' runs three launches and matches the oracle
-    wide = [P.poisson2d(800, 3), P.batch_system(1, 64, 3000)[0]]
+    wide = [P.poisson2d(7000, 2), P.batch_system(1, 64, 3000)[0]]
     bw = [P.uniform_vector(A_.n, 40 + s) for s, A_ in enumerate(wide)]
     Aw, offw = P.block_diag(wide)
     Mw = prcg.Matrix(Aw.row_ptr, Aw.col_idx, Aw.values, "none")
