@@ -230,7 +230,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
     static_assert(PRE || !NUDOT, "without a preconditioner the product kernel reads r anyway");
     __shared__ double lds[kWaves * 5];
     int64_t g0, g1, i0, i1;
-    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    // rows in the opposite order to the product kernel's (see
+    // reverse_block): slot is the workgroup that owns them in that order
+    const int slot = reverse_block(blockIdx.x, sp.G);
+    chunk_of(slot, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double* __restrict__ x = v.x;
     double* __restrict__ r = v.r;
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Split sp, const State* __r
             }
         }
     }
-    if (NUDOT) write_partials<2>(acc, PN, sp.Gs, blockIdx.x, lds);
+    if (NUDOT) write_partials<2>(acc, PN, sp.Gs, slot, lds);
 }
 
 // One workgroup: stage 2 of iteration k and the scalar step of a
@@ -452,7 +455,9 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
     }
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
-    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    // rows in the opposite order to the product kernel's (reverse_block)
+    const int slot = reverse_block(blockIdx.x, sp.G);
+    chunk_of(slot, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double* __restrict__ x = v.x;
@@ -496,7 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_update(Split sp, const State* _
         acc[3] = fma(rti, rn, acc[3]);                         // nu_k    = <r~_k, r_k>
         if (PRE) acc[4] = fma(rn, rn, acc[4]);
     }
-    write_partials<5>(acc, PS, sp.Gs, blockIdx.x, lds);
+    write_partials<5>(acc, PS, sp.Gs, slot, lds);
     if (LAST && take_last_ticket(ticket, sp.G)) {
         State nx = st;
         double t[5];

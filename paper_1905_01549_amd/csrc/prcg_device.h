@@ -312,6 +312,17 @@ __device__ __forceinline__ void chunk_of(int b, int G, int64_t ngroups, int64_t&
     g1 = (int64_t)(c + 1) * ngroups / G;
 }
 
+// The workgroup whose runs chunk_of gives workgroup b in reverse order:
+// each XCD then sweeps its rows from the other end, so a kernel that
+// follows one in the forward order starts on the rows that kernel touched
+// last, still in the last-level cache.  A kernel that takes its runs this
+// way writes its partials at the slot of that workgroup, which keeps the
+// reductions' order.
+__device__ __forceinline__ int reverse_block(int b, int G)
+{
+    return (G % 8 == 0) ? b % 8 + 8 * (G / 8 - 1 - b / 8) : G - 1 - b;
+}
+
 // Products of one SELL-64 row (entries summed in stored column order; zero
 // slots add nothing).  The slots are consumed in fixed-size pieces: K
 // values, K columns and K gathered entries are loaded before the first of
