@@ -662,12 +662,18 @@ template <bool PRE, int SPW, int W>
 __global__ __launch_bounds__(kBlock) void k_ls_fused(BatchView B, GroupView gv, State* __restrict__ S,
                                                      double* __restrict__ x, const double* __restrict__ d,
                                                      LsVecs in, LsVecs out, double* __restrict__ P, int form,
-                                                     int32_t* __restrict__ iters, int32_t* __restrict__ status)
+                                                     int32_t* __restrict__ iters, int32_t* __restrict__ status,
+                                                     int reverse)
 {
     extern __shared__ double window[];
     __shared__ double lds[kWaves * 5];
+    // XCD x (workgroups b with b mod 8 = x) takes a contiguous range of
+    // groups, in increasing order, or decreasing on every other iteration
+    // (reverse): an iteration then starts on the groups the previous one
+    // touched last, whose vectors may still be in the last-level cache
     const int64_t gp = gridDim.x;  // a multiple of 8
-    const int64_t g = (blockIdx.x % 8) * (gp / 8) + blockIdx.x / 8;
+    const int64_t pos = blockIdx.x / 8;
+    const int64_t g = (blockIdx.x % 8) * (gp / 8) + (reverse ? gp / 8 - 1 - pos : pos);
     if (g >= gv.ngroups || gv.gdone[g]) return;  // the whole workgroup
     const Group G = gv.grp[g];
     const double alpha = S[G.sys].alpha, beta = S[G.sys].beta;
@@ -965,10 +971,10 @@ hipError_t launch_lockstep_iterations(const BatchView& B, const GroupView& gv, c
             for (int k = 0; k < iterations; ++k) {
                 if (pre)
                     hipLaunchKernelGGL((k_ls_fused<true, SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, v.d,
-                                       k % 2 ? A2 : A, k % 2 ? A : A2, P, form, iters, status);
+                                       k % 2 ? A2 : A, k % 2 ? A : A2, P, form, iters, status, k % 2);
                 else
                     hipLaunchKernelGGL((k_ls_fused<false, SPW, W>), fgrid, blk, lds, st, B, gv, S, v.x, v.d,
-                                       k % 2 ? A2 : A, k % 2 ? A : A2, P, form, iters, status);
+                                       k % 2 ? A2 : A, k % 2 ? A : A2, P, form, iters, status, k % 2);
             }
             return hipGetLastError();
         };
