@@ -578,10 +578,13 @@ __global__ __launch_bounds__(kBlock, PRE ? kLockstepSpmvWaves - 1 : kLockstepSpm
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_ls_update(GroupView gv, const State* __restrict__ S, Vecs v)
 {
-    // the flag and the record load together; the state's scalars load
+    // the groups in the order opposite to k_ls_spmv's, so each kernel
+    // starts on the groups the other touched last (still in the last-level
+    // cache); the flag and the record load together, the state's scalars
     // with the rows (they are needed only for the arithmetic)
-    if (gv.gdone[blockIdx.x]) return;
-    const Group G = gv.grp[blockIdx.x];
+    const int64_t g = gv.ngroups - 1 - blockIdx.x;
+    if (gv.gdone[g]) return;
+    const Group G = gv.grp[g];
     const double alpha = S[G.sys].alpha, beta = S[G.sys].beta;
     double* __restrict__ x = v.x;
     double* __restrict__ r = v.r;
