@@ -569,7 +569,9 @@ __global__ __launch_bounds__(kBlock) void k_gv_update(Split sp, const State* __r
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
-    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    // rows in the opposite order to the product kernel's (reverse_block)
+    const int slot = reverse_block(blockIdx.x, sp.G);
+    chunk_of(slot, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double* __restrict__ x = v.x;
     double* __restrict__ r = v.r;
@@ -613,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_gv_update(Split sp, const State* __r
         acc[1] = fma(rtn, wn, acc[1]);                            // eta_k = <r~_k, w_k>
         if (PRE) acc[2] = fma(rn, rn, acc[2]);
     }
-    write_partials<3>(acc, PS, sp.Gs, blockIdx.x, lds);
+    write_partials<3>(acc, PS, sp.Gs, slot, lds);
 }
 
 // t_k = A w~_k.  Workgroup 0 first reduces nu_k, eta_k (+ <r_k, r_k>) and
@@ -672,7 +674,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Split sp, const State* __r
     if (st.done) return;
     const double alpha = st.alpha, beta = st.beta;
     int64_t g0, g1, i0, i1;
-    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    // rows in the opposite order to the product kernel's (reverse_block)
+    const int slot = reverse_block(blockIdx.x, sp.G);
+    chunk_of(slot, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double* __restrict__ x = v.x;
     double* __restrict__ r = v.r;
@@ -698,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Split sp, const State* __r
         acc[0] = fma(rtn, rn, acc[0]);                          // nu_k
         if (PRE) acc[1] = fma(rn, rn, acc[1]);
     }
-    write_partials<2>(acc, PN, sp.Gs, blockIdx.x, lds);
+    write_partials<2>(acc, PN, sp.Gs, slot, lds);
 }
 
 // w_k = A r~_k and the partials of eta_k = <r~_k, w_k>.
@@ -772,7 +776,9 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
     }
     const double alpha = st.alpha;
     int64_t g0, g1, i0, i1;
-    chunk_of(blockIdx.x, sp.G, sp.ngroups, g0, g1);
+    // rows in the opposite order to the product kernel's (reverse_block)
+    const int slot = reverse_block(blockIdx.x, sp.G);
+    chunk_of(slot, sp.G, sp.ngroups, g0, g1);
     row_range(sp, g0, g1, i0, i1);
     double acc[2] = {0.0, 0.0};
     double* __restrict__ x = v.x;
@@ -790,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_hs_xr(Split sp, const State* __restr
         acc[0] = fma(rti, rn, acc[0]);
         if (PRE) acc[1] = fma(rn, rn, acc[1]);
     }
-    write_partials<2>(acc, PU, sp.Gs, blockIdx.x, lds);
+    write_partials<2>(acc, PU, sp.Gs, slot, lds);
     if (LAST && take_last_ticket(ticket, sp.G)) {
         double t[2];
         reduce_partials<2>(PU, sp.G, sp.Gs, t, lds);
