@@ -117,7 +117,7 @@ struct prcg_matrix_s {
     int32_t* scol = nullptr;
     double* sval = nullptr;
     int64_t nslices = 0;
-    int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
+    int64_t stream_from = INT64_MAX;  // first slice past the cacheable values (cached_value_bytes)
     int32_t runs = 0;            // 1 when some slice is stored in a run of more than one
     int64_t stored = 0;          // value slots, padding included
     int64_t stored_packed = 0;   // slots of packed slices (they also read a column index)
@@ -225,7 +225,7 @@ struct prcg_batch_s {
     hipGraphExec_t graph[kNumVariants] = {};
     double graph_tol[kNumVariants] = {};
     int32_t graph_maxit[kNumVariants] = {};
-    int64_t stream_from = INT64_MAX;  // first slice past the cached kCachedValueBytes of values
+    int64_t stream_from = INT64_MAX;  // first slice past the cacheable values (cached_value_bytes)
     // lockstep solver (PR-CG, M-CG): row groups of 8, 16 and 32 slices
     // (tables 0, 1, 2: 2, 4, 8 slices per wavefront), per-system states,
     // partials
@@ -695,6 +695,9 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     const int64_t run_max = (n + kGroupRows - 1) / kGroupRows >= kBigGroups ? kRunSlices : 1;
     std::vector<int64_t> hptr((size_t)A->nslices + 1);
     std::vector<int32_t> hmeta((size_t)A->nslices), hshape((size_t)A->nslices);
+    int64_t total = 0;  // value slots of the whole matrix
+    for (int64_t q = 0; q < A->nslices; ++q) total += (int64_t)kSlice * width[q];
+    const int64_t cached = cached_value_bytes(total * (int64_t)sizeof(double));
     int64_t pos = 0;
     for (int64_t q0 = 0; q0 < A->nslices;) {
         int64_t len = 1;
@@ -707,7 +710,7 @@ prcg_status prcg_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
         }
         if (len > 1) A->runs = 1;
         pos += (int64_t)kSlice * len * width[q0];
-        if (A->stream_from == INT64_MAX && pos * (int64_t)sizeof(double) > kCachedValueBytes)
+        if (A->stream_from == INT64_MAX && pos * (int64_t)sizeof(double) > cached)
             A->stream_from = q0 + len;  // the next run
         q0 += len;
     }
@@ -1119,8 +1122,9 @@ prcg_status prcg_create_batch(prcg_matrix A, int32_t nsys, const int64_t* sys_ro
     B->noffsets = noff;
     for (int64_t q = 0; q < ns; ++q)
         if (!aligned[q]) B->stored_packed += (int64_t)kSlice * width[q];
+    const int64_t cached = cached_value_bytes(hptr[ns] * (int64_t)sizeof(double));
     for (int64_t q = 0; q < ns; ++q)
-        if (hptr[q + 1] * (int64_t)sizeof(double) > kCachedValueBytes) {
+        if (hptr[q + 1] * (int64_t)sizeof(double) > cached) {
             B->stream_from = q + 1;
             break;
         }

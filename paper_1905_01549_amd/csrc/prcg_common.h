@@ -105,12 +105,22 @@ struct SellView {
     int32_t runs = 0;  // 1 when some slice is stored in a run of more than one
 };
 
-// Matrix values kept cacheable before loads turn nontemporal: half of the
-// MI355X's 256 MB last-level cache, so the vectors of an iteration fit
-// beside them (measured on a 27-point matrix of 885 MB: prefixes of 64, 128
-// and 192 MB gave products of 205, 199 and 217 us against 230 us with every
-// load cached and 213 us with none).
+// Matrix values kept cacheable before loads turn nontemporal: all of them
+// up to kCachedValueBytes, half of the MI355X's 256 MB last-level cache, so
+// the vectors of an iteration fit beside them; of a larger matrix, only the
+// first kCachedPrefixBytes (measured on a 27-point matrix of 885 MB:
+// prefixes of 64, 128 and 192 MB gave products of 205, 199 and 217 us
+// against 230 us with every load cached and 213 us with none; once the
+// update kernel swept the rows in reverse, a 96 MB prefix gave PR-CG 215
+// against 218 us per iteration with 128 MB, while the 118 MB matrix of the
+// 128^3 problem ran 11% slower when only 96 MB of it were cached).
 constexpr int64_t kCachedValueBytes = (int64_t)128 << 20;
+constexpr int64_t kCachedPrefixBytes = (int64_t)96 << 20;
+// The cacheable prefix of a matrix whose values take `total` bytes.
+inline int64_t cached_value_bytes(int64_t total)
+{
+    return total <= kCachedValueBytes ? total : kCachedPrefixBytes;
+}
 
 // Slices per run of the SELL-64 layout (measured on MI355X, streaming the
 // 885 MB of a 27-point matrix: runs of 64 slices 6% faster than single
