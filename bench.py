@@ -202,10 +202,8 @@ def batched_section(torch, prcg, problems, traffic, reps=3, sequential=True, con
     # writes s) plus the system's share of the matrix, taken per row: the
     # batch's SELL-64 bytes (format basis) or the CSR count 12 nnz + 4 (n + 1)
     # of the byte model
-    words = 8 if (mode == "lockstep" and props["fused"]) else 10
-    row_iters = float(np.sum(iters * sizes))
-    moved = row_iters * (8.0 * words + props["matrix_bytes"] / float(A.n))
-    moved_csr = row_iters * (8.0 * words + (12.0 * A.nnz + 4.0 * (A.n + 1)) / float(A.n))
+    words = traffic.batched_words(mode, bool(props["fused"]))
+    moved, moved_csr = traffic.batched_bytes(float(np.sum(iters * sizes)), words, props["matrix_bytes"], A.n, A.nnz)
     # sequential: one handle and one solve per system (handles created before timing)
     t_seq, seq_iters = float("nan"), 0
     if sequential:

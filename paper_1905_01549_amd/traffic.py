@@ -88,3 +88,26 @@ def iteration_bytes(variant: str, jacobi: bool, n: int, matrix_bytes: int, fused
 def csr_matrix_bytes(n: int, nnz: int) -> int:
     """Bytes of plain CSR (int32 indices, float64 values) read once."""
     return 12 * nnz + 4 * (n + 1)
+
+
+def batched_words(mode: str, fused: bool, jacobi: bool = False) -> int:
+    """Vector words per row and iteration of a batched PR-CG solve: the fused
+    lockstep iteration reads x, r, p, s and writes x, r', p', s' (with Jacobi
+    also r~ and d read and r~' written); the three-launch lockstep iteration
+    and the persistent kernel move the two-kernel byte model's words (the
+    update reads x, r, p, s and writes x, r, p; the product reads p, r and
+    writes s; with Jacobi r~ and d as well)."""
+    if mode == "lockstep" and fused:
+        return 12 if jacobi else 8
+    return 15 if jacobi else 10
+
+
+def batched_bytes(row_iterations: float, words: int, matrix_bytes: int, n: int, nnz: int) -> tuple:
+    """Bytes moved by a batched solve of sum over systems of (iterations x
+    rows) = row_iterations: per row and iteration the vector words plus the
+    system's share of the matrix, taken per row, either as the batch's own
+    storage (matrix_bytes, read once per iteration of every system) or as
+    the CSR count 12 nnz + 4 (n + 1).  Returns (format bytes, CSR bytes)."""
+    fmt = row_iterations * (8.0 * words + matrix_bytes / float(n))
+    csr = row_iterations * (8.0 * words + csr_matrix_bytes(n, nnz) / float(n))
+    return fmt, csr

@@ -57,3 +57,24 @@ def test_traffic_of_an_unprofiled_workload_is_none():
     sys.path.insert(0, ROOT)
     import bench
     assert bench.load_traffic("k_pr_spmv", "no_such_workload") is None
+
+
+@pytest.mark.parametrize("mode, fused, jacobi, words", [
+    ("lockstep", True, False, 8),     # x, r, p, s read; x, r', p', s' written
+    ("lockstep", True, True, 12),     # and r~, d read, r~' written
+    ("lockstep", False, False, 10),   # update 4 + 3, product 2 + 1
+    ("persistent", False, False, 10),
+    ("persistent", True, True, 15),   # fusion applies to the lockstep mode only
+])
+def test_batched_words_follow_the_structure(mode, fused, jacobi, words):
+    assert traffic.batched_words(mode, fused, jacobi) == words
+
+
+def test_batched_bytes_take_the_matrix_per_row():
+    """Two systems of 100 and 300 rows running 10 and 20 iterations: 7,000
+    row-iterations, each with its words and the matrix's bytes per row, in
+    the batch's own storage or as the CSR count."""
+    n, nnz, matrix_bytes = 400, 2000, 16_000
+    fmt, csr = traffic.batched_bytes(100 * 10 + 300 * 20, 8, matrix_bytes, n, nnz)
+    assert fmt == 7000 * (64 + 40)
+    assert csr == 7000 * (64 + (12 * 2000 + 4 * 401) / 400)
